@@ -1,0 +1,179 @@
+/*
+ * p2o.h - C ABI of the MI355X (gfx950) library for the shift-invariant
+ * parameter-to-observable map of "Real-time Bayesian inference at extreme
+ * scale: a digital twin for tsunami early warning".
+ *
+ * The map (section "FFT-based Hessian matvecs", eq. ShiftInvariance) is the
+ * block lower-triangular Toeplitz matrix F with Nt x Nt blocks of size
+ * Nd x Nm; block (i, j) is F_{i-j} for j <= i.  Only the first block column
+ * F_0 .. F_{Nt-1} is stored, and F is applied through a block-circulant
+ * embedding of length L diagonalised by the DFT: d = F m becomes one Nd x Nm
+ * complex block product per frequency.  F* is the Euclidean transpose F^T.
+ * On top of F and F* the library forms the data-space Hessian
+ * K = Gamma_noise + F Gamma_prior F* and the posterior mean
+ * m = Gamma_prior F* K^{-1} d (section "Real-time Bayesian inference and
+ * prediction framework", Phases 2 and 4, zero prior mean).
+ *
+ * Conventions shared by every entry point
+ *   - Blocks:  [Nt][Nd][Nm] row-major float64, blocks[k] = F_k = the paper's
+ *              F_{k+1,1}.
+ *   - Vectors: a parameter vector is [nrhs][Nt][Nm], a data vector
+ *              [nrhs][Nt][Nd]; row-major float64; time step outermost
+ *              within one right-hand side.
+ *   - Pointers to arrays are DEVICE pointers unless stated otherwise.  The
+ *     caller owns every buffer it passes; the library owns the frequency
+ *     blocks, the scales and its workspaces, and frees them in p2o_destroy.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Every call is
+ *     ordered on it and returns without waiting for the device, except the
+ *     setup calls, p2o_reserve and p2o_posterior_solve, which may allocate
+ *     or synchronise the stream.
+ *   - Errors are reported only through the return code; nothing is thrown
+ *     across the ABI.  On any code other than P2O_OK the outputs are
+ *     unspecified and the handle remains usable.  P2O_EHIP carries the HIP
+ *     error code, readable with p2o_last_hip_error (per calling thread).
+ *   - A handle is not thread-safe: serialise calls on one handle.
+ *   - L is the smallest even integer >= 2*Nt whose prime factors are all in
+ *     {2, 3, 5, 7} (L = 2*Nt whenever 2*Nt is such a number, e.g. Nt = 32,
+ *     200, 420); L >= 2*Nt - 1 is what makes the circulant embedding exact.
+ *     The library stores nf = L/2 + 1 frequency blocks.
+ */
+#ifndef P2O_H
+#define P2O_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct p2o_plan_s* p2o_handle;
+
+typedef enum {
+  P2O_OK = 0,
+  P2O_EINVAL = 1,        /* bad argument: null pointer, size < 1, bad enum  */
+  P2O_ENOMEM = 2,        /* device allocation failed or size overflows      */
+  P2O_EHIP = 3,          /* a HIP runtime call failed                        */
+  P2O_ENOTPD = 4,        /* Cholesky met a non-positive pivot                */
+  P2O_ESTATE = 5,        /* call out of order (e.g. apply before setup_end)  */
+  P2O_EUNSUPPORTED = 6   /* valid request this build does not provide        */
+} p2o_status;
+
+typedef enum {
+  P2O_F = 0,     /* y = F x : x parameter vector, y data vector       */
+  P2O_FADJ = 1   /* y = F* x: x data vector,      y parameter vector  */
+} p2o_op;
+
+typedef enum {
+  /* Frequency blocks stored as complex float64, transforms and block
+   * products in float64. */
+  P2O_FP64 = 0,
+  /* Frequency blocks stored as two 16-bit terms per real component,
+   * v ~= s * (hi + lo * 2^-11) in IEEE binary16, with one power-of-two float32
+   * scale s per (frequency, 256-column tile) sub-block; transforms in
+   * float32, block products accumulated in float32, partial sums combined in
+   * float64.  8 bytes per complex block entry. */
+  P2O_MIXED_FP16 = 1,
+  /* As P2O_MIXED_FP16 with bfloat16 terms, v ~= s * (hi + lo). */
+  P2O_MIXED_BF16 = 2,
+  /* bfloat16 hi term only (4 bytes per complex entry); error ~1e-3. */
+  P2O_FAST_BF16 = 3
+} p2o_prec;
+
+/* ---------------------------------------------------------------- setup */
+
+/* One-shot setup from all blocks at once.
+ *   blocks  device [Nt][Nd][Nm] float64 (first block column, see above).
+ *           Not retained: the caller may free it once `stream` has drained.
+ *   Nd, Nm, Nt >= 1;  prec one of p2o_prec.
+ *   out     host pointer receiving the new handle (set to NULL on error).
+ * Allocates the frequency blocks (nf*Nd*Nm complex entries of the chosen
+ * precision) and synchronises `stream` before returning. */
+p2o_status p2o_setup(const double* blocks, int64_t Nd, int64_t Nm, int64_t Nt,
+                     p2o_prec prec, void* stream, p2o_handle* out);
+
+/* Chunked setup, so the time-domain blocks never need to co-reside with the
+ * frequency blocks: begin, then setup_columns for column ranges that cover
+ * [0, Nm) exactly once (any order), then setup_end.
+ *   blocks_chunk  device [Nt][Nd][p1-p0] float64, columns p0..p1-1 of every
+ *                 block; 0 <= p0 < p1 <= Nm.  For the mixed precisions p0
+ *                 must be a multiple of 256 and p1 a multiple of 256 or Nm.
+ * setup_columns synchronises `stream` before returning. */
+p2o_status p2o_setup_begin(int64_t Nd, int64_t Nm, int64_t Nt, p2o_prec prec,
+                           void* stream, p2o_handle* out);
+p2o_status p2o_setup_columns(p2o_handle h, const double* blocks_chunk,
+                             int64_t p0, int64_t p1, void* stream);
+p2o_status p2o_setup_end(p2o_handle h, void* stream);
+
+/* Query the shape and precision of a plan (host out-pointers may be NULL). */
+p2o_status p2o_get_info(p2o_handle h, int64_t* Nd, int64_t* Nm, int64_t* Nt,
+                        int64_t* L, int* prec);
+
+/* Pre-allocate the apply workspace for up to `nrhs` right-hand sides, so
+ * that later p2o_apply calls with nrhs <= this do not allocate. */
+p2o_status p2o_reserve(p2o_handle h, int64_t nrhs, void* stream);
+
+/* ---------------------------------------------------------------- apply */
+
+/* y = F x (op = P2O_F) or y = F* x (op = P2O_FADJ) for nrhs >= 1
+ * right-hand sides, through the frequency blocks (exact up to rounding).
+ *   P2O_F   : x [nrhs][Nt][Nm], y [nrhs][Nt][Nd]
+ *   P2O_FADJ: x [nrhs][Nt][Nd], y [nrhs][Nt][Nm]
+ * Input and output are float64 whatever the plan precision; x and y must
+ * not overlap.  May allocate workspace on first use of a larger nrhs. */
+p2o_status p2o_apply(p2o_handle h, p2o_op op, const double* x, double* y,
+                     int64_t nrhs, void* stream);
+
+/* ------------------------------------------------------ inversion (FP64) */
+
+/* K = Gamma_noise + F Gamma_prior F* (Phase 2), Gamma_prior =
+ * prior_var * I, Gamma_noise = diag(noise_var), formed as the paper does:
+ * one F Gamma_prior F* product per unit vector of data space, in batches.
+ *   noise_var  device [Nt*Nd] float64 (> 0 expected, not checked)
+ *   K          device [(Nt*Nd)^2] float64 row-major, caller-allocated;
+ *              entry (i*Nd + s, j*Nd + r) couples sensor s at step i with
+ *              sensor r at step j.  K is symmetrised, (K + K^T)/2.
+ * Requires a P2O_FP64 plan (else P2O_EUNSUPPORTED). */
+p2o_status p2o_hessian_assemble(p2o_handle h, double prior_var,
+                                const double* noise_var, double* K,
+                                void* stream);
+
+/* Posterior mean m = Gamma_prior F* K^{-1} d (Phase 4, zero prior mean).
+ *   K      device [(Nt*Nd)^2] float64; on return its lower triangle holds
+ *          the Cholesky factor L (K = L L^T) and its strict upper triangle
+ *          is unchanged.
+ *   d      device [nrhs][Nt][Nd];  m_out device [nrhs][Nt][Nm].
+ *   refine_steps  >= 0 rounds of iterative refinement x += K^{-1}(d - K x),
+ *          with the residual formed in float64 from the untouched upper
+ *          triangle and a saved copy of the diagonal.
+ *   failed_pivot  HOST pointer (may be NULL); on P2O_ENOTPD receives the
+ *          0-based index of the first non-positive pivot.
+ * Requires a P2O_FP64 plan.  Synchronises `stream`. */
+p2o_status p2o_posterior_solve(p2o_handle h, double* K, const double* d,
+                               double* m_out, int64_t nrhs, double prior_var,
+                               int refine_steps, int64_t* failed_pivot,
+                               void* stream);
+
+/* ------------------------------------------------------------ housekeeping */
+
+/* Frees the frequency blocks, scales and workspaces; NULL-safe. */
+void p2o_destroy(p2o_handle h);
+
+/* Static description of a status code. */
+const char* p2o_status_string(p2o_status s);
+
+/* The HIP error behind the last P2O_EHIP returned on this thread. */
+p2o_status p2o_last_hip_error(int* code);
+
+/* Kernel timing: when enabled, p2o_apply brackets each frequency-block
+ * product kernel with HIP events on `stream`.  p2o_kernel_time reads back
+ * the summed milliseconds and launch count since the last reset for
+ * op = P2O_F or P2O_FADJ (synchronises on the last event). */
+p2o_status p2o_set_kernel_timing(p2o_handle h, int enable);
+p2o_status p2o_kernel_time(p2o_handle h, p2o_op op, double* total_ms,
+                           int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* P2O_H */

@@ -1,0 +1,493 @@
+// Host runtime behind include/p2o.h: plan lifetime, setup (time-domain
+// blocks -> frequency blocks), and p2o_apply, which chains
+//   forward transform of x  ->  per-frequency block product  ->  inverse
+//   transform with truncation to the first Nt steps
+// on the caller's stream (section "FFT-based Hessian matvecs").
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "p2o_internal.h"
+
+using namespace p2o;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+p2o_status hip_fail(hipError_t e) {
+  g_last_hip = (int)e;
+  (void)hipGetLastError();  // do not leave the error for the next launch check
+  return e == hipErrorOutOfMemory ? P2O_ENOMEM : P2O_EHIP;
+}
+
+#define TRY_HIP(expr)                         \
+  do {                                        \
+    const hipError_t e_ = (expr);             \
+    if (e_ != hipSuccess) return hip_fail(e_); \
+  } while (0)
+
+#define TRY_ST(expr)                     \
+  do {                                   \
+    const p2o_status s_ = (expr);        \
+    if (s_ != P2O_OK) return s_;         \
+  } while (0)
+
+bool valid_prec(int p) { return p >= P2O_FP64 && p <= P2O_FAST_BF16; }
+bool is_mixed(p2o_prec p) { return p != P2O_FP64; }
+int64_t entry_bytes(p2o_prec p) {
+  switch (p) {
+    case P2O_FP64: return 16;
+    case P2O_MIXED_FP16:
+    case P2O_MIXED_BF16: return 8;
+    case P2O_FAST_BF16: return 4;
+  }
+  return 0;
+}
+Fmt16 fmt_of(p2o_prec p) { return p == P2O_MIXED_FP16 ? Fmt16::FP16 : Fmt16::BF16; }
+bool uses_lo(p2o_prec p) { return p != P2O_FAST_BF16; }
+
+bool mul3(int64_t a, int64_t b, int64_t c, int64_t* r) {
+  int64_t t;
+  return !__builtin_mul_overflow(a, b, &t) && !__builtin_mul_overflow(t, c, r);
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+constexpr int kRowsPerWave = 4;        // must match the row kernels
+constexpr int64_t kTargetWaves = 16384;
+
+// Column chunking of the F product: enough wavefronts to fill the chip,
+// chunks of at least 256 columns, chunk length a multiple of 64.
+void choose_chunks(p2o_plan_s* h, int64_t* n_pc, int64_t* pc_len) {
+  const int64_t base = h->nf * ((h->Nd + kRowsPerWave - 1) / kRowsPerWave);
+  int64_t n = std::max<int64_t>(1, (kTargetWaves + base - 1) / base);
+  n = std::min<int64_t>(n, std::max<int64_t>(1, h->Nm / 256));
+  int64_t len = (h->Nm + n - 1) / n;
+  len = (len + 63) / 64 * 64;
+  *pc_len = len;
+  *n_pc = (h->Nm + len - 1) / len;
+}
+
+struct WsLayout {
+  size_t a_off, b_off, total;
+};
+
+// F : a = transformed x [nrhs][nf][Nm], b = partial spectra [nrhs][n_pc][nf][Nd]
+// F*: a = transformed x [nrhs][nf][Nd], b = product      [nrhs][nf][Nm]
+WsLayout ws_layout(const p2o_plan_s* h, p2o_op op, int64_t nrhs) {
+  const size_t vb = is_mixed(h->prec) ? 8 : 16;  // complex vector entry
+  WsLayout w{};
+  if (op == P2O_F) {
+    w.a_off = 0;
+    w.b_off = align_up((size_t)nrhs * h->nf * h->Nm * vb);
+    w.total = w.b_off + align_up((size_t)nrhs * h->n_pc * h->nf * h->Nd * 16);
+  } else {
+    w.a_off = 0;
+    w.b_off = align_up((size_t)nrhs * h->nf * h->Nd * vb);
+    w.total = w.b_off + align_up((size_t)nrhs * h->nf * h->Nm * vb);
+  }
+  return w;
+}
+
+p2o_status ensure_ws(p2o_plan_s* h, int64_t nrhs) {
+  const size_t need = std::max(ws_layout(h, P2O_F, nrhs).total,
+                               ws_layout(h, P2O_FADJ, nrhs).total);
+  if (need <= h->ws_bytes) return P2O_OK;
+  if (h->ws) {
+    TRY_HIP(hipFree(h->ws));
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+  }
+  TRY_HIP(hipMalloc(&h->ws, need));
+  h->ws_bytes = need;
+  return P2O_OK;
+}
+
+void free_plan(p2o_plan_s* h) {
+  if (!h) return;
+  (void)hipFree(h->tw64);
+  (void)hipFree(h->tw32);
+  (void)hipFree(h->perm);
+  (void)hipFree(h->fhat);
+  (void)hipFree(h->scales);
+  (void)hipFree(h->scratch);
+  (void)hipFree(h->ws);
+  for (int op = 0; op < 2; ++op) {
+    for (auto& pr : h->pending[op]) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  }
+  delete h;
+}
+
+p2o_status make_tables(p2o_plan_s* h) {
+  const int L = h->fft.L;
+  std::vector<cpx<double>> w64(L);
+  std::vector<cpx<float>> w32(L);
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  for (int m = 0; m < L; ++m) {
+    const long double a = two_pi * (long double)m / (long double)L;
+    w64[m] = {(double)std::cos(a), (double)-std::sin(a)};
+    w32[m] = {(float)w64[m].x, (float)w64[m].y};
+  }
+  const std::vector<int> perm = make_perm(h->fft);
+  TRY_HIP(hipMalloc(&h->tw64, sizeof(cpx<double>) * L));
+  TRY_HIP(hipMalloc(&h->tw32, sizeof(cpx<float>) * L));
+  TRY_HIP(hipMalloc(&h->perm, sizeof(int) * perm.size()));
+  TRY_HIP(hipMemcpy(h->tw64, w64.data(), sizeof(cpx<double>) * L, hipMemcpyHostToDevice));
+  TRY_HIP(hipMemcpy(h->tw32, w32.data(), sizeof(cpx<float>) * L, hipMemcpyHostToDevice));
+  TRY_HIP(hipMemcpy(h->perm, perm.data(), sizeof(int) * perm.size(), hipMemcpyHostToDevice));
+  return P2O_OK;
+}
+
+p2o_status begin_impl(int64_t Nd, int64_t Nm, int64_t Nt, p2o_prec prec,
+                      p2o_plan_s** out) {
+  FftDesc d{};
+  if (!make_fft_desc(Nt, &d)) return P2O_EUNSUPPORTED;
+  // one column of the transform must fit the 64 KB LDS tile in float64;
+  // the setup transform walks the sensors on the second grid axis
+  if ((int64_t)d.N * 16 > 65536 || Nd > 65535) return P2O_EUNSUPPORTED;
+  const int64_t nf = d.N + 1;
+  int64_t bytes;
+  if (!mul3(nf, Nd, Nm, &bytes) || __builtin_mul_overflow(bytes, entry_bytes(prec), &bytes))
+    return P2O_ENOMEM;
+  p2o_plan_s* h = new (std::nothrow) p2o_plan_s;
+  if (!h) return P2O_ENOMEM;
+  h->Nd = Nd;
+  h->Nm = Nm;
+  h->Nt = Nt;
+  h->fft = d;
+  h->L = d.L;
+  h->N = d.N;
+  h->nf = nf;
+  h->prec = prec;
+  h->ntiles = (Nm + kScaleTile - 1) / kScaleTile;
+  choose_chunks(h, &h->n_pc, &h->pc_len);
+  hipError_t e = hipGetDevice(&h->device);
+  if (e != hipSuccess) {
+    free_plan(h);
+    return hip_fail(e);
+  }
+  p2o_status st = make_tables(h);
+  if (st == P2O_OK) {
+    e = hipMalloc(&h->fhat, (size_t)bytes);
+    if (e != hipSuccess) st = hip_fail(e);
+  }
+  if (st == P2O_OK && is_mixed(prec)) {
+    e = hipMalloc((void**)&h->scales, sizeof(float) * nf * h->ntiles);
+    if (e != hipSuccess) st = hip_fail(e);
+  }
+  if (st != P2O_OK) {
+    free_plan(h);
+    return st;
+  }
+  *out = h;
+  return P2O_OK;
+}
+
+// Transform columns p0..p1-1 of the time-domain blocks (row stride `ld`
+// within one block row) into the stored frequency blocks.
+p2o_status columns_impl(p2o_plan_s* h, const double* src, int64_t ld,
+                        int64_t p0, int64_t p1, hipStream_t s) {
+  const int64_t pc = p1 - p0;
+  FftIo io{};
+  io.in = src;
+  io.ncols = pc;
+  io.in_row = h->Nd * ld;
+  io.in_batch = ld;
+  io.nparts = 1;
+  io.scale = 1.0;
+  if (!is_mixed(h->prec)) {
+    io.out = static_cast<cpx<double>*>(h->fhat) + p0;
+    io.out_row = h->Nd * h->Nm;
+    io.out_batch = h->Nm;
+    TRY_HIP(launch_rfft_fwd_f64(h->fft, h->tw64, h->perm, io, h->Nd, s));
+  } else {
+    const size_t need = (size_t)h->nf * h->Nd * pc * sizeof(cpx<double>);
+    if (need > h->scratch_bytes) {
+      if (h->scratch) {
+        TRY_HIP(hipStreamSynchronize(s));
+        TRY_HIP(hipFree(h->scratch));
+        h->scratch = nullptr;
+        h->scratch_bytes = 0;
+      }
+      TRY_HIP(hipMalloc(&h->scratch, need));
+      h->scratch_bytes = need;
+    }
+    io.out = h->scratch;
+    io.out_row = h->Nd * pc;
+    io.out_batch = pc;
+    TRY_HIP(launch_rfft_fwd_f64(h->fft, h->tw64, h->perm, io, h->Nd, s));
+    TRY_HIP(launch_quantise(static_cast<const cpx<double>*>(h->scratch), h->nf, h->Nd,
+                            h->Nm, p0, pc, static_cast<uint2*>(h->fhat), h->scales,
+                            fmt_of(h->prec), uses_lo(h->prec), s));
+  }
+  TRY_HIP(hipStreamSynchronize(s));
+  h->cols_done += pc;
+  return P2O_OK;
+}
+
+p2o_status end_impl(p2o_plan_s* h) {
+  if (h->cols_done != h->Nm) return P2O_ESTATE;
+  if (h->scratch) {
+    TRY_HIP(hipFree(h->scratch));
+    h->scratch = nullptr;
+    h->scratch_bytes = 0;
+  }
+  h->ready = true;
+  return P2O_OK;
+}
+
+p2o_status timed_begin(p2o_plan_s* h, p2o_op op, hipStream_t s) {
+  if (!h->timing) return P2O_OK;
+  hipEvent_t a, b;
+  TRY_HIP(hipEventCreate(&a));
+  TRY_HIP(hipEventCreate(&b));
+  h->pending[op].push_back({a, b});
+  TRY_HIP(hipEventRecord(a, s));
+  return P2O_OK;
+}
+
+p2o_status timed_end(p2o_plan_s* h, p2o_op op, hipStream_t s) {
+  if (!h->timing) return P2O_OK;
+  TRY_HIP(hipEventRecord(h->pending[op].back().second, s));
+  return P2O_OK;
+}
+
+p2o_status apply_fp64(p2o_plan_s* h, p2o_op op, const double* x, double* y,
+                      int64_t nrhs, hipStream_t s) {
+  const WsLayout w = ws_layout(h, op, nrhs);
+  char* ws = static_cast<char*>(h->ws);
+  auto* a = reinterpret_cast<cpx<double>*>(ws + w.a_off);
+  auto* b = reinterpret_cast<cpx<double>*>(ws + w.b_off);
+  const auto* A = static_cast<const cpx<double>*>(h->fhat);
+  GemvShape g{h->nf, h->Nd, h->Nm, nrhs, (int)h->n_pc, h->pc_len};
+  const int64_t nin = (op == P2O_F) ? h->Nm : h->Nd;
+  const int64_t nout = (op == P2O_F) ? h->Nd : h->Nm;
+
+  FftIo f{};
+  f.in = x;
+  f.out = a;
+  f.ncols = nin;
+  f.in_row = nin;
+  f.in_batch = h->Nt * nin;
+  f.out_row = nin;
+  f.out_batch = h->nf * nin;
+  f.nparts = 1;
+  f.scale = 1.0;
+  TRY_HIP(launch_rfft_fwd_f64(h->fft, h->tw64, h->perm, f, nrhs, s));
+
+  TRY_ST(timed_begin(h, op, s));
+  if (op == P2O_F)
+    TRY_HIP(launch_gemv_rows_f64(A, a, b, g, s));
+  else
+    TRY_HIP(launch_gemv_cols_f64(A, a, b, g, s));
+  TRY_ST(timed_end(h, op, s));
+
+  FftIo v{};
+  v.in = b;
+  v.out = y;
+  v.ncols = nout;
+  v.in_row = nout;
+  v.nparts = (op == P2O_F) ? (int)h->n_pc : 1;
+  v.part_stride = h->nf * nout;
+  v.in_batch = (int64_t)v.nparts * h->nf * nout;
+  v.out_row = nout;
+  v.out_batch = h->Nt * nout;
+  v.scale = 1.0 / (double)h->L;
+  TRY_HIP(launch_rfft_inv_f64(h->fft, h->tw64, h->perm, v, nrhs, s));
+  return P2O_OK;
+}
+
+p2o_status apply_mixed(p2o_plan_s* h, p2o_op op, const double* x, double* y,
+                       int64_t nrhs, hipStream_t s) {
+  const WsLayout w = ws_layout(h, op, nrhs);
+  char* ws = static_cast<char*>(h->ws);
+  auto* a = reinterpret_cast<cpx<float>*>(ws + w.a_off);
+  const auto* A = static_cast<const uint2*>(h->fhat);
+  GemvShape g{h->nf, h->Nd, h->Nm, nrhs, (int)h->n_pc, h->pc_len};
+  const int64_t nin = (op == P2O_F) ? h->Nm : h->Nd;
+  const int64_t nout = (op == P2O_F) ? h->Nd : h->Nm;
+  const Fmt16 fmt = fmt_of(h->prec);
+  const bool lo = uses_lo(h->prec);
+
+  FftIo f{};
+  f.in = x;
+  f.out = a;
+  f.ncols = nin;
+  f.in_row = nin;
+  f.in_batch = h->Nt * nin;
+  f.out_row = nin;
+  f.out_batch = h->nf * nin;
+  f.nparts = 1;
+  f.scale = 1.0;
+  TRY_HIP(launch_rfft_fwd_f32(h->fft, h->tw32, h->perm, f, nrhs, s));
+
+  FftIo v{};
+  v.out = y;
+  v.ncols = nout;
+  v.in_row = nout;
+  v.out_row = nout;
+  v.out_batch = h->Nt * nout;
+  v.scale = 1.0 / (double)h->L;
+  TRY_ST(timed_begin(h, op, s));
+  if (op == P2O_F) {
+    auto* parts = reinterpret_cast<cpx<double>*>(ws + w.b_off);
+    TRY_HIP(launch_gemv_rows_mixed(A, h->scales, a, parts, g, fmt, lo, s));
+    TRY_ST(timed_end(h, op, s));
+    v.in = parts;
+    v.nparts = (int)h->n_pc;
+    v.part_stride = h->nf * nout;
+    v.in_batch = (int64_t)v.nparts * h->nf * nout;
+    TRY_HIP(launch_rfft_inv_f32(h->fft, h->tw32, h->perm, v, true, nrhs, s));
+  } else {
+    auto* prod = reinterpret_cast<cpx<float>*>(ws + w.b_off);
+    TRY_HIP(launch_gemv_cols_mixed(A, h->scales, a, prod, g, fmt, lo, s));
+    TRY_ST(timed_end(h, op, s));
+    v.in = prod;
+    v.nparts = 1;
+    v.part_stride = 0;
+    v.in_batch = h->nf * nout;
+    TRY_HIP(launch_rfft_inv_f32(h->fft, h->tw32, h->perm, v, false, nrhs, s));
+  }
+  return P2O_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+p2o_status p2o_setup_begin(int64_t Nd, int64_t Nm, int64_t Nt, p2o_prec prec,
+                           void* stream, p2o_handle* out) {
+  (void)stream;
+  if (!out) return P2O_EINVAL;
+  *out = nullptr;
+  if (Nd < 1 || Nm < 1 || Nt < 1 || !valid_prec(prec)) return P2O_EINVAL;
+  return begin_impl(Nd, Nm, Nt, prec, out);
+}
+
+p2o_status p2o_setup_columns(p2o_handle h, const double* blocks_chunk,
+                             int64_t p0, int64_t p1, void* stream) {
+  if (!h || !blocks_chunk) return P2O_EINVAL;
+  if (h->ready) return P2O_ESTATE;
+  if (p0 < 0 || p1 <= p0 || p1 > h->Nm) return P2O_EINVAL;
+  if (is_mixed(h->prec) &&
+      (p0 % kScaleTile != 0 || (p1 % kScaleTile != 0 && p1 != h->Nm)))
+    return P2O_EINVAL;
+  return columns_impl(h, blocks_chunk, p1 - p0, p0, p1, (hipStream_t)stream);
+}
+
+p2o_status p2o_setup_end(p2o_handle h, void* stream) {
+  (void)stream;
+  if (!h) return P2O_EINVAL;
+  if (h->ready) return P2O_ESTATE;
+  return end_impl(h);
+}
+
+p2o_status p2o_setup(const double* blocks, int64_t Nd, int64_t Nm, int64_t Nt,
+                     p2o_prec prec, void* stream, p2o_handle* out) {
+  if (!out) return P2O_EINVAL;
+  *out = nullptr;
+  if (!blocks) return P2O_EINVAL;
+  p2o_handle h = nullptr;
+  p2o_status st = p2o_setup_begin(Nd, Nm, Nt, prec, stream, &h);
+  if (st != P2O_OK) return st;
+  // mixed precisions stage float64 spectra per chunk: keep that under ~1 GB
+  int64_t chunk = Nm;
+  if (is_mixed(prec)) {
+    const int64_t per_col = h->nf * Nd * 16;
+    chunk = std::max<int64_t>(1, ((int64_t)1 << 30) / per_col / kScaleTile) * kScaleTile;
+  }
+  for (int64_t p0 = 0; p0 < Nm && st == P2O_OK; p0 += chunk) {
+    const int64_t p1 = std::min(Nm, p0 + chunk);
+    st = columns_impl(h, blocks + p0, Nm, p0, p1, (hipStream_t)stream);
+  }
+  if (st == P2O_OK) st = end_impl(h);
+  if (st != P2O_OK) {
+    free_plan(h);
+    return st;
+  }
+  *out = h;
+  return P2O_OK;
+}
+
+p2o_status p2o_get_info(p2o_handle h, int64_t* Nd, int64_t* Nm, int64_t* Nt,
+                        int64_t* L, int* prec) {
+  if (!h) return P2O_EINVAL;
+  if (Nd) *Nd = h->Nd;
+  if (Nm) *Nm = h->Nm;
+  if (Nt) *Nt = h->Nt;
+  if (L) *L = h->L;
+  if (prec) *prec = (int)h->prec;
+  return P2O_OK;
+}
+
+p2o_status p2o_reserve(p2o_handle h, int64_t nrhs, void* stream) {
+  if (!h || nrhs < 1) return P2O_EINVAL;
+  if (h->ws) TRY_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return ensure_ws(h, nrhs);
+}
+
+p2o_status p2o_apply(p2o_handle h, p2o_op op, const double* x, double* y,
+                     int64_t nrhs, void* stream) {
+  if (!h || !x || !y || nrhs < 1 || nrhs > 65535) return P2O_EINVAL;
+  if (op != P2O_F && op != P2O_FADJ) return P2O_EINVAL;
+  if (!h->ready) return P2O_ESTATE;
+  (void)hipGetLastError();  // launch checks below must see only our errors
+  TRY_ST(ensure_ws(h, nrhs));
+  hipStream_t s = (hipStream_t)stream;
+  if (!is_mixed(h->prec)) return apply_fp64(h, op, x, y, nrhs, s);
+  return apply_mixed(h, op, x, y, nrhs, s);
+}
+
+void p2o_destroy(p2o_handle h) { free_plan(h); }
+
+const char* p2o_status_string(p2o_status s) {
+  switch (s) {
+    case P2O_OK: return "ok";
+    case P2O_EINVAL: return "invalid argument";
+    case P2O_ENOMEM: return "out of device memory or size overflow";
+    case P2O_EHIP: return "HIP runtime error";
+    case P2O_ENOTPD: return "matrix is not positive definite";
+    case P2O_ESTATE: return "call out of order for this handle";
+    case P2O_EUNSUPPORTED: return "unsupported request";
+  }
+  return "unknown status";
+}
+
+p2o_status p2o_last_hip_error(int* code) {
+  if (!code) return P2O_EINVAL;
+  *code = g_last_hip;
+  return P2O_OK;
+}
+
+p2o_status p2o_set_kernel_timing(p2o_handle h, int enable) {
+  if (!h) return P2O_EINVAL;
+  h->timing = enable != 0;
+  return P2O_OK;
+}
+
+p2o_status p2o_kernel_time(p2o_handle h, p2o_op op, double* total_ms,
+                           int64_t* launches) {
+  if (!h || (op != P2O_F && op != P2O_FADJ)) return P2O_EINVAL;
+  for (auto& pr : h->pending[op]) {
+    TRY_HIP(hipEventSynchronize(pr.second));
+    float ms = 0.f;
+    TRY_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+    h->kernel_ms[op] += ms;
+    h->kernel_launches[op] += 1;
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  h->pending[op].clear();
+  if (total_ms) *total_ms = h->kernel_ms[op];
+  if (launches) *launches = h->kernel_launches[op];
+  h->kernel_ms[op] = 0;
+  h->kernel_launches[op] = 0;
+  return P2O_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,354 @@
+// Batched real transforms along the time axis for the block-circulant
+// embedding of the p2o map (section "FFT-based Hessian matvecs", items
+// (ii)-(iii)): the Toeplitz matrix is embedded in a block circulant of
+// length L >= 2*Nt - 1 that the DFT block-diagonalises.
+//
+// Each work-group owns C adjacent columns (C a power of two) of one batch.
+// A column is a length-L real series whose first Nt samples are read and
+// whose remaining samples are the zero padding.  The series is packed as
+// z[n] = x[2n] + i x[2n+1] (n < N = L/2) into LDS laid out [n][C] so that
+// lanes with consecutive column indices touch consecutive LDS words, then
+// transformed in place by a mixed-radix decimation-in-frequency FFT (every
+// butterfly reads and writes the same R slots, so a stage needs no second
+// buffer), leaving Z in digit-reversed order; `perm[k]` is the LDS row
+// holding Z[k].  The even/odd split is undone while storing:
+//   X[k] = (Z[k] + conj Z[N-k]) / 2 - i W_L^k (Z[k] - conj Z[N-k]) / 2.
+// The inverse runs the same steps backwards and writes only the first Nt
+// real samples, which is the truncation back to the Toeplitz block.
+#include <cmath>
+
+#include "p2o_internal.h"
+
+namespace p2o {
+
+int64_t smooth_length(int64_t Nt) {
+  for (int64_t L = 2 * Nt;; L += 2) {
+    int64_t n = L;
+    for (int p : {2, 3, 5, 7})
+      while (n % p == 0) n /= p;
+    if (n == 1) return L;
+  }
+}
+
+bool make_fft_desc(int64_t Nt, FftDesc* d) {
+  if (Nt < 1 || Nt > (1 << 22)) return false;
+  const int64_t L = smooth_length(Nt);
+  d->L = (int)L;
+  d->N = (int)(L / 2);
+  d->Nt = (int)Nt;
+  d->nst = 0;
+  int64_t n = d->N;
+  auto push = [&](int r) {
+    if (d->nst >= kMaxStages) return false;
+    d->radix[d->nst++] = r;
+    n /= r;
+    return true;
+  };
+  while (n % 4 == 0)
+    if (!push(4)) return false;
+  while (n % 2 == 0)
+    if (!push(2)) return false;
+  for (int p : {3, 5, 7})
+    while (n % p == 0)
+      if (!push(p)) return false;
+  return n == 1;
+}
+
+// Z[k] sits at LDS row sum_s u_s * (M_s / r_s), where k = u_1 + r_1 u_2 +
+// r_1 r_2 u_3 + ... and M_s is the sub-transform length entering stage s.
+std::vector<int> make_perm(const FftDesc& d) {
+  std::vector<int> perm(d.N);
+  for (int k = 0; k < d.N; ++k) {
+    int kk = k, pos = 0, M = d.N;
+    for (int s = 0; s < d.nst; ++s) {
+      const int r = d.radix[s];
+      M /= r;
+      pos += (kk % r) * M;
+      kk /= r;
+    }
+    perm[k] = pos;
+  }
+  return perm;
+}
+
+namespace {
+
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) {
+  return {a.x + b.x, a.y + b.y};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) {
+  return {a.x - b.x, a.y - b.y};
+}
+
+// Length-R DFT y[u] = sum_q x[q] w^(q u); w = exp(-+2 pi i / R) is held in
+// wr[1] (wr[m] = w^m, already conjugated for the inverse).
+template <int R, typename T>
+__device__ __forceinline__ void dft(const cpx<T>* x, cpx<T>* y,
+                                    const cpx<T>* wr, bool inv) {
+  if constexpr (R == 2) {
+    y[0] = cadd(x[0], x[1]);
+    y[1] = csub(x[0], x[1]);
+  } else if constexpr (R == 4) {
+    const cpx<T> a = cadd(x[0], x[2]), b = csub(x[0], x[2]);
+    const cpx<T> c = cadd(x[1], x[3]), e = csub(x[1], x[3]);
+    y[0] = cadd(a, c);
+    y[2] = csub(a, c);
+    // forward: y1 = b - i e, y3 = b + i e; inverse swaps the signs of i.
+    const cpx<T> mie = {e.y, -e.x};  // -i e
+    if (!inv) {
+      y[1] = cadd(b, mie);
+      y[3] = csub(b, mie);
+    } else {
+      y[1] = csub(b, mie);
+      y[3] = cadd(b, mie);
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      cpx<T> acc = x[0];
+#pragma unroll
+      for (int q = 1; q < R; ++q) {
+        const cpx<T> w = wr[(q * u) % R];
+        acc.x += x[q].x * w.x - x[q].y * w.y;
+        acc.y += x[q].x * w.y + x[q].y * w.x;
+      }
+      y[u] = acc;
+    }
+  }
+}
+
+// One decimation-in-frequency stage of radix R on every column.  Sub-arrays
+// of length M start at multiples of M; butterfly (g, n') combines the R
+// values at g*M + n' + q*M/R, applies the DFT over q and the twiddle
+// W_M^(n' u) to output u, and writes output u back to slot g*M + n' + u*M/R.
+template <int R, typename T>
+__device__ __forceinline__ void dif_stage(cpx<T>* buf, int N, int M, int L,
+                                          const cpx<T>* __restrict__ tw,
+                                          bool inv, int logC, int tid,
+                                          int nthr) {
+  const int Mr = M / R;
+  const int nbf = N / R;
+  const int twstep = 2 * (N / M);  // W_M = W_L^(2N/M)
+  const int C = 1 << logC;
+  cpx<T> wr[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    wr[m] = tw[(L / R) * m];
+    if (inv) wr[m].y = -wr[m].y;
+  }
+  for (int idx = tid; idx < (nbf << logC); idx += nthr) {
+    const int bf = idx >> logC;
+    const int c = idx & (C - 1);
+    const int g = bf / Mr;
+    const int np = bf - g * Mr;
+    const int base = g * M + np;
+    cpx<T> x[R], y[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) x[q] = buf[((base + q * Mr) << logC) + c];
+    dft<R, T>(x, y, wr, inv);
+    buf[(base << logC) + c] = y[0];
+#pragma unroll
+    for (int u = 1; u < R; ++u) {
+      cpx<T> w = tw[twstep * np * u];  // index < L: np < M/R, u < R
+      if (inv) w.y = -w.y;
+      buf[((base + u * Mr) << logC) + c] = cmul(y[u], w);
+    }
+  }
+}
+
+template <typename T>
+__device__ void dif_all_stages(cpx<T>* buf, const FftDesc& d,
+                               const cpx<T>* __restrict__ tw, bool inv,
+                               int logC, int tid, int nthr) {
+  int M = d.N;
+  for (int s = 0; s < d.nst; ++s) {
+    __syncthreads();
+    const int R = d.radix[s];
+    switch (R) {
+      case 4: dif_stage<4, T>(buf, d.N, M, d.L, tw, inv, logC, tid, nthr); break;
+      case 2: dif_stage<2, T>(buf, d.N, M, d.L, tw, inv, logC, tid, nthr); break;
+      case 3: dif_stage<3, T>(buf, d.N, M, d.L, tw, inv, logC, tid, nthr); break;
+      case 5: dif_stage<5, T>(buf, d.N, M, d.L, tw, inv, logC, tid, nthr); break;
+      default: dif_stage<7, T>(buf, d.N, M, d.L, tw, inv, logC, tid, nthr); break;
+    }
+    M /= R;
+  }
+  __syncthreads();
+}
+
+// Forward: x (float64 rows 0..Nt-1 of each column) -> X[k], k = 0..N.
+template <typename T>
+__global__ void __launch_bounds__(512)
+rfft_fwd_kernel(FftDesc d, const cpx<T>* __restrict__ tw,
+                const int* __restrict__ perm, FftIo io, int logC) {
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int C = 1 << logC;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int64_t c0 = (int64_t)blockIdx.x << logC;
+  const int64_t b = blockIdx.y;
+  const double* __restrict__ in =
+      static_cast<const double*>(io.in) + b * io.in_batch + c0;
+  cpx<T>* __restrict__ out = static_cast<cpx<T>*>(io.out) + b * io.out_batch + c0;
+  const int ncol = (int)min((int64_t)C, io.ncols - c0);
+  const int N = d.N, Nt = d.Nt;
+
+  for (int idx = tid; idx < (N << logC); idx += nthr) {
+    const int n = idx >> logC, c = idx & (C - 1);
+    T re = 0, im = 0;
+    if (c < ncol) {
+      const int t0 = 2 * n;
+      if (t0 < Nt) re = (T)in[(int64_t)t0 * io.in_row + c];
+      if (t0 + 1 < Nt) im = (T)in[(int64_t)(t0 + 1) * io.in_row + c];
+    }
+    buf[idx] = {re, im};
+  }
+  dif_all_stages<T>(buf, d, tw, false, logC, tid, nthr);
+
+  const T half = (T)0.5;
+  for (int idx = tid; idx < ((N + 1) << logC); idx += nthr) {
+    const int k = idx >> logC, c = idx & (C - 1);
+    if (c >= ncol) continue;
+    const int k1 = (k == N) ? 0 : k;
+    const int k2 = (k == 0) ? 0 : N - k;
+    const cpx<T> zk = buf[(perm[k1] << logC) + c];
+    const cpx<T> zn = buf[(perm[k2] << logC) + c];
+    const cpx<T> w = tw[k];
+    // a = Zk + conj Zn, e = Zk - conj Zn, X = a/2 - i w e / 2
+    const T ar = zk.x + zn.x, ai = zk.y - zn.y;
+    const T er = zk.x - zn.x, ei = zk.y + zn.y;
+    const T wer = w.x * er - w.y * ei, wei = w.x * ei + w.y * er;
+    out[(int64_t)k * io.out_row + c] = {half * (ar + wei), half * (ai - wer)};
+  }
+}
+
+template <typename TIN, typename T>
+__device__ __forceinline__ cpx<T> load_bins(const cpx<TIN>* __restrict__ in,
+                                            const FftIo& io, int k, int c) {
+  cpx<TIN> acc = in[(int64_t)k * io.in_row + c];
+  for (int q = 1; q < io.nparts; ++q) {
+    const cpx<TIN> v = in[q * io.part_stride + (int64_t)k * io.in_row + c];
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  return {(T)acc.x, (T)acc.y};
+}
+
+// Z[k] = (Xa + conj Xb) + i conj(W_L^k) (Xa - conj Xb) with Xa = X[k],
+// Xb = X[N-k]; the 1/2 of the split and the 1/N of the inverse DFT are
+// folded into io.scale (= 1/L).
+template <typename T>
+__device__ __forceinline__ cpx<T> unsplit(cpx<T> xa, cpx<T> xb, cpx<T> w) {
+  const T ar = xa.x + xb.x, ai = xa.y - xb.y;
+  const T er = xa.x - xb.x, ei = xa.y + xb.y;
+  // conj(w) * e
+  const T cr = w.x * er + w.y * ei, ci = w.x * ei - w.y * er;
+  return {ar - ci, ai + cr};
+}
+
+// Inverse: X[k], k = 0..N (sum of io.nparts partial spectra) -> first Nt
+// real samples of the length-L inverse DFT, times io.scale, as float64.
+template <typename TIN, typename T>
+__global__ void __launch_bounds__(512)
+rfft_inv_kernel(FftDesc d, const cpx<T>* __restrict__ tw,
+                const int* __restrict__ perm, FftIo io, int logC) {
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int C = 1 << logC;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int64_t c0 = (int64_t)blockIdx.x << logC;
+  const int64_t b = blockIdx.y;
+  const cpx<TIN>* __restrict__ in =
+      static_cast<const cpx<TIN>*>(io.in) + b * io.in_batch + c0;
+  double* __restrict__ out = static_cast<double*>(io.out) + b * io.out_batch + c0;
+  const int ncol = (int)min((int64_t)C, io.ncols - c0);
+  const int N = d.N, Nt = d.Nt;
+  const int half = N / 2;
+
+  for (int idx = tid; idx < ((half + 1) << logC); idx += nthr) {
+    const int k = idx >> logC, c = idx & (C - 1);
+    cpx<T> xa = {0, 0}, xb = {0, 0};
+    if (c < ncol) {
+      xa = load_bins<TIN, T>(in, io, k, c);
+      xb = load_bins<TIN, T>(in, io, N - k, c);
+    }
+    if (k == 0) {  // bins 0 and N of a real series are real
+      xa.y = 0;
+      xb.y = 0;
+    }
+    buf[(k << logC) + c] = unsplit(xa, xb, tw[k]);
+    const int k2 = N - k;
+    if (k2 != k && k2 < N) buf[(k2 << logC) + c] = unsplit(xb, xa, tw[k2]);
+  }
+  dif_all_stages<T>(buf, d, tw, true, logC, tid, nthr);
+
+  const double scale = io.scale;
+  for (int idx = tid; idx < (Nt << logC); idx += nthr) {
+    const int t = idx >> logC, c = idx & (C - 1);
+    if (c >= ncol) continue;
+    const cpx<T> z = buf[(perm[t >> 1] << logC) + c];
+    out[(int64_t)t * io.out_row + c] = (double)((t & 1) ? z.y : z.x) * scale;
+  }
+}
+
+// Columns per work-group: the largest power of two <= 64 whose LDS tile
+// (N complex values per column) fits in 64 KB.
+template <typename T>
+int pick_logC(int N) {
+  int logC = 0;
+  while (logC < 6 && ((size_t)N << (logC + 1)) * sizeof(cpx<T>) <= 65536) ++logC;
+  return logC;
+}
+
+template <typename T, typename K>
+hipError_t launch_common(K kernel, const FftDesc& d, const cpx<T>* tw,
+                         const int* perm, const FftIo& io, int64_t nbatch,
+                         hipStream_t s) {
+  if (nbatch < 1 || io.ncols < 1) return hipSuccess;
+  if (nbatch > 65535) return hipErrorInvalidConfiguration;
+  const int logC = pick_logC<T>(d.N);
+  const size_t lds = ((size_t)d.N << logC) * sizeof(cpx<T>);
+  if (lds > 65536) return hipErrorInvalidConfiguration;
+  const int64_t gx = (io.ncols + (1 << logC) - 1) >> logC;
+  if (gx > 0x7fffffff) return hipErrorInvalidConfiguration;
+  const int threads = 512;
+  hipLaunchKernelGGL(kernel, dim3((unsigned)gx, (unsigned)nbatch), dim3(threads),
+                     lds, s, d, tw, perm, io, logC);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_rfft_fwd_f64(const FftDesc& d, const cpx<double>* tw,
+                               const int* perm, const FftIo& io, int64_t nbatch,
+                               hipStream_t s) {
+  return launch_common<double>(rfft_fwd_kernel<double>, d, tw, perm, io, nbatch, s);
+}
+hipError_t launch_rfft_fwd_f32(const FftDesc& d, const cpx<float>* tw,
+                               const int* perm, const FftIo& io, int64_t nbatch,
+                               hipStream_t s) {
+  return launch_common<float>(rfft_fwd_kernel<float>, d, tw, perm, io, nbatch, s);
+}
+hipError_t launch_rfft_inv_f64(const FftDesc& d, const cpx<double>* tw,
+                               const int* perm, const FftIo& io, int64_t nbatch,
+                               hipStream_t s) {
+  return launch_common<double>(rfft_inv_kernel<double, double>, d, tw, perm, io,
+                               nbatch, s);
+}
+hipError_t launch_rfft_inv_f32(const FftDesc& d, const cpx<float>* tw,
+                               const int* perm, const FftIo& io, bool in_f64,
+                               int64_t nbatch, hipStream_t s) {
+  if (in_f64)
+    return launch_common<float>(rfft_inv_kernel<double, float>, d, tw, perm, io,
+                                nbatch, s);
+  return launch_common<float>(rfft_inv_kernel<float, float>, d, tw, perm, io,
+                              nbatch, s);
+}
+
+}  // namespace p2o

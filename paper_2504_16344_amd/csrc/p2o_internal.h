@@ -1,0 +1,140 @@
+// Internal declarations of the p2o library: plan object, transform
+// descriptors, and the kernel launchers each .hip file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "p2o.h"
+
+namespace p2o {
+
+// ---------------------------------------------------------------- complex
+template <typename T>
+struct cpx {
+  T x, y;
+};
+
+// ------------------------------------------------------------- transforms
+// Real transforms of length L along the time axis, computed as a complex
+// DFT of length N = L/2 on z[n] = x[2n] + i x[2n+1] (in-place mixed-radix
+// decimation in frequency, radices 4, 2, 3, 5, 7), with the even/odd split
+// undone on the way out.  Output bins are 0..N (nf = N + 1).
+constexpr int kMaxStages = 24;
+
+struct FftDesc {
+  int N;    // complex length L/2
+  int L;    // real embedding length
+  int Nt;   // real samples read (forward) / written (inverse)
+  int nst;  // number of radix stages
+  int radix[kMaxStages];
+};
+
+// Column-batched layout of one transform call.  Columns are contiguous in
+// memory; the transformed axis (time or frequency) has its own stride; a
+// second grid axis walks independent batches (right-hand sides, or sensors
+// during setup).
+struct FftIo {
+  const void* in;
+  void* out;
+  int64_t ncols;       // columns per batch
+  int64_t in_row;      // element stride between consecutive rows of `in`
+  int64_t in_batch;    // element stride between batches of `in`
+  int64_t out_row;
+  int64_t out_batch;
+  int nparts;          // inverse only: number of partial spectra summed
+  int64_t part_stride; // inverse only: element stride between partials
+  double scale;        // inverse only: output multiplier (1/L folded in)
+};
+
+int64_t smooth_length(int64_t Nt);  // L: smallest even 7-smooth >= 2*Nt
+bool make_fft_desc(int64_t Nt, FftDesc* d);
+std::vector<int> make_perm(const FftDesc& d);
+
+// Launchers (return hipError_t of the launch).
+// Forward: real float64 rows [Nt] -> complex bins [N+1] of type TC.
+hipError_t launch_rfft_fwd_f64(const FftDesc& d, const cpx<double>* tw,
+                               const int* perm, const FftIo& io, int64_t nbatch,
+                               hipStream_t s);
+hipError_t launch_rfft_fwd_f32(const FftDesc& d, const cpx<float>* tw,
+                               const int* perm, const FftIo& io, int64_t nbatch,
+                               hipStream_t s);
+// Inverse: complex bins (sum of nparts partials) -> first Nt real samples,
+// times io.scale, written as float64.  in_f64 selects the input type.
+hipError_t launch_rfft_inv_f64(const FftDesc& d, const cpx<double>* tw,
+                               const int* perm, const FftIo& io, int64_t nbatch,
+                               hipStream_t s);
+hipError_t launch_rfft_inv_f32(const FftDesc& d, const cpx<float>* tw,
+                               const int* perm, const FftIo& io, bool in_f64,
+                               int64_t nbatch, hipStream_t s);
+
+// ----------------------------------------------------------- block products
+// Frequency-block layout: [nf][Nd][Nm], column p contiguous.
+struct GemvShape {
+  int64_t nf, Nd, Nm;
+  int64_t nrhs;
+  int n_pc;       // F only: number of column chunks (partial sums)
+  int64_t pc_len; // F only: columns per chunk (multiple of 64)
+};
+
+// F, float64: P[b][pc][k][s] = sum_{p in chunk pc} A[k][s][p] X[b][k][p]
+hipError_t launch_gemv_rows_f64(const cpx<double>* A, const cpx<double>* X,
+                                cpx<double>* P, const GemvShape& g,
+                                hipStream_t s);
+// F*, float64: Y[b][k][p] = sum_s conj(A[k][s][p]) D[b][k][s]
+hipError_t launch_gemv_cols_f64(const cpx<double>* A, const cpx<double>* D,
+                                cpx<double>* Y, const GemvShape& g,
+                                hipStream_t s);
+
+// Mixed storage: one uint2 per complex entry holding (hi.re, hi.im) in .x
+// and (lo.re, lo.im) in .y as 16-bit words (low half = real part).
+constexpr int kScaleTile = 256;  // columns per scale sub-block
+enum class Fmt16 { FP16 = 0, BF16 = 1 };
+
+hipError_t launch_gemv_rows_mixed(const uint2* A, const float* scales,
+                                  const cpx<float>* X, cpx<double>* P,
+                                  const GemvShape& g, Fmt16 fmt, bool use_lo,
+                                  hipStream_t s);
+hipError_t launch_gemv_cols_mixed(const uint2* A, const float* scales,
+                                  const cpx<float>* D, cpx<float>* Y,
+                                  const GemvShape& g, Fmt16 fmt, bool use_lo,
+                                  hipStream_t s);
+// Quantise a float64 frequency chunk [nf][Nd][pc] into the packed layout at
+// column offset p0 of [nf][Nd][Nm], with one scale per (k, 256-col tile).
+hipError_t launch_quantise(const cpx<double>* chunk, int64_t nf, int64_t Nd,
+                           int64_t Nm, int64_t p0, int64_t pc, uint2* A,
+                           float* scales, Fmt16 fmt, bool use_lo,
+                           hipStream_t s);
+
+}  // namespace p2o
+
+// ------------------------------------------------------------------ plan
+struct p2o_plan_s {
+  int64_t Nd = 0, Nm = 0, Nt = 0, L = 0, N = 0, nf = 0;
+  p2o_prec prec = P2O_FP64;
+  int device = 0;
+  p2o::FftDesc fft{};
+  p2o::cpx<double>* tw64 = nullptr;  // [L] exp(-2 pi i m / L)
+  p2o::cpx<float>* tw32 = nullptr;
+  int* perm = nullptr;               // [N] digit-reversal positions
+  void* fhat = nullptr;              // frequency blocks
+  float* scales = nullptr;           // [nf][ntiles] (mixed only)
+  int64_t ntiles = 0;
+  int64_t n_pc = 1;                  // F product: column chunks
+  int64_t pc_len = 0;                // F product: columns per chunk
+  int64_t cols_done = 0;             // setup progress
+  bool ready = false;
+  void* scratch = nullptr;           // setup chunk staging (mixed)
+  size_t scratch_bytes = 0;
+  void* ws = nullptr;                // apply workspace
+  size_t ws_bytes = 0;
+  bool timing = false;
+  hipEvent_t ev_begin[2] = {nullptr, nullptr};
+  hipEvent_t ev_end[2] = {nullptr, nullptr};
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[2];
+  double kernel_ms[2] = {0, 0};
+  int64_t kernel_launches[2] = {0, 0};
+};
