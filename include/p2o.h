@@ -25,8 +25,8 @@
  *     blocks, the scales and its workspaces, and frees them in p2o_destroy.
  *   - `stream` is a hipStream_t (NULL = the null stream).  Every call is
  *     ordered on it and returns without waiting for the device, except the
- *     setup calls, p2o_reserve and p2o_posterior_solve, which may allocate
- *     or synchronise the stream.
+ *     setup calls, p2o_reserve, p2o_autotune, p2o_hessian_assemble and
+ *     p2o_posterior_solve, which may allocate or synchronise the stream.
  *   - Errors are reported only through the return code; nothing is thrown
  *     across the ABI.  On any code other than P2O_OK the outputs are
  *     unspecified and the handle remains usable.  P2O_EHIP carries the HIP
@@ -123,6 +123,36 @@ p2o_status p2o_reserve(p2o_handle h, int64_t nrhs, void* stream);
 p2o_status p2o_apply(p2o_handle h, p2o_op op, const double* x, double* y,
                      int64_t nrhs, void* stream);
 
+/* --------------------------------------------------------------- tuning */
+
+/* The frequency-block product kernel of each op has a small table of
+ * candidate configurations (rows per wavefront for F, column groups per
+ * wavefront for F*, load vector width).  Candidate 0 that is valid for the
+ * plan's shape is the default; a candidate whose vector width does not
+ * divide Nm is not valid.
+ *
+ * p2o_autotune times every valid candidate for `op` on one right-hand
+ * side (`reps` timed launches each, after one warm-up) on the plan's own
+ * frequency blocks, and keeps the fastest for later p2o_apply calls.
+ *   times_ms  host array (may be NULL when max_times = 0); entry c receives
+ *             candidate c's mean time in ms, or -1 if it is not valid.
+ *   chosen    host pointer (may be NULL) receiving the chosen index.
+ * If the environment variable P2O_TUNE_CACHE names a file, the choice is
+ * stored there (a flat JSON object keyed by architecture, precision, op and
+ * shape) and p2o_setup / p2o_setup_end apply stored choices to new plans.
+ * Synchronises `stream`; allocates the single-RHS workspace if needed. */
+p2o_status p2o_autotune(p2o_handle h, p2o_op op, int reps, double* times_ms,
+                        int64_t max_times, int64_t* chosen, void* stream);
+
+/* Current candidate index for `op` and the table size (host pointers, may
+ * be NULL). */
+p2o_status p2o_get_config(p2o_handle h, p2o_op op, int64_t* cfg,
+                          int64_t* n_candidates);
+
+/* Force candidate `cfg` for `op`: P2O_EINVAL if out of range,
+ * P2O_EUNSUPPORTED if not valid for this plan's shape. */
+p2o_status p2o_set_config(p2o_handle h, p2o_op op, int64_t cfg);
+
 /* ------------------------------------------------------ inversion (FP64) */
 
 /* K = Gamma_noise + F Gamma_prior F* (Phase 2), Gamma_prior =
@@ -132,7 +162,8 @@ p2o_status p2o_apply(p2o_handle h, p2o_op op, const double* x, double* y,
  *   K          device [(Nt*Nd)^2] float64 row-major, caller-allocated;
  *              entry (i*Nd + s, j*Nd + r) couples sensor s at step i with
  *              sensor r at step j.  K is symmetrised, (K + K^T)/2.
- * Requires a P2O_FP64 plan (else P2O_EUNSUPPORTED). */
+ * Requires a P2O_FP64 plan (else P2O_EUNSUPPORTED).  Allocates a temporary
+ * workspace of up to ~8 GB and synchronises `stream`. */
 p2o_status p2o_hessian_assemble(p2o_handle h, double prior_var,
                                 const double* noise_var, double* K,
                                 void* stream);

@@ -47,6 +47,9 @@ _SIGNATURES = {
     "p2o_status_string": (_c.c_char_p, [_int]),
     "p2o_last_hip_error": (_int, [_c.POINTER(_int)]),
     "p2o_set_kernel_timing": (_int, [_vp, _int]),
+    "p2o_autotune": (_int, [_vp, _int, _int, _c.POINTER(_dbl), _i64, _c.POINTER(_i64), _vp]),
+    "p2o_get_config": (_int, [_vp, _int, _c.POINTER(_i64), _c.POINTER(_i64)]),
+    "p2o_set_config": (_int, [_vp, _int, _i64]),
     "p2o_kernel_time": (_int, [_vp, _int, _c.POINTER(_dbl), _c.POINTER(_i64)]),
 }
 EXPORTED_SYMBOLS = tuple(_SIGNATURES)
@@ -243,6 +246,26 @@ class Plan:
             raise err
         _check("p2o_posterior_solve", st)
         return out
+
+    def autotune(self, op: int, reps: int = 3, stream=None):
+        """Time every candidate product kernel for `op`; keep the fastest.
+        Returns (chosen index, per-candidate ms list, -1 = not valid)."""
+        n = self.config(op)[1]
+        times = (_dbl * n)()
+        chosen = _i64(-1)
+        _check("p2o_autotune", self._lib.p2o_autotune(self._handle(), op, reps, times, n,
+                                                      _c.byref(chosen), _stream_handle(stream)))
+        return chosen.value, list(times)
+
+    def config(self, op: int):
+        """(current candidate index, number of candidates) for `op`."""
+        cfg, n = _i64(0), _i64(0)
+        _check("p2o_get_config", self._lib.p2o_get_config(self._handle(), op, _c.byref(cfg),
+                                                          _c.byref(n)))
+        return cfg.value, n.value
+
+    def set_config(self, op: int, cfg: int) -> None:
+        _check("p2o_set_config", self._lib.p2o_set_config(self._handle(), op, cfg))
 
     def set_kernel_timing(self, enable: bool) -> None:
         _check("p2o_set_kernel_timing", self._lib.p2o_set_kernel_timing(self._handle(), int(enable)))

@@ -5,8 +5,14 @@
 // on the caller's stream (section "FFT-based Hessian matvecs").
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <new>
+#include <sstream>
+#include <string>
 
 #include "p2o_internal.h"
 
@@ -15,6 +21,8 @@ using namespace p2o;
 namespace {
 
 thread_local int g_last_hip = 0;
+
+void load_tuned(p2o_plan_s* h);
 
 p2o_status hip_fail(hipError_t e) {
   g_last_hip = (int)e;
@@ -237,8 +245,97 @@ p2o_status end_impl(p2o_plan_s* h) {
     h->scratch = nullptr;
     h->scratch_bytes = 0;
   }
+  load_tuned(h);
   h->ready = true;
   return P2O_OK;
+}
+
+bool cfg_valid(const p2o_plan_s* h, p2o_op op, int cfg) {
+  if (cfg < 0 || cfg >= gemv_candidates(is_mixed(h->prec), op)) return false;
+  const int v = gemv_vec_width(is_mixed(h->prec), uses_lo(h->prec), op, cfg);
+  return h->Nm % v == 0;
+}
+
+// Candidate 0 of every table loads one entry per lane and is valid for
+// any shape.
+int default_cfg(const p2o_plan_s* h, p2o_op op) {
+  (void)h;
+  (void)op;
+  return 0;
+}
+
+// The frequency-block product of `op` with candidate `cfg`; `a` is the
+// transformed input, `b` the product (F: partial spectra).
+hipError_t launch_product(const p2o_plan_s* h, p2o_op op, void* a, void* b,
+                          int64_t nrhs, int cfg, hipStream_t s) {
+  GemvShape g{h->nf, h->Nd, h->Nm, nrhs, (int)h->n_pc, h->pc_len};
+  if (!is_mixed(h->prec)) {
+    const auto* A = static_cast<const cpx<double>*>(h->fhat);
+    if (op == P2O_F)
+      return launch_gemv_rows_f64(A, static_cast<const cpx<double>*>(a),
+                                  static_cast<cpx<double>*>(b), g, cfg, s);
+    return launch_gemv_cols_f64(A, static_cast<const cpx<double>*>(a),
+                                static_cast<cpx<double>*>(b), g, cfg, s);
+  }
+  const Fmt16 fmt = fmt_of(h->prec);
+  const bool lo = uses_lo(h->prec);
+  if (op == P2O_F)
+    return launch_gemv_rows_mixed(h->fhat, h->scales, static_cast<const cpx<float>*>(a),
+                                  static_cast<cpx<double>*>(b), g, fmt, lo, cfg, s);
+  return launch_gemv_cols_mixed(h->fhat, h->scales, static_cast<const cpx<float>*>(a),
+                                static_cast<cpx<float>*>(b), g, fmt, lo, cfg, s);
+}
+
+// ------------------------------------------------------------ tuning cache
+// A flat JSON object {"key": index, ...}, one entry per line, in the file
+// named by P2O_TUNE_CACHE.  Key: device architecture, precision, op and
+// the plan shape.
+std::string tune_key(const p2o_plan_s* h, p2o_op op) {
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) arch = prop.gcnArchName;
+  std::ostringstream k;
+  k << arch << "|prec" << (int)h->prec << "|op" << (int)op << "|" << h->Nd << "x" << h->Nm
+    << "x" << h->Nt;
+  return k.str();
+}
+
+std::map<std::string, int> read_cache(const char* path) {
+  std::map<std::string, int> m;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    const size_t q0 = line.find('"');
+    const size_t q1 = q0 == std::string::npos ? q0 : line.find('"', q0 + 1);
+    const size_t c = q1 == std::string::npos ? q1 : line.find(':', q1);
+    if (c == std::string::npos) continue;
+    m[line.substr(q0 + 1, q1 - q0 - 1)] = std::atoi(line.c_str() + c + 1);
+  }
+  return m;
+}
+
+void write_cache(const char* path, const std::map<std::string, int>& m) {
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream f(tmp);
+    f << "{\n";
+    size_t i = 0;
+    for (const auto& kv : m)
+      f << "  \"" << kv.first << "\": " << kv.second << (++i < m.size() ? ",\n" : "\n");
+    f << "}\n";
+  }
+  std::rename(tmp.c_str(), path);
+}
+
+void load_tuned(p2o_plan_s* h) {
+  const char* path = std::getenv("P2O_TUNE_CACHE");
+  for (int op = 0; op < 2; ++op) {
+    h->cfg[op] = default_cfg(h, (p2o_op)op);
+    if (!path) continue;
+    const auto m = read_cache(path);
+    const auto it = m.find(tune_key(h, (p2o_op)op));
+    if (it != m.end() && cfg_valid(h, (p2o_op)op, it->second)) h->cfg[op] = it->second;
+  }
 }
 
 p2o_status timed_begin(p2o_plan_s* h, p2o_op op, hipStream_t s) {
@@ -258,13 +355,11 @@ p2o_status timed_end(p2o_plan_s* h, p2o_op op, hipStream_t s) {
 }
 
 p2o_status apply_fp64(p2o_plan_s* h, p2o_op op, const double* x, double* y,
-                      int64_t nrhs, hipStream_t s) {
+                      int64_t nrhs, hipStream_t s, double out_scale = 1.0) {
   const WsLayout w = ws_layout(h, op, nrhs);
   char* ws = static_cast<char*>(h->ws);
   auto* a = reinterpret_cast<cpx<double>*>(ws + w.a_off);
   auto* b = reinterpret_cast<cpx<double>*>(ws + w.b_off);
-  const auto* A = static_cast<const cpx<double>*>(h->fhat);
-  GemvShape g{h->nf, h->Nd, h->Nm, nrhs, (int)h->n_pc, h->pc_len};
   const int64_t nin = (op == P2O_F) ? h->Nm : h->Nd;
   const int64_t nout = (op == P2O_F) ? h->Nd : h->Nm;
 
@@ -281,10 +376,7 @@ p2o_status apply_fp64(p2o_plan_s* h, p2o_op op, const double* x, double* y,
   TRY_HIP(launch_rfft_fwd_f64(h->fft, h->tw64, h->perm, f, nrhs, s));
 
   TRY_ST(timed_begin(h, op, s));
-  if (op == P2O_F)
-    TRY_HIP(launch_gemv_rows_f64(A, a, b, g, s));
-  else
-    TRY_HIP(launch_gemv_cols_f64(A, a, b, g, s));
+  TRY_HIP(launch_product(h, op, a, b, nrhs, h->cfg[op], s));
   TRY_ST(timed_end(h, op, s));
 
   FftIo v{};
@@ -297,7 +389,7 @@ p2o_status apply_fp64(p2o_plan_s* h, p2o_op op, const double* x, double* y,
   v.in_batch = (int64_t)v.nparts * h->nf * nout;
   v.out_row = nout;
   v.out_batch = h->Nt * nout;
-  v.scale = 1.0 / (double)h->L;
+  v.scale = out_scale / (double)h->L;
   TRY_HIP(launch_rfft_inv_f64(h->fft, h->tw64, h->perm, v, nrhs, s));
   return P2O_OK;
 }
@@ -307,12 +399,8 @@ p2o_status apply_mixed(p2o_plan_s* h, p2o_op op, const double* x, double* y,
   const WsLayout w = ws_layout(h, op, nrhs);
   char* ws = static_cast<char*>(h->ws);
   auto* a = reinterpret_cast<cpx<float>*>(ws + w.a_off);
-  const auto* A = static_cast<const uint2*>(h->fhat);
-  GemvShape g{h->nf, h->Nd, h->Nm, nrhs, (int)h->n_pc, h->pc_len};
   const int64_t nin = (op == P2O_F) ? h->Nm : h->Nd;
   const int64_t nout = (op == P2O_F) ? h->Nd : h->Nm;
-  const Fmt16 fmt = fmt_of(h->prec);
-  const bool lo = uses_lo(h->prec);
 
   FftIo f{};
   f.in = x;
@@ -336,7 +424,7 @@ p2o_status apply_mixed(p2o_plan_s* h, p2o_op op, const double* x, double* y,
   TRY_ST(timed_begin(h, op, s));
   if (op == P2O_F) {
     auto* parts = reinterpret_cast<cpx<double>*>(ws + w.b_off);
-    TRY_HIP(launch_gemv_rows_mixed(A, h->scales, a, parts, g, fmt, lo, s));
+    TRY_HIP(launch_product(h, op, a, parts, nrhs, h->cfg[op], s));
     TRY_ST(timed_end(h, op, s));
     v.in = parts;
     v.nparts = (int)h->n_pc;
@@ -345,7 +433,7 @@ p2o_status apply_mixed(p2o_plan_s* h, p2o_op op, const double* x, double* y,
     TRY_HIP(launch_rfft_inv_f32(h->fft, h->tw32, h->perm, v, true, nrhs, s));
   } else {
     auto* prod = reinterpret_cast<cpx<float>*>(ws + w.b_off);
-    TRY_HIP(launch_gemv_cols_mixed(A, h->scales, a, prod, g, fmt, lo, s));
+    TRY_HIP(launch_product(h, op, a, prod, nrhs, h->cfg[op], s));
     TRY_ST(timed_end(h, op, s));
     v.in = prod;
     v.nparts = 1;
@@ -487,6 +575,211 @@ p2o_status p2o_kernel_time(p2o_handle h, p2o_op op, double* total_ms,
   if (launches) *launches = h->kernel_launches[op];
   h->kernel_ms[op] = 0;
   h->kernel_launches[op] = 0;
+  return P2O_OK;
+}
+
+p2o_status p2o_get_config(p2o_handle h, p2o_op op, int64_t* cfg, int64_t* n_candidates) {
+  if (!h || (op != P2O_F && op != P2O_FADJ)) return P2O_EINVAL;
+  if (cfg) *cfg = h->cfg[op];
+  if (n_candidates) *n_candidates = gemv_candidates(is_mixed(h->prec), op);
+  return P2O_OK;
+}
+
+p2o_status p2o_set_config(p2o_handle h, p2o_op op, int64_t cfg) {
+  if (!h || (op != P2O_F && op != P2O_FADJ)) return P2O_EINVAL;
+  if (cfg < 0 || cfg >= gemv_candidates(is_mixed(h->prec), op)) return P2O_EINVAL;
+  if (!cfg_valid(h, op, (int)cfg)) return P2O_EUNSUPPORTED;
+  h->cfg[op] = (int)cfg;
+  return P2O_OK;
+}
+
+p2o_status p2o_autotune(p2o_handle h, p2o_op op, int reps, double* times_ms,
+                        int64_t max_times, int64_t* chosen, void* stream) {
+  if (!h || (op != P2O_F && op != P2O_FADJ) || reps < 1 || max_times < 0 ||
+      (max_times > 0 && !times_ms))
+    return P2O_EINVAL;
+  if (!h->ready) return P2O_ESTATE;
+  (void)hipGetLastError();
+  hipStream_t s = (hipStream_t)stream;
+  TRY_ST(ensure_ws(h, 1));
+  const WsLayout w = ws_layout(h, op, 1);
+  char* ws = static_cast<char*>(h->ws);
+  TRY_HIP(hipMemsetAsync(ws + w.a_off, 0, w.b_off - w.a_off, s));
+  const int n = gemv_candidates(is_mixed(h->prec), op);
+  hipEvent_t e0, e1;
+  TRY_HIP(hipEventCreate(&e0));
+  TRY_HIP(hipEventCreate(&e1));
+  int best = -1;
+  float best_ms = 0.f;
+  hipError_t err = hipSuccess;
+  for (int c = 0; c < n && err == hipSuccess; ++c) {
+    float ms = -1.f;
+    if (cfg_valid(h, op, c)) {
+      err = launch_product(h, op, ws + w.a_off, ws + w.b_off, 1, c, s);  // warm-up
+      if (err == hipSuccess) err = hipEventRecord(e0, s);
+      for (int r = 0; r < reps && err == hipSuccess; ++r)
+        err = launch_product(h, op, ws + w.a_off, ws + w.b_off, 1, c, s);
+      if (err == hipSuccess) err = hipEventRecord(e1, s);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      ms /= reps;
+      if (err == hipSuccess && (best < 0 || ms < best_ms)) {
+        best = c;
+        best_ms = ms;
+      }
+    }
+    if (c < max_times) times_ms[c] = ms;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return hip_fail(err);
+  h->cfg[op] = best;
+  if (chosen) *chosen = best;
+  if (const char* path = std::getenv("P2O_TUNE_CACHE")) {
+    auto m = read_cache(path);
+    m[tune_key(h, op)] = best;
+    write_cache(path, m);
+  }
+  return P2O_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------- Phase 2/4
+namespace {
+
+// Device buffers of one inversion call, freed on every exit path.
+struct DevBufs {
+  std::vector<void*> ptrs;
+  ~DevBufs() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  hipError_t alloc(void** out, size_t bytes) {
+    const hipError_t e = hipMalloc(out, std::max<size_t>(bytes, 256));
+    if (e == hipSuccess) ptrs.push_back(*out);
+    return e;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+p2o_status p2o_hessian_assemble(p2o_handle h, double prior_var,
+                                const double* noise_var, double* K,
+                                void* stream) {
+  if (!h || !noise_var || !K) return P2O_EINVAL;
+  if (!h->ready) return P2O_ESTATE;
+  if (h->prec != P2O_FP64) return P2O_EUNSUPPORTED;
+  (void)hipGetLastError();
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = h->Nt * h->Nd;
+  // per unit vector: adjoint spectrum (reused for the refiltered parameter
+  // spectrum), time-domain parameter vector, partial data spectra
+  const size_t per = (size_t)h->nf * h->Nm * 16 + (size_t)h->Nt * h->Nm * 8 +
+                     (size_t)h->n_pc * h->nf * h->Nd * 16;
+  const size_t budget = (size_t)8 << 30;
+  const int64_t B = std::max<int64_t>(1, std::min<int64_t>({n, 65535, (int64_t)(budget / per)}));
+  DevBufs bufs;
+  void *xh, *m, *parts;
+  TRY_HIP(bufs.alloc(&xh, (size_t)B * h->nf * h->Nm * 16));
+  TRY_HIP(bufs.alloc(&m, (size_t)B * h->Nt * h->Nm * 8));
+  TRY_HIP(bufs.alloc(&parts, (size_t)B * h->n_pc * h->nf * h->Nd * 16));
+  for (int64_t j0 = 0; j0 < n; j0 += B) {
+    const int64_t nb = std::min(B, n - j0);
+    // F* e_j for the unit vectors j0 .. j0+nb-1: spectra, then time domain
+    // (truncated to Nt steps) times prior_var
+    TRY_HIP(launch_unit_adjoint_spectra(static_cast<const cpx<double>*>(h->fhat), h->tw64,
+                                        static_cast<cpx<double>*>(xh), h->nf, h->Nd, h->Nm,
+                                        h->L, j0, nb, s));
+    FftIo inv{};
+    inv.in = xh;
+    inv.out = m;
+    inv.ncols = h->Nm;
+    inv.in_row = h->Nm;
+    inv.in_batch = h->nf * h->Nm;
+    inv.out_row = h->Nm;
+    inv.out_batch = h->Nt * h->Nm;
+    inv.nparts = 1;
+    inv.scale = prior_var / (double)h->L;
+    TRY_HIP(launch_rfft_inv_f64(h->fft, h->tw64, h->perm, inv, nb, s));
+    // F applied to those parameter vectors; row j of the result is K e_j
+    FftIo fwd{};
+    fwd.in = m;
+    fwd.out = xh;
+    fwd.ncols = h->Nm;
+    fwd.in_row = h->Nm;
+    fwd.in_batch = h->Nt * h->Nm;
+    fwd.out_row = h->Nm;
+    fwd.out_batch = h->nf * h->Nm;
+    fwd.nparts = 1;
+    fwd.scale = 1.0;
+    TRY_HIP(launch_rfft_fwd_f64(h->fft, h->tw64, h->perm, fwd, nb, s));
+    TRY_HIP(launch_product(h, P2O_F, xh, parts, nb, h->cfg[P2O_F], s));
+    FftIo out{};
+    out.in = parts;
+    out.out = K + j0 * n;
+    out.ncols = h->Nd;
+    out.in_row = h->Nd;
+    out.nparts = (int)h->n_pc;
+    out.part_stride = h->nf * h->Nd;
+    out.in_batch = h->n_pc * h->nf * h->Nd;
+    out.out_row = h->Nd;
+    out.out_batch = n;
+    out.scale = 1.0 / (double)h->L;
+    TRY_HIP(launch_rfft_inv_f64(h->fft, h->tw64, h->perm, out, nb, s));
+  }
+  TRY_HIP(launch_add_diagonal(K, noise_var, n, s));
+  TRY_HIP(launch_symmetrize(K, n, s));
+  TRY_HIP(hipStreamSynchronize(s));
+  return P2O_OK;
+}
+
+p2o_status p2o_posterior_solve(p2o_handle h, double* K, const double* d,
+                               double* m_out, int64_t nrhs, double prior_var,
+                               int refine_steps, int64_t* failed_pivot,
+                               void* stream) {
+  if (!h || !K || !d || !m_out || nrhs < 1 || nrhs > 65535 || refine_steps < 0)
+    return P2O_EINVAL;
+  if (!h->ready) return P2O_ESTATE;
+  if (h->prec != P2O_FP64) return P2O_EUNSUPPORTED;
+  (void)hipGetLastError();
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = h->Nt * h->Nd;
+  const int64_t nchunks = (n + 1023) / 1024;
+  DevBufs bufs;
+  void *diag, *info, *x, *r, *rows, *psolve, *psymv;
+  TRY_HIP(bufs.alloc(&diag, n * 8));
+  TRY_HIP(bufs.alloc(&info, 8));
+  TRY_HIP(bufs.alloc(&x, (size_t)nrhs * n * 8));
+  TRY_HIP(bufs.alloc(&r, (size_t)nrhs * n * 8));
+  TRY_HIP(bufs.alloc(&rows, (size_t)nrhs * n * 8));
+  TRY_HIP(bufs.alloc(&psolve, cholesky_solve_scratch(n, nrhs)));
+  TRY_HIP(bufs.alloc(&psymv, (size_t)nchunks * nrhs * n * 8));
+  const int64_t minus_one = -1;
+  TRY_HIP(hipMemcpyAsync(info, &minus_one, 8, hipMemcpyHostToDevice, s));
+  TRY_HIP(launch_copy_diagonal(K, static_cast<double*>(diag), n, s));
+  TRY_HIP(launch_cholesky(K, n, static_cast<int64_t*>(info), s));
+  int64_t piv = -1;
+  TRY_HIP(hipMemcpyAsync(&piv, info, 8, hipMemcpyDeviceToHost, s));
+  TRY_HIP(hipStreamSynchronize(s));
+  if (piv >= 0) {
+    if (failed_pivot) *failed_pivot = piv;
+    return P2O_ENOTPD;
+  }
+  double* X = static_cast<double*>(x);
+  double* Rr = static_cast<double*>(r);
+  TRY_HIP(hipMemcpyAsync(X, d, (size_t)nrhs * n * 8, hipMemcpyDeviceToDevice, s));
+  TRY_HIP(launch_cholesky_solve(K, X, static_cast<double*>(psolve), n, nrhs, s));
+  for (int it = 0; it < refine_steps; ++it) {
+    TRY_HIP(launch_residual(K, static_cast<const double*>(diag), d, X, Rr,
+                            static_cast<double*>(rows), static_cast<double*>(psymv), n, nrhs, s));
+    TRY_HIP(launch_cholesky_solve(K, Rr, static_cast<double*>(psolve), n, nrhs, s));
+    TRY_HIP(launch_axpy(X, Rr, 1.0, nrhs * n, s));
+  }
+  TRY_ST(ensure_ws(h, nrhs));
+  TRY_ST(apply_fp64(h, P2O_FADJ, X, m_out, nrhs, s, prior_var));
+  TRY_HIP(hipStreamSynchronize(s));
   return P2O_OK;
 }
 

@@ -8,19 +8,27 @@
 //
 // One copy of Fhat, layout [k][s][p] with p contiguous, serves both.
 // F   ("rows"): a wavefront owns R consecutive rows s of one frequency k and
-//     one column chunk; lane l walks columns p = p0 + l + 64 j, so each row
-//     load of the wavefront is one contiguous 1 KB (float64) segment, and
-//     Xhat_k[p] is loaded once and reused for the R rows.  Lane partial sums
-//     are reduced across the wavefront at the end and written per chunk;
-//     the chunks are summed in fixed order by the inverse transform, so the
-//     result does not depend on scheduling.
-// F*  ("cols"): a wavefront owns 64*J consecutive columns of one k and walks
-//     all rows s; Dhat_k[s] is wave-uniform (scalar loads), each lane keeps
-//     its own columns' sums, so no cross-lane reduction is needed.
+//     one column chunk; lane l walks columns p = p0 + V*l + 64*V*j, so each
+//     row load of the wavefront is one contiguous segment, and Xhat_k[p] is
+//     loaded once and reused for the R rows.  Lane partial sums are reduced
+//     across the wavefront at the end and written per chunk; the chunks are
+//     summed in fixed order by the inverse transform, so the result does not
+//     depend on scheduling.
+// F*  ("cols"): a wavefront owns 64*J*V consecutive columns of one k and
+//     walks all rows s; Dhat_k[s] is wave-uniform, each lane keeps its own
+//     columns' sums, so no cross-lane reduction is needed.
+// The blocks are read with non-temporal loads: they are touched once per
+// apply, and keeping them out of the caches leaves L2 to the reused vector.
+// R, J and the vector width V are the tuning knobs (see the candidate
+// tables at the end of this file).
 #include "p2o_internal.h"
 
 namespace p2o {
 namespace {
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef unsigned u2v __attribute__((ext_vector_type(2)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -31,6 +39,11 @@ __device__ __forceinline__ T wave_sum(T v) {
 
 __device__ __forceinline__ int wave_id_in_block() {
   return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+__device__ __forceinline__ cpx<double> ld_block(const cpx<double>* p) {
+  const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
+  return {v.x, v.y};
 }
 
 // ----------------------------------------------------------------- float64
@@ -76,7 +89,7 @@ gemv_rows_f64_kernel(const cpx<double>* __restrict__ A,
     for (int bb = 0; bb < B; ++bb) x[bb] = Xb[bb][p];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const cpx<double> a = Ar[r][p];
+      const cpx<double> a = ld_block(Ar[r] + p);
 #pragma unroll
       for (int bb = 0; bb < B; ++bb) {
         ar[r][bb] += a.x * x[bb].x - a.y * x[bb].y;
@@ -139,7 +152,7 @@ gemv_cols_f64_kernel(const cpx<double>* __restrict__ A,
     const cpx<double>* As = Ak + s * g.Nm;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-      const cpx<double> a = As[pj[j]];
+      const cpx<double> a = ld_block(As + pj[j]);
 #pragma unroll
       for (int bb = 0; bb < B; ++bb) {  // conj(a) * d
         yr[j][bb] += a.x * dv[bb].x + a.y * dv[bb].y;
@@ -160,9 +173,9 @@ gemv_cols_f64_kernel(const cpx<double>* __restrict__ A,
 }
 
 // ------------------------------------------------------------------- mixed
-// Entry e of the packed layout: e.x = hi (re low half, im high half),
-// e.y = lo (same).  Value = s * (hi + lo * kLoScale) with s the
-// (k, 256-column tile) scale.
+// Packed entry: word 0 = hi (real part in the low 16 bits, imaginary in the
+// high 16 bits), word 1 = lo (same), absent for the hi-only tier.  Value =
+// s * (hi + lo * kLoScale) with s the (k, 256-column tile) scale.
 template <Fmt16 FMT>
 struct Dec;
 template <>
@@ -192,28 +205,43 @@ struct Dec<Fmt16::BF16> {
   }
 };
 
-template <Fmt16 FMT, bool LO>
-struct Entry {
-  using type = typename std::conditional<LO, uint2, uint32_t>::type;
-  __device__ static __forceinline__ cpx<float> value(uint2 e) {
-    cpx<float> v = {Dec<FMT>::lo16(e.x), Dec<FMT>::hi16(e.x)};
-    v.x = fmaf(Dec<FMT>::lo16(e.y), Dec<FMT>::kLoScale, v.x);
-    v.y = fmaf(Dec<FMT>::hi16(e.y), Dec<FMT>::kLoScale, v.y);
-    return v;
-  }
-  __device__ static __forceinline__ cpx<float> value(uint32_t e) {
-    return {Dec<FMT>::lo16(e), Dec<FMT>::hi16(e)};
+// V consecutive entries loaded with one instruction (4, 8 or 16 bytes).
+template <bool LO, int V>
+struct Pack {
+  static constexpr int kWords = (LO ? 2 : 1) * V;
+  using T = typename std::conditional<kWords == 1, uint32_t,
+            typename std::conditional<kWords == 2, u2v, u4v>::type>::type;
+  __device__ static __forceinline__ void load(const void* base, int64_t entry,
+                                              uint32_t (&w)[kWords]) {
+    const T v = __builtin_nontemporal_load(
+        reinterpret_cast<const T*>(static_cast<const uint32_t*>(base) + entry * (LO ? 2 : 1)));
+    if constexpr (kWords == 1) {
+      w[0] = v;
+    } else {
+#pragma unroll
+      for (int i = 0; i < kWords; ++i) w[i] = v[i];
+    }
   }
 };
 
-template <int R, Fmt16 FMT, bool LO>
+template <Fmt16 FMT, bool LO>
+__device__ __forceinline__ cpx<float> decode(const uint32_t* w) {
+  cpx<float> v = {Dec<FMT>::lo16(w[0]), Dec<FMT>::hi16(w[0])};
+  if constexpr (LO) {
+    v.x = fmaf(Dec<FMT>::lo16(w[1]), Dec<FMT>::kLoScale, v.x);
+    v.y = fmaf(Dec<FMT>::hi16(w[1]), Dec<FMT>::kLoScale, v.y);
+  }
+  return v;
+}
+
+template <int R, int V, Fmt16 FMT, bool LO>
 __global__ void __launch_bounds__(256)
-gemv_rows_mixed_kernel(const void* __restrict__ Araw,
+gemv_rows_mixed_kernel(const void* __restrict__ A,
                        const float* __restrict__ scales,
                        const cpx<float>* __restrict__ X,
                        cpx<double>* __restrict__ P, GemvShape g, int64_t b) {
-  using E = typename Entry<FMT, LO>::type;
-  const E* __restrict__ A = static_cast<const E*>(Araw);
+  using PK = Pack<LO, V>;
+  constexpr int WPE = LO ? 2 : 1;  // words per entry
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave_id_in_block();
   const int64_t nsg = (g.Nd + R - 1) / R;
@@ -228,26 +256,37 @@ gemv_rows_mixed_kernel(const void* __restrict__ Araw,
   const int64_t ntiles = (g.Nm + kScaleTile - 1) / kScaleTile;
   const float* __restrict__ sk = scales + k * ntiles;
 
-  const E* Ar[R];
+  int64_t Ar[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) Ar[r] = A + (k * g.Nd + min(s0 + r, g.Nd - 1)) * g.Nm;
+  for (int r = 0; r < R; ++r) Ar[r] = (k * g.Nd + min(s0 + r, g.Nd - 1)) * g.Nm;
   const cpx<float>* Xk = X + (b * g.nf + k) * g.Nm;
 
   float ar[R], ai[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) ar[r] = ai[r] = 0.0f;
 
+  // V consecutive columns per lane; Nm and the chunk bounds are multiples
+  // of V whenever V > 1 is selected, so no partial vector occurs.
 #pragma unroll 2
-  for (int64_t p = p0 + lane; p < p1; p += 64) {
-    cpx<float> x = Xk[p];
+  for (int64_t p = p0 + (int64_t)V * lane; p < p1; p += 64 * V) {
     const float sc = sk[p / kScaleTile];
-    x.x *= sc;
-    x.y *= sc;
+    cpx<float> x[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      x[v] = Xk[p + v];
+      x[v].x *= sc;
+      x[v].y *= sc;
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const cpx<float> a = Entry<FMT, LO>::value(Ar[r][p]);
-      ar[r] = fmaf(a.x, x.x, fmaf(-a.y, x.y, ar[r]));
-      ai[r] = fmaf(a.x, x.y, fmaf(a.y, x.x, ai[r]));
+      uint32_t w[PK::kWords];
+      PK::load(A, Ar[r] + p, w);
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const cpx<float> a = decode<FMT, LO>(w + WPE * v);
+        ar[r] = fmaf(a.x, x[v].x, fmaf(-a.y, x[v].y, ar[r]));
+        ai[r] = fmaf(a.x, x[v].y, fmaf(a.y, x[v].x, ai[r]));
+      }
     }
   }
   double dr[R], di[R];
@@ -265,48 +304,58 @@ gemv_rows_mixed_kernel(const void* __restrict__ Araw,
   }
 }
 
-template <int J, Fmt16 FMT, bool LO>
+template <int J, int V, Fmt16 FMT, bool LO>
 __global__ void __launch_bounds__(256)
-gemv_cols_mixed_kernel(const void* __restrict__ Araw,
+gemv_cols_mixed_kernel(const void* __restrict__ A,
                        const float* __restrict__ scales,
                        const cpx<float>* __restrict__ D,
                        cpx<float>* __restrict__ Y, GemvShape g, int64_t b) {
-  using E = typename Entry<FMT, LO>::type;
-  const E* __restrict__ A = static_cast<const E*>(Araw);
+  using PK = Pack<LO, V>;
+  constexpr int WPE = LO ? 2 : 1;
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave_id_in_block();
-  const int64_t npg = (g.Nm + 64 * J - 1) / (64 * J);
+  constexpr int kCols = 64 * J * V;  // columns per wavefront
+  const int64_t npg = (g.Nm + kCols - 1) / kCols;
   const int64_t pg = wave % npg;
   const int64_t k = wave / npg;
   if (k >= g.nf) return;
   int64_t pj[J];
 #pragma unroll
-  for (int j = 0; j < J; ++j) pj[j] = min(pg * 64 * J + j * 64 + lane, g.Nm - 1);
-  const E* Ak = A + k * g.Nd * g.Nm;
+  for (int j = 0; j < J; ++j)
+    pj[j] = min(pg * kCols + (int64_t)j * 64 * V + (int64_t)V * lane, g.Nm - V);
+  const int64_t Ak = k * g.Nd * g.Nm;
   const cpx<float>* Dk = D + (b * g.nf + k) * g.Nd;
 
-  float yr[J], yi[J];
+  float yr[J][V], yi[J][V];
 #pragma unroll
-  for (int j = 0; j < J; ++j) yr[j] = yi[j] = 0.0f;
+  for (int j = 0; j < J; ++j)
+#pragma unroll
+    for (int v = 0; v < V; ++v) yr[j][v] = yi[j][v] = 0.0f;
 
 #pragma unroll 4
   for (int64_t s = 0; s < g.Nd; ++s) {
     const cpx<float> dv = Dk[s];
-    const E* As = Ak + s * g.Nm;
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-      const cpx<float> a = Entry<FMT, LO>::value(As[pj[j]]);
-      yr[j] = fmaf(a.x, dv.x, fmaf(a.y, dv.y, yr[j]));
-      yi[j] = fmaf(a.x, dv.y, fmaf(-a.y, dv.x, yi[j]));
+      uint32_t w[PK::kWords];
+      PK::load(A, Ak + s * g.Nm + pj[j], w);
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const cpx<float> a = decode<FMT, LO>(w + WPE * v);
+        yr[j][v] = fmaf(a.x, dv.x, fmaf(a.y, dv.y, yr[j][v]));
+        yi[j][v] = fmaf(a.x, dv.y, fmaf(-a.y, dv.x, yi[j][v]));
+      }
     }
   }
   const int64_t ntiles = (g.Nm + kScaleTile - 1) / kScaleTile;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    const int64_t p = pg * 64 * J + j * 64 + lane;
-    if (p >= g.Nm) break;
-    const float sc = scales[k * ntiles + p / kScaleTile];
-    Y[(b * g.nf + k) * g.Nm + p] = {yr[j] * sc, yi[j] * sc};
+    const int64_t pbase = pg * kCols + (int64_t)j * 64 * V + (int64_t)V * lane;
+    if (pbase >= g.Nm) break;
+    const float sc = scales[k * ntiles + pbase / kScaleTile];
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+      Y[(b * g.nf + k) * g.Nm + pbase + v] = {yr[j][v] * sc, yi[j][v] * sc};
   }
 }
 
@@ -314,111 +363,155 @@ inline unsigned blocks_for_waves(int64_t waves) {
   return (unsigned)((waves + 3) / 4);  // 4 wavefronts per 256-thread block
 }
 
-constexpr int kRowsF64 = 4;
-constexpr int kColsF64 = 2;
-constexpr int kRowsMixed = 4;
-constexpr int kColsMixed = 2;
-
-template <int B>
+// ------------------------------------------------------------ dispatching
+template <int R, int B>
 hipError_t rows_f64_pass(const cpx<double>* A, const cpx<double>* X,
                          cpx<double>* P, const GemvShape& g, int64_t b0, int nb,
                          hipStream_t s) {
-  const int64_t waves = g.nf * ((g.Nd + kRowsF64 - 1) / kRowsF64) * g.n_pc;
-  hipLaunchKernelGGL((gemv_rows_f64_kernel<kRowsF64, B>), dim3(blocks_for_waves(waves)),
+  const int64_t waves = g.nf * ((g.Nd + R - 1) / R) * g.n_pc;
+  hipLaunchKernelGGL((gemv_rows_f64_kernel<R, B>), dim3(blocks_for_waves(waves)),
                      dim3(256), 0, s, A, X, P, g, b0, nb);
   return hipGetLastError();
 }
 
-template <int B>
+template <int J, int B>
 hipError_t cols_f64_pass(const cpx<double>* A, const cpx<double>* D,
                          cpx<double>* Y, const GemvShape& g, int64_t b0, int nb,
                          hipStream_t s) {
-  const int64_t waves = g.nf * ((g.Nm + 64 * kColsF64 - 1) / (64 * kColsF64));
-  hipLaunchKernelGGL((gemv_cols_f64_kernel<kColsF64, B>), dim3(blocks_for_waves(waves)),
+  const int64_t waves = g.nf * ((g.Nm + 64 * J - 1) / (64 * J));
+  hipLaunchKernelGGL((gemv_cols_f64_kernel<J, B>), dim3(blocks_for_waves(waves)),
                      dim3(256), 0, s, A, D, Y, g, b0, nb);
   return hipGetLastError();
 }
 
-}  // namespace
-
-hipError_t launch_gemv_rows_f64(const cpx<double>* A, const cpx<double>* X,
-                                cpx<double>* P, const GemvShape& g,
-                                hipStream_t s) {
+template <int T>
+hipError_t rows_f64_all(const cpx<double>* A, const cpx<double>* X,
+                        cpx<double>* P, const GemvShape& g, hipStream_t s) {
   for (int64_t b0 = 0; b0 < g.nrhs;) {
     const int64_t left = g.nrhs - b0;
     hipError_t e;
     int step;
-    if (left >= 4) { e = rows_f64_pass<4>(A, X, P, g, b0, 4, s); step = 4; }
-    else if (left >= 2) { e = rows_f64_pass<2>(A, X, P, g, b0, 2, s); step = 2; }
-    else { e = rows_f64_pass<1>(A, X, P, g, b0, 1, s); step = 1; }
+    if (left >= 4) { e = rows_f64_pass<T, 4>(A, X, P, g, b0, 4, s); step = 4; }
+    else if (left >= 2) { e = rows_f64_pass<T, 2>(A, X, P, g, b0, 2, s); step = 2; }
+    else { e = rows_f64_pass<T, 1>(A, X, P, g, b0, 1, s); step = 1; }
     if (e != hipSuccess) return e;
     b0 += step;
   }
   return hipSuccess;
+}
+
+template <int T>
+hipError_t cols_f64_all(const cpx<double>* A, const cpx<double>* D,
+                        cpx<double>* Y, const GemvShape& g, hipStream_t s) {
+  for (int64_t b0 = 0; b0 < g.nrhs;) {
+    const int64_t left = g.nrhs - b0;
+    hipError_t e;
+    int step;
+    if (left >= 4) { e = cols_f64_pass<T, 4>(A, D, Y, g, b0, 4, s); step = 4; }
+    else if (left >= 2) { e = cols_f64_pass<T, 2>(A, D, Y, g, b0, 2, s); step = 2; }
+    else { e = cols_f64_pass<T, 1>(A, D, Y, g, b0, 1, s); step = 1; }
+    if (e != hipSuccess) return e;
+    b0 += step;
+  }
+  return hipSuccess;
+}
+
+template <int R, int V, Fmt16 FMT, bool LO>
+hipError_t rows_mixed_all(const void* A, const float* sc, const cpx<float>* X,
+                          cpx<double>* P, const GemvShape& g, hipStream_t s) {
+  const int64_t waves = g.nf * ((g.Nd + R - 1) / R) * g.n_pc;
+  for (int64_t b = 0; b < g.nrhs; ++b) {
+    hipLaunchKernelGGL((gemv_rows_mixed_kernel<R, V, FMT, LO>), dim3(blocks_for_waves(waves)),
+                       dim3(256), 0, s, A, sc, X, P, g, b);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <int J, int V, Fmt16 FMT, bool LO>
+hipError_t cols_mixed_all(const void* A, const float* sc, const cpx<float>* D,
+                          cpx<float>* Y, const GemvShape& g, hipStream_t s) {
+  const int64_t waves = g.nf * ((g.Nm + 64 * J * V - 1) / (64 * J * V));
+  for (int64_t b = 0; b < g.nrhs; ++b) {
+    hipLaunchKernelGGL((gemv_cols_mixed_kernel<J, V, FMT, LO>), dim3(blocks_for_waves(waves)),
+                       dim3(256), 0, s, A, sc, D, Y, g, b);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Candidate tables.  Each row is one configuration the autotuner may pick;
+// index 0 of every table is the default used before any tuning.
+struct F64Rows { int R; hipError_t (*fn)(const cpx<double>*, const cpx<double>*, cpx<double>*, const GemvShape&, hipStream_t); };
+struct F64Cols { int J; hipError_t (*fn)(const cpx<double>*, const cpx<double>*, cpx<double>*, const GemvShape&, hipStream_t); };
+const F64Rows kF64Rows[] = {{4, rows_f64_all<4>}, {2, rows_f64_all<2>}, {8, rows_f64_all<8>}};
+const F64Cols kF64Cols[] = {{2, cols_f64_all<2>}, {1, cols_f64_all<1>}, {4, cols_f64_all<4>}};
+
+using RowsMixedFn = hipError_t (*)(const void*, const float*, const cpx<float>*, cpx<double>*,
+                                   const GemvShape&, hipStream_t);
+using ColsMixedFn = hipError_t (*)(const void*, const float*, const cpx<float>*, cpx<float>*,
+                                   const GemvShape&, hipStream_t);
+struct MixedRows { int R, V; RowsMixedFn fn[3]; };  // FP16 hi+lo, BF16 hi+lo, BF16 hi
+struct MixedCols { int J, V; ColsMixedFn fn[3]; };
+
+#define ROWS_SET(R, V) {R, V, {rows_mixed_all<R, V, Fmt16::FP16, true>, \
+    rows_mixed_all<R, V, Fmt16::BF16, true>, rows_mixed_all<R, V, Fmt16::BF16, false>}}
+#define COLS_SET(J, V) {J, V, {cols_mixed_all<J, V, Fmt16::FP16, true>, \
+    cols_mixed_all<J, V, Fmt16::BF16, true>, cols_mixed_all<J, V, Fmt16::BF16, false>}}
+// Candidate 0 of every table has vector width 1, so it is valid for any Nm.
+const MixedRows kMixedRows[] = {ROWS_SET(4, 1), ROWS_SET(2, 1), ROWS_SET(8, 1),
+                                ROWS_SET(4, 2), ROWS_SET(2, 2), ROWS_SET(8, 2)};
+const MixedCols kMixedCols[] = {COLS_SET(2, 1), COLS_SET(1, 1), COLS_SET(4, 1),
+                                COLS_SET(2, 2), COLS_SET(1, 2), COLS_SET(4, 2)};
+
+int mixed_slot(Fmt16 fmt, bool lo) {
+  if (!lo) return 2;
+  return fmt == Fmt16::FP16 ? 0 : 1;
+}
+
+}  // namespace
+
+int gemv_candidates(bool mixed, p2o_op op) {
+  if (!mixed) return op == P2O_F ? 3 : 3;
+  return op == P2O_F ? 6 : 6;
+}
+
+int gemv_vec_width(bool mixed, bool lo, p2o_op op, int cfg) {
+  (void)lo;
+  if (!mixed) return 1;
+  return (op == P2O_F) ? kMixedRows[cfg].V : kMixedCols[cfg].V;
+}
+
+int gemv_rows_per_wave(bool mixed, int cfg) {
+  return mixed ? kMixedRows[cfg].R : kF64Rows[cfg].R;
+}
+
+hipError_t launch_gemv_rows_f64(const cpx<double>* A, const cpx<double>* X,
+                                cpx<double>* P, const GemvShape& g, int cfg,
+                                hipStream_t s) {
+  return kF64Rows[cfg].fn(A, X, P, g, s);
 }
 
 hipError_t launch_gemv_cols_f64(const cpx<double>* A, const cpx<double>* D,
-                                cpx<double>* Y, const GemvShape& g,
+                                cpx<double>* Y, const GemvShape& g, int cfg,
                                 hipStream_t s) {
-  for (int64_t b0 = 0; b0 < g.nrhs;) {
-    const int64_t left = g.nrhs - b0;
-    hipError_t e;
-    int step;
-    if (left >= 4) { e = cols_f64_pass<4>(A, D, Y, g, b0, 4, s); step = 4; }
-    else if (left >= 2) { e = cols_f64_pass<2>(A, D, Y, g, b0, 2, s); step = 2; }
-    else { e = cols_f64_pass<1>(A, D, Y, g, b0, 1, s); step = 1; }
-    if (e != hipSuccess) return e;
-    b0 += step;
-  }
-  return hipSuccess;
+  return kF64Cols[cfg].fn(A, D, Y, g, s);
 }
 
-hipError_t launch_gemv_rows_mixed(const uint2* A, const float* scales,
+hipError_t launch_gemv_rows_mixed(const void* A, const float* scales,
                                   const cpx<float>* X, cpx<double>* P,
                                   const GemvShape& g, Fmt16 fmt, bool use_lo,
-                                  hipStream_t s) {
-  const int64_t waves = g.nf * ((g.Nd + kRowsMixed - 1) / kRowsMixed) * g.n_pc;
-  for (int64_t b = 0; b < g.nrhs; ++b) {
-    if (fmt == Fmt16::FP16 && use_lo)
-      hipLaunchKernelGGL((gemv_rows_mixed_kernel<kRowsMixed, Fmt16::FP16, true>),
-                         dim3(blocks_for_waves(waves)), dim3(256), 0, s, A, scales, X, P, g, b);
-    else if (fmt == Fmt16::BF16 && use_lo)
-      hipLaunchKernelGGL((gemv_rows_mixed_kernel<kRowsMixed, Fmt16::BF16, true>),
-                         dim3(blocks_for_waves(waves)), dim3(256), 0, s, A, scales, X, P, g, b);
-    else if (fmt == Fmt16::BF16)
-      hipLaunchKernelGGL((gemv_rows_mixed_kernel<kRowsMixed, Fmt16::BF16, false>),
-                         dim3(blocks_for_waves(waves)), dim3(256), 0, s, A, scales, X, P, g, b);
-    else
-      hipLaunchKernelGGL((gemv_rows_mixed_kernel<kRowsMixed, Fmt16::FP16, false>),
-                         dim3(blocks_for_waves(waves)), dim3(256), 0, s, A, scales, X, P, g, b);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+                                  int cfg, hipStream_t s) {
+  return kMixedRows[cfg].fn[mixed_slot(fmt, use_lo)](A, scales, X, P, g, s);
 }
 
-hipError_t launch_gemv_cols_mixed(const uint2* A, const float* scales,
+hipError_t launch_gemv_cols_mixed(const void* A, const float* scales,
                                   const cpx<float>* D, cpx<float>* Y,
                                   const GemvShape& g, Fmt16 fmt, bool use_lo,
-                                  hipStream_t s) {
-  const int64_t waves = g.nf * ((g.Nm + 64 * kColsMixed - 1) / (64 * kColsMixed));
-  for (int64_t b = 0; b < g.nrhs; ++b) {
-    if (fmt == Fmt16::FP16 && use_lo)
-      hipLaunchKernelGGL((gemv_cols_mixed_kernel<kColsMixed, Fmt16::FP16, true>),
-                         dim3(blocks_for_waves(waves)), dim3(256), 0, s, A, scales, D, Y, g, b);
-    else if (fmt == Fmt16::BF16 && use_lo)
-      hipLaunchKernelGGL((gemv_cols_mixed_kernel<kColsMixed, Fmt16::BF16, true>),
-                         dim3(blocks_for_waves(waves)), dim3(256), 0, s, A, scales, D, Y, g, b);
-    else if (fmt == Fmt16::BF16)
-      hipLaunchKernelGGL((gemv_cols_mixed_kernel<kColsMixed, Fmt16::BF16, false>),
-                         dim3(blocks_for_waves(waves)), dim3(256), 0, s, A, scales, D, Y, g, b);
-    else
-      hipLaunchKernelGGL((gemv_cols_mixed_kernel<kColsMixed, Fmt16::FP16, false>),
-                         dim3(blocks_for_waves(waves)), dim3(256), 0, s, A, scales, D, Y, g, b);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+                                  int cfg, hipStream_t s) {
+  return kMixedCols[cfg].fn[mixed_slot(fmt, use_lo)](A, scales, D, Y, g, s);
 }
 
 }  // namespace p2o

@@ -1,24 +1,432 @@
-// Data-space Hessian assembly and posterior mean (placeholders until the
-// float64 Cholesky lands).
+// Data-space Hessian and posterior mean (section "Real-time Bayesian
+// inference and prediction framework", Phases 2 and 4), float64 only:
+//
+//   K = Gamma_noise + F Gamma_prior F*,   formed one unit vector of data
+//       space at a time (Phase 2), in batches of right-hand sides;
+//   K = L L^T (blocked Cholesky), x = K^{-1} d with iterative refinement,
+//   m = Gamma_prior F* x.
+//
+// F* of the unit vector e_(i,s) needs no block product: the transform of
+// that data vector is dhat_k[s'] = [s' = s] W_L^(i k), W_L = exp(-2 pi i / L),
+// so the product Fhat_k^H dhat_k is the conjugated row s of Fhat_k times a
+// phase:  xhat_k[p] = conj(Fhat_k[s, p]) * W_L^(i k).
+// That spectrum still has to go through the inverse transform and the
+// truncation to Nt steps (the time-domain F* output) before F is applied,
+// exactly as in a full F* apply.
+#include <cmath>
+
 #include "p2o_internal.h"
 
-extern "C" {
+namespace p2o {
+namespace {
 
-p2o_status p2o_hessian_assemble(p2o_handle h, double prior_var,
-                                const double* noise_var, double* K,
-                                void* stream) {
-  (void)prior_var; (void)stream;
-  if (!h || !noise_var || !K) return P2O_EINVAL;
-  return P2O_EUNSUPPORTED;
+constexpr int kNb = 64;  // Cholesky / triangular-solve block size
+
+// ------------------------------------------------------------ assembly
+// xhat[b][k][p] = conj(Fhat[k][s_b][p]) * W_L^((i_b k) mod L), column
+// j = j0 + b = i_b * Nd + s_b of data space.
+__global__ void __launch_bounds__(256)
+unit_adjoint_spectra(const cpx<double>* __restrict__ A,
+                     const cpx<double>* __restrict__ tw, cpx<double>* __restrict__ xh,
+                     int64_t nf, int64_t Nd, int64_t Nm, int64_t L, int64_t j0,
+                     int64_t nb) {
+  const int64_t total = nb * nf * Nm;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = idx % Nm;
+    const int64_t bk = idx / Nm;
+    const int64_t k = bk % nf;
+    const int64_t b = bk / nf;
+    const int64_t j = j0 + b;
+    const int64_t i = j / Nd, s = j % Nd;
+    const cpx<double> a = A[(k * Nd + s) * Nm + p];
+    const cpx<double> w = tw[(i * k) % L];
+    // conj(a) * w
+    xh[idx] = {a.x * w.x + a.y * w.y, a.x * w.y - a.y * w.x};
+  }
 }
 
-p2o_status p2o_posterior_solve(p2o_handle h, double* K, const double* d,
-                               double* m_out, int64_t nrhs, double prior_var,
-                               int refine_steps, int64_t* failed_pivot,
-                               void* stream) {
-  (void)prior_var; (void)refine_steps; (void)failed_pivot; (void)stream;
-  if (!h || !K || !d || !m_out || nrhs < 1) return P2O_EINVAL;
-  return P2O_EUNSUPPORTED;
+__global__ void add_diagonal(double* __restrict__ K, const double* __restrict__ v,
+                             int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) K[i * n + i] += v[i];
 }
 
-}  // extern "C"
+// K <- (K + K^T) / 2 on 32 x 32 tile pairs (I, J), I <= J.
+__global__ void __launch_bounds__(256)
+symmetrize(double* __restrict__ K, int64_t n, int64_t T) {
+  __shared__ double a[32][33], b[32][33];
+  // linear index over the upper triangle of tiles: t -> (I, J), I <= J
+  const int64_t t = blockIdx.x;
+  int64_t J = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) / 2.0);
+  while (J * (J + 1) / 2 > t) --J;
+  while ((J + 1) * (J + 2) / 2 <= t) ++J;
+  const int64_t I = t - J * (J + 1) / 2;
+  (void)T;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t gi = I * 32 + r, gj = J * 32 + tx;
+    a[r][tx] = (gi < n && gj < n) ? K[gi * n + gj] : 0.0;   // tile (I, J)
+    const int64_t hi = J * 32 + r, hj = I * 32 + tx;
+    b[r][tx] = (hi < n && hj < n) ? K[hi * n + hj] : 0.0;   // tile (J, I)
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    // element (I*32+r, J*32+tx) pairs with (J*32+tx, I*32+r) = b[tx][r]
+    const double v = 0.5 * (a[r][tx] + b[tx][r]);
+    const int64_t gi = I * 32 + r, gj = J * 32 + tx;
+    if (gi < n && gj < n) K[gi * n + gj] = v;
+    const int64_t hi = J * 32 + tx, hj = I * 32 + r;
+    if (hi < n && hj < n) K[hi * n + hj] = v;
+  }
+}
+
+// ------------------------------------------------------------ Cholesky
+// Factor the bs x bs diagonal block at (j0, j0) in LDS; lower triangle
+// only (the strict upper triangle of K is left untouched).  The first
+// non-positive (or NaN) pivot index is recorded in *info.
+__global__ void __launch_bounds__(256)
+potrf_diag(double* __restrict__ K, int64_t n, int64_t j0, int bs,
+           int64_t* __restrict__ info) {
+  __shared__ double a[kNb][kNb + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < bs * bs; e += blockDim.x) {
+    const int i = e / bs, j = e % bs;
+    a[i][j] = (j <= i) ? K[(j0 + i) * n + j0 + j] : 0.0;
+  }
+  for (int k = 0; k < bs; ++k) {
+    __syncthreads();
+    if (tid == 0) {
+      const double d = a[k][k];
+      if (!(d > 0.0) && *info < 0) *info = j0 + k;
+      a[k][k] = sqrt(d);
+    }
+    __syncthreads();
+    const double piv = a[k][k];
+    for (int i = k + 1 + tid; i < bs; i += blockDim.x) a[i][k] /= piv;
+    __syncthreads();
+    const int m = bs - k - 1;  // trailing size
+    for (int e = tid; e < m * m; e += blockDim.x) {
+      const int i = k + 1 + e / m, j = k + 1 + e % m;
+      if (j <= i) a[i][j] -= a[i][k] * a[j][k];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < bs * bs; e += blockDim.x) {
+    const int i = e / bs, j = e % bs;
+    if (j <= i) K[(j0 + i) * n + j0 + j] = a[i][j];
+  }
+}
+
+// Panel rows r in [j1, n): X = B L11^{-T}; one wavefront per 64 rows.
+__global__ void __launch_bounds__(64)
+trsm_panel(double* __restrict__ K, int64_t n, int64_t j0, int bs) {
+  __shared__ double l[kNb][kNb + 1];
+  __shared__ double x[kNb][kNb + 1];
+  const int tid = threadIdx.x;
+  const int64_t j1 = j0 + bs;
+  const int64_t r0 = j1 + (int64_t)blockIdx.x * kNb;
+  const int rows = (int)min((int64_t)kNb, n - r0);
+  for (int i = 0; i < bs; ++i)
+    for (int j = tid; j < bs; j += 64) l[i][j] = (j <= i) ? K[(j0 + i) * n + j0 + j] : 0.0;
+  for (int i = 0; i < rows; ++i)
+    for (int j = tid; j < bs; j += 64) x[i][j] = K[(r0 + i) * n + j0 + j];
+  __syncthreads();
+  if (tid < rows) {
+    for (int c = 0; c < bs; ++c) {
+      double s = x[tid][c];
+      for (int t = 0; t < c; ++t) s -= x[tid][t] * l[c][t];
+      x[tid][c] = s / l[c][c];
+    }
+  }
+  __syncthreads();
+  for (int i = 0; i < rows; ++i)
+    for (int j = tid; j < bs; j += 64) K[(r0 + i) * n + j0 + j] = x[i][j];
+}
+
+// Trailing update of the lower triangle: C[I, J] -= P_I P_J^T for 64 x 64
+// tiles I >= J of rows/cols [j1, n), P = K[j1:n, j0:j0+bs].
+__global__ void __launch_bounds__(256)
+syrk_update(double* __restrict__ K, int64_t n, int64_t j0, int bs) {
+  __shared__ double pi[kNb][kNb + 1];  // [k][row]
+  __shared__ double pj[kNb][kNb + 1];
+  const int64_t j1 = j0 + bs;
+  const int64_t t = blockIdx.x;
+  int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) / 2.0);
+  while (I * (I + 1) / 2 > t) --I;
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  const int64_t J = t - I * (I + 1) / 2;  // J <= I
+  const int64_t ri = j1 + I * kNb, rj = j1 + J * kNb;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kNb * kNb; e += 256) {
+    const int r = e / kNb, k = e % kNb;
+    pi[k][r] = (ri + r < n && k < bs) ? K[(ri + r) * n + j0 + k] : 0.0;
+    pj[k][r] = (rj + r < n && k < bs) ? K[(rj + r) * n + j0 + k] : 0.0;
+  }
+  __syncthreads();
+  const int tx = tid & 15, ty = tid >> 4;
+  double acc[4][4] = {};
+  for (int k = 0; k < bs; ++k) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = pi[k][ty + 16 * u];
+      b[u] = pj[k][tx + 16 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t gi = ri + ty + 16 * u, gj = rj + tx + 16 * v;
+      if (gi < n && gj < n && gj <= gi) K[gi * n + gj] -= acc[u][v];
+    }
+}
+
+// ------------------------------------------------------ triangular solves
+// Y is [nrhs][n].  Forward: L y = b block by block.
+// Solve the diagonal block in place: y[j0:j0+bs] = L11^{-1} y[j0:j0+bs].
+__global__ void __launch_bounds__(64)
+trsv_lower_diag(const double* __restrict__ K, double* __restrict__ Y, int64_t n,
+                int64_t nrhs, int64_t j0, int bs) {
+  __shared__ double l[kNb][kNb + 1];
+  const int tid = threadIdx.x;
+  for (int i = 0; i < bs; ++i)
+    for (int j = tid; j < bs; j += 64) l[i][j] = (j <= i) ? K[(j0 + i) * n + j0 + j] : 0.0;
+  __syncthreads();
+  for (int64_t r = tid; r < nrhs; r += 64) {
+    double* y = Y + r * n + j0;
+    for (int c = 0; c < bs; ++c) {
+      double s = y[c];
+      for (int t = 0; t < c; ++t) s -= l[c][t] * y[t];
+      y[c] = s / l[c][c];
+    }
+  }
+}
+
+// Rows i >= j1: y[i] -= L[i, j0:j1] y[j0:j1]; one wavefront per row, lanes
+// over the block's columns.
+__global__ void __launch_bounds__(256)
+trsv_lower_update(const double* __restrict__ K, double* __restrict__ Y, int64_t n,
+                  int64_t nrhs, int64_t j0, int bs) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = j0 + bs + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  const double l = (lane < bs) ? K[i * n + j0 + lane] : 0.0;
+  for (int64_t r = 0; r < nrhs; ++r) {
+    double v = (lane < bs) ? l * Y[r * n + j0 + lane] : 0.0;
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) Y[r * n + i] -= v;
+  }
+}
+
+// Backward: L^T x = y.  Partial sums of L[i, j0:j1]^T x[i] over row ranges
+// of 256 rows i >= j1: part[w][r][c].
+__global__ void __launch_bounds__(256)
+trsv_upper_partial(const double* __restrict__ K, const double* __restrict__ Y,
+                   double* __restrict__ part, int64_t n, int64_t nrhs, int64_t j0,
+                   int bs) {
+  __shared__ double red[4][kNb];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t j1 = j0 + bs;
+  const int64_t rbeg = j1 + (int64_t)blockIdx.x * 256;
+  const int64_t rend = min(rbeg + 256, n);
+  for (int64_t r = 0; r < nrhs; ++r) {
+    double acc = 0.0;
+    if (lane < bs)
+      for (int64_t i = rbeg + wv; i < rend; i += 4) acc += K[i * n + j0 + lane] * Y[r * n + i];
+    red[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0)
+      part[((int64_t)blockIdx.x * nrhs + r) * kNb + lane] =
+          red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(64)
+trsv_upper_diag(const double* __restrict__ K, double* __restrict__ Y,
+                const double* __restrict__ part, int nparts, int64_t n, int64_t nrhs,
+                int64_t j0, int bs) {
+  __shared__ double l[kNb][kNb + 1];
+  const int tid = threadIdx.x;
+  for (int i = 0; i < bs; ++i)
+    for (int j = tid; j < bs; j += 64) l[i][j] = (j <= i) ? K[(j0 + i) * n + j0 + j] : 0.0;
+  __syncthreads();
+  for (int64_t r = tid; r < nrhs; r += 64) {
+    double* y = Y + r * n + j0;
+    for (int w = 0; w < nparts; ++w)
+      for (int c = 0; c < bs; ++c) y[c] -= part[((int64_t)w * nrhs + r) * kNb + c];
+    for (int c = bs - 1; c >= 0; --c) {
+      double s = y[c];
+      for (int t = c + 1; t < bs; ++t) s -= l[t][c] * y[t];
+      y[c] = s / l[c][c];
+    }
+  }
+}
+
+// ------------------------------------------------- residual r = d - K x
+// K x from the strict upper triangle U (untouched by the factorisation) and
+// the saved diagonal: K x = U x + U^T x + diag x.
+// U x: one wavefront per row, lanes over columns j > i.
+__global__ void __launch_bounds__(256)
+symv_upper_rows(const double* __restrict__ K, const double* __restrict__ X,
+                double* __restrict__ out, int64_t n, int64_t nrhs) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= n) return;
+  for (int64_t r = 0; r < nrhs; ++r) {
+    double acc = 0.0;
+    for (int64_t j = i + 1 + lane; j < n; j += 64) acc += K[i * n + j] * X[r * n + j];
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) out[r * n + i] = acc;
+  }
+}
+
+// U^T x over a chunk of 1024 rows: part[c][r][i] = sum_{j in chunk, j < i} K[j][i] x[j].
+__global__ void __launch_bounds__(256)
+symv_upper_cols(const double* __restrict__ K, const double* __restrict__ X,
+                double* __restrict__ part, int64_t n, int64_t nrhs) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t c = blockIdx.y;
+  const int64_t jbeg = c * 1024, jend = min(jbeg + 1024, n);
+  if (i >= n) return;
+  for (int64_t r = 0; r < nrhs; ++r) {
+    double acc = 0.0;
+    const int64_t je = min(jend, i);
+    for (int64_t j = jbeg; j < je; ++j) acc += K[j * n + i] * X[r * n + j];
+    part[(c * nrhs + r) * n + i] = acc;
+  }
+}
+
+__global__ void residual(const double* __restrict__ D, const double* __restrict__ X,
+                         const double* __restrict__ diag, const double* __restrict__ rows,
+                         const double* __restrict__ part, int nparts, double* __restrict__ R,
+                         int64_t n, int64_t nrhs) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * nrhs) return;
+  const int64_t i = idx % n;
+  double kx = diag[i] * X[idx] + rows[idx];
+  for (int c = 0; c < nparts; ++c) kx += part[(int64_t)c * n * nrhs + idx];
+  R[idx] = D[idx] - kx;
+}
+
+__global__ void copy_diagonal(const double* __restrict__ K, double* __restrict__ d, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = K[i * n + i];
+}
+
+__global__ void axpy(double* __restrict__ y, const double* __restrict__ x, double a, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += a * x[i];
+}
+
+unsigned grid1(int64_t n, int per = 256) {
+  int64_t g = (n + per - 1) / per;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, 1 << 30));
+}
+
+}  // namespace
+
+hipError_t launch_unit_adjoint_spectra(const cpx<double>* A, const cpx<double>* tw,
+                                       cpx<double>* xh, int64_t nf, int64_t Nd,
+                                       int64_t Nm, int64_t L, int64_t j0, int64_t nb,
+                                       hipStream_t s) {
+  const int64_t total = nb * nf * Nm;
+  const unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(unit_adjoint_spectra, dim3(g), dim3(256), 0, s, A, tw, xh, nf, Nd, Nm,
+                     L, j0, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_diagonal(double* K, const double* v, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(add_diagonal, dim3(grid1(n)), dim3(256), 0, s, K, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_symmetrize(double* K, int64_t n, hipStream_t s) {
+  const int64_t T = (n + 31) / 32;
+  const int64_t pairs = T * (T + 1) / 2;
+  if (pairs > 0x7fffffff) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(symmetrize, dim3((unsigned)pairs), dim3(256), 0, s, K, n, T);
+  return hipGetLastError();
+}
+
+// Blocked right-looking Cholesky of the lower triangle.
+hipError_t launch_cholesky(double* K, int64_t n, int64_t* info_dev, hipStream_t s) {
+  for (int64_t j0 = 0; j0 < n; j0 += kNb) {
+    const int bs = (int)std::min<int64_t>(kNb, n - j0);
+    hipLaunchKernelGGL(potrf_diag, dim3(1), dim3(256), 0, s, K, n, j0, bs, info_dev);
+    const int64_t m = n - j0 - bs;
+    if (m > 0) {
+      hipLaunchKernelGGL(trsm_panel, dim3(grid1(m, kNb)), dim3(64), 0, s, K, n, j0, bs);
+      const int64_t T = (m + kNb - 1) / kNb;
+      hipLaunchKernelGGL(syrk_update, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, s, K,
+                         n, j0, bs);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// In place: Y <- (L L^T)^{-1} Y; part: scratch of ceil(n/256)*nrhs*64 doubles.
+hipError_t launch_cholesky_solve(const double* K, double* Y, double* part, int64_t n,
+                                 int64_t nrhs, hipStream_t s) {
+  for (int64_t j0 = 0; j0 < n; j0 += kNb) {
+    const int bs = (int)std::min<int64_t>(kNb, n - j0);
+    hipLaunchKernelGGL(trsv_lower_diag, dim3(1), dim3(64), 0, s, K, Y, n, nrhs, j0, bs);
+    const int64_t m = n - j0 - bs;
+    if (m > 0)
+      hipLaunchKernelGGL(trsv_lower_update, dim3(grid1(m, 4)), dim3(256), 0, s, K, Y, n, nrhs,
+                         j0, bs);
+  }
+  const int64_t last = ((n - 1) / kNb) * kNb;
+  for (int64_t j0 = last; j0 >= 0; j0 -= kNb) {
+    const int bs = (int)std::min<int64_t>(kNb, n - j0);
+    const int64_t m = n - j0 - bs;
+    int nparts = 0;
+    if (m > 0) {
+      nparts = (int)((m + 255) / 256);
+      hipLaunchKernelGGL(trsv_upper_partial, dim3(nparts), dim3(256), 0, s, K, Y, part, n, nrhs,
+                         j0, bs);
+    }
+    hipLaunchKernelGGL(trsv_upper_diag, dim3(1), dim3(64), 0, s, K, Y, part, nparts, n, nrhs,
+                       j0, bs);
+  }
+  return hipGetLastError();
+}
+
+size_t cholesky_solve_scratch(int64_t n, int64_t nrhs) {
+  return (size_t)((n + 255) / 256 + 1) * nrhs * kNb * sizeof(double);
+}
+
+hipError_t launch_copy_diagonal(const double* K, double* d, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(copy_diagonal, dim3(grid1(n)), dim3(256), 0, s, K, d, n);
+  return hipGetLastError();
+}
+
+// R = D - K X with K given by its strict upper triangle and `diag`.
+// rows: [nrhs][n] scratch; part: [ceil(n/1024)][nrhs][n] scratch.
+hipError_t launch_residual(const double* K, const double* diag, const double* D,
+                           const double* X, double* R, double* rows, double* part, int64_t n,
+                           int64_t nrhs, hipStream_t s) {
+  hipLaunchKernelGGL(symv_upper_rows, dim3(grid1(n, 4)), dim3(256), 0, s, K, X, rows, n, nrhs);
+  const int64_t nc = (n + 1023) / 1024;
+  hipLaunchKernelGGL(symv_upper_cols, dim3(grid1(n), (unsigned)nc), dim3(256), 0, s, K, X,
+                     part, n, nrhs);
+  hipLaunchKernelGGL(residual, dim3(grid1(n * nrhs)), dim3(256), 0, s, D, X, diag, rows, part,
+                     (int)nc, R, n, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(axpy, dim3(grid1(n)), dim3(256), 0, s, y, x, a, n);
+  return hipGetLastError();
+}
+
+}  // namespace p2o

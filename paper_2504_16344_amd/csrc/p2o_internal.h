@@ -80,34 +80,57 @@ struct GemvShape {
   int64_t pc_len; // F only: columns per chunk (multiple of 64)
 };
 
-// F, float64: P[b][pc][k][s] = sum_{p in chunk pc} A[k][s][p] X[b][k][p]
-hipError_t launch_gemv_rows_f64(const cpx<double>* A, const cpx<double>* X,
-                                cpx<double>* P, const GemvShape& g,
-                                hipStream_t s);
-// F*, float64: Y[b][k][p] = sum_s conj(A[k][s][p]) D[b][k][s]
-hipError_t launch_gemv_cols_f64(const cpx<double>* A, const cpx<double>* D,
-                                cpx<double>* Y, const GemvShape& g,
-                                hipStream_t s);
-
-// Mixed storage: one uint2 per complex entry holding (hi.re, hi.im) in .x
-// and (lo.re, lo.im) in .y as 16-bit words (low half = real part).
+// Mixed storage: 16-bit terms packed per complex entry, word 0 = hi (real
+// part in the low half), word 1 = lo (absent for the hi-only tier).
 constexpr int kScaleTile = 256;  // columns per scale sub-block
 enum class Fmt16 { FP16 = 0, BF16 = 1 };
 
-hipError_t launch_gemv_rows_mixed(const uint2* A, const float* scales,
+// Candidate configurations of the product kernels (rows per wavefront for
+// F, column groups per wavefront for F*, vector width).  `cfg` indexes the
+// candidate table of the kernel family; 0 is the untuned default.
+int gemv_candidates(bool mixed, p2o_op op);
+int gemv_vec_width(bool mixed, bool lo, p2o_op op, int cfg);
+int gemv_rows_per_wave(bool mixed, int cfg);
+
+// F, float64: P[b][pc][k][s] = sum_{p in chunk pc} A[k][s][p] X[b][k][p]
+hipError_t launch_gemv_rows_f64(const cpx<double>* A, const cpx<double>* X,
+                                cpx<double>* P, const GemvShape& g, int cfg,
+                                hipStream_t s);
+// F*, float64: Y[b][k][p] = sum_s conj(A[k][s][p]) D[b][k][s]
+hipError_t launch_gemv_cols_f64(const cpx<double>* A, const cpx<double>* D,
+                                cpx<double>* Y, const GemvShape& g, int cfg,
+                                hipStream_t s);
+hipError_t launch_gemv_rows_mixed(const void* A, const float* scales,
                                   const cpx<float>* X, cpx<double>* P,
                                   const GemvShape& g, Fmt16 fmt, bool use_lo,
-                                  hipStream_t s);
-hipError_t launch_gemv_cols_mixed(const uint2* A, const float* scales,
+                                  int cfg, hipStream_t s);
+hipError_t launch_gemv_cols_mixed(const void* A, const float* scales,
                                   const cpx<float>* D, cpx<float>* Y,
                                   const GemvShape& g, Fmt16 fmt, bool use_lo,
-                                  hipStream_t s);
+                                  int cfg, hipStream_t s);
 // Quantise a float64 frequency chunk [nf][Nd][pc] into the packed layout at
 // column offset p0 of [nf][Nd][Nm], with one scale per (k, 256-col tile).
 hipError_t launch_quantise(const cpx<double>* chunk, int64_t nf, int64_t Nd,
-                           int64_t Nm, int64_t p0, int64_t pc, uint2* A,
+                           int64_t Nm, int64_t p0, int64_t pc, void* A,
                            float* scales, Fmt16 fmt, bool use_lo,
                            hipStream_t s);
+
+// ------------------------------------------------------- inversion kernels
+hipError_t launch_unit_adjoint_spectra(const cpx<double>* A, const cpx<double>* tw,
+                                       cpx<double>* xh, int64_t nf, int64_t Nd,
+                                       int64_t Nm, int64_t L, int64_t j0, int64_t nb,
+                                       hipStream_t s);
+hipError_t launch_add_diagonal(double* K, const double* v, int64_t n, hipStream_t s);
+hipError_t launch_symmetrize(double* K, int64_t n, hipStream_t s);
+hipError_t launch_cholesky(double* K, int64_t n, int64_t* info_dev, hipStream_t s);
+hipError_t launch_cholesky_solve(const double* K, double* Y, double* part, int64_t n,
+                                 int64_t nrhs, hipStream_t s);
+size_t cholesky_solve_scratch(int64_t n, int64_t nrhs);
+hipError_t launch_copy_diagonal(const double* K, double* d, int64_t n, hipStream_t s);
+hipError_t launch_residual(const double* K, const double* diag, const double* D,
+                           const double* X, double* R, double* rows, double* part, int64_t n,
+                           int64_t nrhs, hipStream_t s);
+hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t s);
 
 }  // namespace p2o
 
@@ -126,6 +149,7 @@ struct p2o_plan_s {
   int64_t n_pc = 1;                  // F product: column chunks
   int64_t pc_len = 0;                // F product: columns per chunk
   int64_t cols_done = 0;             // setup progress
+  int cfg[2] = {0, 0};               // product-kernel candidate per op
   bool ready = false;
   void* scratch = nullptr;           // setup chunk staging (mixed)
   size_t scratch_bytes = 0;

@@ -118,7 +118,7 @@ quantise_kernel(const cpx<double>* __restrict__ chunk, int64_t nf, int64_t Nd,
 }  // namespace
 
 hipError_t launch_quantise(const cpx<double>* chunk, int64_t nf, int64_t Nd,
-                           int64_t Nm, int64_t p0, int64_t pc, uint2* A,
+                           int64_t Nm, int64_t p0, int64_t pc, void* A,
                            float* scales, Fmt16 fmt, bool use_lo,
                            hipStream_t s) {
   if (pc < 1) return hipSuccess;

@@ -1,0 +1,103 @@
+"""Data-space Hessian K = Gn + F Gp F* (Phase 2) and the posterior mean
+m = Gp F* K^{-1} d (Phase 4) through the C ABI, against the oracle: full K
+at small and ragged sizes (Cholesky blocks of 64 with a ragged tail, several
+right-hand sides, 0-2 refinement steps), sampled K columns and the MAP
+optimality condition at the 100 x 5000 x 200 inversion workload, and the
+error paths."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import p2o_synth as S
+import paper_2504_16344_amd as P
+from gpu_helpers import dev, host, rel_err, workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _noise(seed, n, lo=0.05, hi=0.5):
+    u = (S.vector(seed, S.ARRAY_NOISE, n) + 10.0) / 20.0  # deterministic, positive
+    return lo + (hi - lo) * np.clip(u, 0.0, 1.0)
+
+
+@pytest.mark.parametrize("shape,nrhs,refine", [
+    ((3, 40, 7), 1, 1),
+    ((5, 300, 29), 3, 0),
+    ((5, 300, 29), 2, 2),
+    ((10, 500, 60), 1, 1),
+    ((20, 300, 55), 2, 1),
+])
+def test_hessian_and_posterior_match_oracle(shape, nrhs, refine):
+    Nd, Nm, Nt = shape
+    print(f"\n[inverse] shape={shape} nrhs={nrhs} refine={refine}", flush=True)
+    blocks, _, _ = workload(6, Nd, Nm, Nt, tau=Nt / 3)
+    n = Nt * Nd
+    nv = _noise(6, n)
+    d = S.vector(6, S.ARRAY_D, nrhs * n).reshape(nrhs, Nt, Nd)
+    K_ref = oracle.hessian_gram(blocks, 0.25, nv)
+    m_ref = np.stack([oracle.posterior_mean(blocks, 0.25, nv, d[r], K=K_ref) for r in range(nrhs)])
+    with P.Plan(dev(blocks), "fp64") as plan:
+        K = plan.hessian(0.25, dev(nv))
+        Kh = host(K)
+        m = host(plan.posterior(K, dev(d), 0.25, refine_steps=refine))
+        L = np.tril(host(K))
+    eK = np.abs(Kh - K_ref).max() / np.abs(K_ref).max()
+    em = rel_err(m, m_ref)
+    print(f"  K err {eK:.2e}  m err {em:.2e}", flush=True)
+    assert np.array_equal(Kh, Kh.T)
+    assert eK <= 1e-12
+    assert em <= 1e-10
+    # the factor left in the lower triangle reproduces K
+    assert np.abs(L @ L.T - K_ref).max() / np.abs(K_ref).max() <= 1e-12
+
+
+def test_inversion_workload_100x5000x200():
+    """Full-size K (20000 x 20000): sampled columns against the paper's
+    unit-vector definition in the oracle, then the posterior mean checked by
+    the MAP optimality condition F* Gn^-1 (F m - d) + m / Gp = 0."""
+    Nd, Nm, Nt = 100, 5000, 200
+    print("\n[inverse] 100x5000x200", flush=True)
+    blocks, m_true, _ = workload(5, Nd, Nm, Nt, tau=40.0)
+    n = Nt * Nd
+    d_clean = oracle.apply_F(blocks, m_true)
+    s2 = 1e-2 * float(np.mean(d_clean ** 2))
+    d_obs = d_clean + np.sqrt(s2) * S.vector(5, S.ARRAY_NOISE, n).reshape(Nt, Nd)
+    nv = np.full(n, s2)
+    with P.Plan(dev(blocks), "fp64") as plan:
+        K = plan.hessian(0.25, dev(nv))
+        torch.cuda.synchronize()
+        for col in (0, 1, 99, 5050, 12345, n - 1):
+            ref = oracle.hessian_column(blocks, 0.25, nv, col)
+            got = host(K[:, col])
+            e = np.abs(got - ref).max() / np.abs(ref).max()
+            print(f"  K column {col}: err {e:.2e}", flush=True)
+            assert e <= 1e-12
+        m = host(plan.posterior(K, dev(d_obs), 0.25, refine_steps=1))
+    g = oracle.map_objective_gradient(blocks, 0.25, nv, d_obs, m)
+    scale = np.linalg.norm(m / 0.25)
+    print(f"  MAP gradient rel {np.linalg.norm(g) / scale:.2e}", flush=True)
+    assert np.linalg.norm(g) / scale <= 1e-9
+
+
+def test_not_positive_definite_reports_pivot():
+    Nd, Nm, Nt = 4, 30, 50  # n = 200: pivot in the fourth Cholesky block
+    blocks, _, _ = workload(7, Nd, Nm, Nt, tau=5.0)
+    n = Nt * Nd
+    with P.Plan(dev(blocks), "fp64") as plan:
+        K = torch.eye(n, dtype=torch.float64, device="cuda")
+        K[137, 137] = -1.0
+        with pytest.raises(P.P2OError) as e:
+            plan.posterior(K, dev(np.ones((Nt, Nd))), 0.25)
+        assert e.value.status == 4 and e.value.failed_pivot == 137
+        # the plan is still usable afterwards
+        K2 = plan.hessian(0.25, dev(np.full(n, 0.1)))
+        assert torch.isfinite(K2).all()
+
+
+def test_inversion_needs_fp64_plan():
+    blocks, _, _ = workload(8, 2, 256, 4, tau=2.0)
+    with P.Plan(dev(blocks), "mixed_bf16") as plan:
+        with pytest.raises(P.P2OError) as e:
+            plan.hessian(0.25, dev(np.ones(8)))
+        assert e.value.status == 6
