@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--tau", type=float, default=80.0)
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--precs", default="mixed_bf16,fp64,mixed_fp16")
-    ap.add_argument("--cpu-cols", type=int, default=24576,
+    ap.add_argument("--cpu-cols", type=int, default=40000,
                     help="columns of the workload the CPU oracle baseline runs on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-gb", type=float, default=4.0,
@@ -102,6 +102,20 @@ def n_chunks(Nd, Nm, nf):
     ln = (Nm + n - 1) // n
     ln = (ln + 63) // 64 * 64
     return (Nm + ln - 1) // ln
+
+
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "hbm_traffic_600x40000x420.json")
+
+
+def load_traffic():
+    """Calibrated counter bytes per launch of the product kernels, if they were
+    measured on the current kernel source (else None: traffic is then null)."""
+    from paper_2504_16344_amd.rocprof_summary import source_digest
+    try:
+        t = json.load(open(TRAFFIC_JSON))
+    except (OSError, ValueError):
+        return None
+    return t if t.get("source_sha256") == source_digest() else None
 
 
 def make_plan(P, S, torch, prec, Nd, Nm, Nt, env_dev, seed, stream):
@@ -273,6 +287,14 @@ def main():
     if copy:
         for r in rooflines.values():
             r["frac_of_measured_copy"] = round(r["achieved"] / copy["gbs"], 4)
+    traffic = load_traffic()
+    if traffic is not None:
+        for op, r in rooflines.items():
+            kname = traffic["by_family"].get(f"{head}/{op}")
+            if kname:
+                kv = traffic["kernels"][kname]
+                r["traffic"] = round(kv["read_bytes"] + kv["write_bytes"])
+                r["traffic_kernel"] = kname
     dom = max(("F", "FADJ"), key=lambda o: h["product_kernel_ms"][o])
     out = {
         "metric": "F/F* apply time & HBM GB/s @Nd=600,Nt=420; mixed vs FP64 at stated rel err",
