@@ -49,6 +49,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-gb", type=float, default=4.0,
                     help="size of the plain device copy timed as the measured HBM ceiling")
+    ap.add_argument("--workload", default="single", choices=["single", "batch"],
+                    help="single: the 600x40000x420 F+F* step (default); batch: 64 uneven "
+                         "instances with 1..256 right-hand sides each")
+    ap.add_argument("--instances", type=int, default=64)
+    ap.add_argument("--budget-gb", type=float, default=200.0,
+                    help="batch workload: device memory per wave of resident instances")
+    ap.add_argument("--no-fp64-loop", action="store_true",
+                    help="batch workload: skip the instance-by-instance float64 comparison")
     return ap.parse_args()
 
 
@@ -180,12 +188,179 @@ def cpu_baseline(torch, S, args, nf, headline_step_bytes, env):
                       f"algorithmic bytes / that time"}
 
 
+# ----------------------------------------------------------------------------
+# Batched uneven instances
+# ----------------------------------------------------------------------------
+def instance_bytes(prec, Nd, Nm, Nt, R, nf, n_pc):
+    """Device bytes one resident instance needs: frequency blocks, apply
+    workspace (largest of F and F*) and its input/output vectors."""
+    n8 = lambda n: (n + 7) // 8 * 8
+    if prec == "fp64":
+        fhat = 16 * nf * Nd * Nm
+        ws = max(R * nf * Nm * 16 + R * n_pc * nf * Nd * 16, R * nf * (Nd + Nm) * 16)
+    else:
+        fhat = 8 * nf * Nd * Nm + 4 * nf * ((Nm + 255) // 256)
+        ws = max(R * nf * Nm * 8 + R * n_pc * nf * Nd * 16 + R * nf * 8 * n8(Nm),
+                 R * nf * (Nd + Nm) * 8 + R * nf * 8 * n8(Nd))
+    vec = 2 * R * Nt * (Nm + Nd) * 8
+    return fhat + ws + vec
+
+
+def batch_apply_bytes(prec, Nd, Nm, Nt, R, nf, n_pc):
+    """Algorithmic HBM bytes of one F apply plus one F* apply of an instance:
+    blocks streamed once per op, vectors and spectra read and written once."""
+    eb, vb = ENTRY_BYTES[prec], VEC_BYTES[prec]
+    blocks = nf * Nd * Nm * eb
+    vecF = R * (Nt * Nm * 8 + 2 * nf * Nm * vb + 2 * n_pc * nf * Nd * 16 + Nt * Nd * 8)
+    vecA = R * (Nt * Nd * 8 + 2 * nf * Nd * vb + 2 * nf * Nm * vb + Nt * Nm * 8)
+    return 2 * blocks + vecF + vecA
+
+
+def bench_batch(args):
+    import torch
+    import p2o_synth as S
+    import paper_2504_16344_amd as P
+
+    n, seed, Nt = args.instances, 4, args.Nt
+    Nd = S.uniform_ints(seed, S.ARRAY_SHAPES, n, 50, 600)
+    Nm = S.uniform_ints(seed, S.ARRAY_SHAPES, n, 1000, 20000, offset=n)
+    R = S.uniform_ints(seed, S.ARRAY_SHAPES, n, 1, 256, offset=2 * n)
+    L = P.smooth_length(Nt)
+    nf = L // 2 + 1
+    stream = torch.cuda.current_stream()
+    prec = "mixed_bf16"
+    npc = [n_chunks(int(Nd[i]), int(Nm[i]), nf) for i in range(n)]
+    need = [instance_bytes(prec, int(Nd[i]), int(Nm[i]), Nt, int(R[i]), nf, npc[i]) for i in range(n)]
+    budget = args.budget_gb * 1e9
+    waves, cur, used = [], [], 0
+    for i in range(n):
+        if cur and used + need[i] > budget:
+            waves.append(cur)
+            cur, used = [], 0
+        cur.append(i)
+        used += need[i]
+    waves.append(cur)
+
+    def inputs(i):
+        inst_seed = 1000 * seed + i
+        m = torch.empty((int(R[i]), Nt, int(Nm[i])), dtype=torch.float64, device="cuda")
+        d = torch.empty((int(R[i]), Nt, int(Nd[i])), dtype=torch.float64, device="cuda")
+        S.device_normals(m.data_ptr(), m.numel(), 0, inst_seed, S.ARRAY_M, 1.0, stream.cuda_stream)
+        S.device_normals(d.data_ptr(), d.numel(), 0, inst_seed, S.ARRAY_D, 1.0, stream.cuda_stream)
+        return m, d
+
+    def plan_for(i, p):
+        env = torch.from_numpy(S.envelope(Nt, 80.0, 1.0 / np.sqrt(int(Nm[i])))).cuda()
+        return make_plan(P, S, torch, p, int(Nd[i]), int(Nm[i]), Nt, env, 1000 * seed + i, stream)
+
+    reps = max(1, args.steps)
+    total_ms = {"F": 0.0, "FADJ": 0.0}
+    wave_info, samples = [], {}
+    for w, ids in enumerate(waves):
+        t0 = time.perf_counter()
+        plans = [plan_for(i, prec) for i in ids]
+        vecs = [inputs(i) for i in ids]
+        yF = [torch.empty((int(R[i]), Nt, int(Nd[i])), dtype=torch.float64, device="cuda") for i in ids]
+        yA = [torch.empty((int(R[i]), Nt, int(Nm[i])), dtype=torch.float64, device="cuda") for i in ids]
+        batch = P.Batch(plans)
+        gF = batch.capture(P.OP_F, [v[0] for v in vecs], yF)
+        gA = batch.capture(P.OP_FADJ, [v[1] for v in vecs], yA)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        for _ in range(args.warmup):
+            gF.launch()
+            gA.launch()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record()
+        for _ in range(reps):
+            gF.launch()
+        ev[1].record()
+        for _ in range(reps):
+            gA.launch()
+        ev[2].record()
+        torch.cuda.synchronize()
+        msF, msA = ev[0].elapsed_time(ev[1]) / reps, ev[1].elapsed_time(ev[2]) / reps
+        total_ms["F"] += msF
+        total_ms["FADJ"] += msA
+        for j, i in enumerate(ids):
+            samples[i] = (yF[j][0].cpu(), yA[j][0].cpu())
+        wave_info.append({"instances": len(ids), "resident_gb": round(sum(need[i] for i in ids) / 1e9, 1),
+                          "ms_F": round(msF, 3), "ms_FADJ": round(msA, 3), "setup_s": round(setup_s, 1)})
+        print(f"[batch] wave {w}: {len(ids)} instances, F {msF:.2f} ms, F* {msA:.2f} ms, "
+              f"setup {setup_s:.1f} s", file=sys.stderr, flush=True)
+        gF.close()
+        gA.close()
+        batch.close()
+        for p in plans:
+            p.close()
+        del plans, vecs, yF, yA, batch
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+
+    fp64 = None
+    errs = []
+    if not args.no_fp64_loop:
+        fp64_ms = 0.0
+        for i in range(n):
+            p = plan_for(i, "fp64")
+            m, d = inputs(i)
+            yf = p.F(m)
+            ya = p.FT(d)
+            torch.cuda.synchronize()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record()
+            for _ in range(reps):
+                p.F(m, out=yf)
+                p.FT(d, out=ya)
+            ev[1].record()
+            torch.cuda.synchronize()
+            fp64_ms += ev[0].elapsed_time(ev[1]) / reps
+            sF, sA = samples[i]
+            errs.append(max((torch.linalg.norm(sF - yf[0].cpu()) / torch.linalg.norm(yf[0].cpu())).item(),
+                            (torch.linalg.norm(sA - ya[0].cpu()) / torch.linalg.norm(ya[0].cpu())).item()))
+            p.close()
+            del p, m, d, yf, ya
+            torch.cuda.empty_cache()
+        fp64 = fp64_ms
+        print(f"[batch] fp64 instance loop: {fp64_ms:.1f} ms per F+F* over all instances",
+              file=sys.stderr, flush=True)
+
+    step_ms = total_ms["F"] + total_ms["FADJ"]
+    bytes_total = sum(batch_apply_bytes(prec, int(Nd[i]), int(Nm[i]), Nt, int(R[i]), nf, npc[i])
+                      for i in range(n))
+    flops = sum(2 * 8 * nf * int(Nd[i]) * int(Nm[i]) * int(R[i]) for i in range(n))
+    out = {
+        "metric": "batched F/F* apply time, uneven instances; mixed (bf16 hi+lo, matrix cores) vs FP64 instance loop",
+        "value": round(bytes_total / (step_ms * 1e-3) / 1e9, 1),
+        "unit": "GB/s",
+        "n_gpus": 1, "steps": reps, "warmup": args.warmup,
+        "ms_per_step": round(step_ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16x2/f32", "data": "synthetic (seeded counter-based normals, generated on device)",
+        "config": {"workload": f"{n} independent p2o instances, Nt={Nt}, Nd U{{50..600}}, "
+                               f"Nm U{{1000..20000}}, 1..256 RHS each; F and F* as captured HIP "
+                               f"graphs (one persistent product launch per op per memory wave)",
+                   "instances": n, "Nt": Nt, "waves": len(waves),
+                   "rhs_total": int(R.sum()), "budget_gb": args.budget_gb},
+        "complex_tflops": round(flops / (step_ms * 1e-3) / 1e12, 2),
+        "waves": wave_info,
+        "op_ms": {k: round(v, 3) for k, v in total_ms.items()},
+    }
+    if fp64 is not None:
+        out["fp64_loop_ms"] = round(fp64, 3)
+        out["speedup_vs_fp64_loop"] = round(fp64 / step_ms, 3)
+        out["rel_err_vs_fp64_max"] = max(errs)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding is a design note, not a measured path)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        return bench_batch(args)
     import torch
     import p2o_synth as S
     import paper_2504_16344_amd as P

@@ -153,6 +153,49 @@ p2o_status p2o_get_config(p2o_handle h, p2o_op op, int64_t* cfg,
  * P2O_EUNSUPPORTED if not valid for this plan's shape. */
 p2o_status p2o_set_config(p2o_handle h, p2o_op op, int64_t cfg);
 
+/* Switch the frequency-block product of `op` from the vector-unit kernels
+ * above to matrix-core (MFMA) kernels once a call has at least `min_rhs`
+ * right-hand sides (default 8); min_rhs <= 0 keeps the vector-unit kernels
+ * for every nrhs.  P2O_FP64 plans use float64 MFMA; P2O_MIXED_BF16 and
+ * P2O_FAST_BF16 plans use bfloat16 MFMA with the vector split into hi + lo
+ * bfloat16 terms and float32 accumulation (same error class as their
+ * vector-unit kernels); P2O_MIXED_FP16 plans always use the vector units. */
+p2o_status p2o_set_mfma_threshold(p2o_handle h, p2o_op op, int64_t min_rhs);
+
+/* ---------------------------------------------------- batched instances */
+
+/* A batch groups independent, set-up plans of uneven shape (all of one
+ * precision, on one device, each plan at most once: instances use their
+ * own workspaces) so that one call applies all of them.  Per instance the
+ * block product takes the vector-unit path or the matrix-core path by its
+ * right-hand-side count (p2o_set_mfma_threshold of that plan), and the
+ * products of all instances run in ONE persistent kernel launch that walks
+ * their work units; each instance's transforms are launched around it.
+ * The plans must outlive the batch.  NULL-safe destroy. */
+typedef struct p2o_batch_s* p2o_batch;
+typedef struct p2o_graph_s* p2o_graph;
+
+p2o_status p2o_batch_create(const p2o_handle* plans, int64_t n, p2o_batch* out);
+
+/* y[i] = F x[i] or F* x[i] for every instance i < n.
+ *   x, y   HOST arrays of n device pointers, laid out as for p2o_apply;
+ *   nrhs   HOST array of n right-hand-side counts (1..65535).
+ * Synchronises `stream` first (the work table is reused between calls),
+ * may allocate instance workspaces; then enqueues without waiting. */
+p2o_status p2o_batch_apply(p2o_batch b, p2o_op op, const double* const* x,
+                           double* const* y, const int64_t* nrhs, void* stream);
+
+/* Capture one batched apply on fixed buffers into a HIP graph (workspaces
+ * are reserved before capture; the graph holds no allocation or memset).
+ * p2o_graph_launch replays it on `stream`; replays read x and write y at
+ * the captured addresses. */
+p2o_status p2o_batch_capture(p2o_batch b, p2o_op op, const double* const* x,
+                             double* const* y, const int64_t* nrhs, void* stream,
+                             p2o_graph* out);
+p2o_status p2o_graph_launch(p2o_graph g, void* stream);
+void p2o_graph_destroy(p2o_graph g);
+void p2o_batch_destroy(p2o_batch b);
+
 /* ------------------------------------------------------ inversion (FP64) */
 
 /* K = Gamma_noise + F Gamma_prior F* (Phase 2), Gamma_prior =

@@ -23,7 +23,7 @@ definition; the two may differ in the last bit of ``log``/``cos``
 (host libm versus the device math library), i.e. by about 1e-16 relative.
 
 Input recipes (seed = workload index; array ids blocks=1, m=2, d=3, noise=4,
-direction=5):
+direction=5, instance shapes=6):
 
 * blocks ``F_k[s, p] = z((k*Nd + s)*Nm + p) * env[k]`` with
   ``env[k] = exp(-k / tau) * amp``.  The envelope table is computed once on
@@ -47,6 +47,7 @@ ARRAY_M = 2
 ARRAY_D = 3
 ARRAY_NOISE = 4
 ARRAY_DIRECTION = 5
+ARRAY_SHAPES = 6
 
 
 _CHUNK = 1 << 20
@@ -113,6 +114,16 @@ def normals(seed: int, array_id: int, idx) -> np.ndarray:
     out = np.empty(flat.shape[0], dtype=np.float64)
     _normals_flat(stream_key(seed, array_id), flat, out)
     return out.reshape(idx.shape)
+
+
+def uniform_ints(seed: int, array_id: int, n: int, lo: int, hi: int,
+                 offset: int = 0) -> np.ndarray:
+    """Integers uniform on lo..hi inclusive from draws offset..offset+n-1:
+    draw mod (hi - lo + 1), plus lo."""
+    key = stream_key(seed, array_id)
+    z = (np.arange(offset, offset + n, dtype=np.uint64) + np.uint64(1)) * GOLDEN + key
+    _mix64_inplace(z, np.empty_like(z))
+    return (z % np.uint64(hi - lo + 1)).astype(np.int64) + lo
 
 
 def envelope(Nt: int, tau: float, amp: float = 1.0) -> np.ndarray:

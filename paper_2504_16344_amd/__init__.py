@@ -14,7 +14,7 @@ import os
 import torch
 
 __all__ = [
-    "Plan", "P2OError", "P2OApply", "P2OAdjoint", "load_library", "LIB_PATH",
+    "Plan", "Batch", "Graph", "P2OError", "P2OApply", "P2OAdjoint", "load_library", "LIB_PATH",
     "FP64", "MIXED_FP16", "MIXED_BF16", "FAST_BF16", "OP_F", "OP_FADJ",
     "smooth_length", "EXPORTED_SYMBOLS",
 ]
@@ -50,7 +50,15 @@ _SIGNATURES = {
     "p2o_autotune": (_int, [_vp, _int, _int, _c.POINTER(_dbl), _i64, _c.POINTER(_i64), _vp]),
     "p2o_get_config": (_int, [_vp, _int, _c.POINTER(_i64), _c.POINTER(_i64)]),
     "p2o_set_config": (_int, [_vp, _int, _i64]),
+    "p2o_set_mfma_threshold": (_int, [_vp, _int, _i64]),
     "p2o_kernel_time": (_int, [_vp, _int, _c.POINTER(_dbl), _c.POINTER(_i64)]),
+    "p2o_batch_create": (_int, [_c.POINTER(_vp), _i64, _c.POINTER(_vp)]),
+    "p2o_batch_apply": (_int, [_vp, _int, _c.POINTER(_vp), _c.POINTER(_vp), _c.POINTER(_i64), _vp]),
+    "p2o_batch_capture": (_int, [_vp, _int, _c.POINTER(_vp), _c.POINTER(_vp), _c.POINTER(_i64),
+                                 _vp, _c.POINTER(_vp)]),
+    "p2o_graph_launch": (_int, [_vp, _vp]),
+    "p2o_graph_destroy": (None, [_vp]),
+    "p2o_batch_destroy": (None, [_vp]),
 }
 EXPORTED_SYMBOLS = tuple(_SIGNATURES)
 
@@ -267,6 +275,11 @@ class Plan:
     def set_config(self, op: int, cfg: int) -> None:
         _check("p2o_set_config", self._lib.p2o_set_config(self._handle(), op, cfg))
 
+    def set_mfma_threshold(self, op: int, min_rhs: int) -> None:
+        """Use the matrix-core kernels from `min_rhs` right-hand sides on (<= 0: never)."""
+        _check("p2o_set_mfma_threshold",
+               self._lib.p2o_set_mfma_threshold(self._handle(), op, min_rhs))
+
     def set_kernel_timing(self, enable: bool) -> None:
         _check("p2o_set_kernel_timing", self._lib.p2o_set_kernel_timing(self._handle(), int(enable)))
 
@@ -293,6 +306,80 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Batch:
+    """Independent plans of uneven shape applied together: one persistent
+    product launch per apply, optionally captured once into a HIP graph."""
+
+    def __init__(self, plans):
+        self._lib = load_library()
+        self.plans = list(plans)
+        hs = (_vp * len(self.plans))(*[p.handle for p in self.plans])
+        h = _vp()
+        _check("p2o_batch_create", self._lib.p2o_batch_create(hs, len(self.plans), _c.byref(h)))
+        self._h = h
+
+    def _args(self, op, xs, ys):
+        if len(xs) != len(self.plans):
+            raise ValueError("one input per plan")
+        outs, nr = [], []
+        for p, x, y in zip(self.plans, xs, ys if ys is not None else [None] * len(xs)):
+            x = _dev_f64(x, "x")
+            n_in, n_out = (p.Nm, p.Nd) if op == OP_F else (p.Nd, p.Nm)
+            if x.shape[-2:] != (p.Nt, n_in) or x.dim() not in (2, 3):
+                raise ValueError(f"input must end in ({p.Nt}, {n_in})")
+            shape = x.shape[:-1] + (n_out,)
+            y = torch.empty(shape, dtype=torch.float64, device=x.device) if y is None else y
+            outs.append(_dev_f64(y, "y"))
+            nr.append(1 if x.dim() == 2 else int(x.shape[0]))
+        n = len(xs)
+        return (outs, (_vp * n)(*[t.data_ptr() for t in xs]),
+                (_vp * n)(*[t.data_ptr() for t in outs]), (_i64 * n)(*nr))
+
+    def apply(self, op: int, xs, ys=None, stream=None):
+        outs, xp, yp, nr = self._args(op, xs, ys)
+        _check("p2o_batch_apply", self._lib.p2o_batch_apply(self._h, op, xp, yp, nr,
+                                                            _stream_handle(stream)))
+        return outs
+
+    def capture(self, op: int, xs, ys, stream=None) -> "Graph":
+        """Graph of one batched apply reading xs and writing ys (fixed buffers)."""
+        outs, xp, yp, nr = self._args(op, xs, ys)
+        g = _vp()
+        _check("p2o_batch_capture", self._lib.p2o_batch_capture(self._h, op, xp, yp, nr,
+                                                                _stream_handle(stream), _c.byref(g)))
+        return Graph(self._lib, g)
+
+    def close(self):
+        if self._h is not None:
+            self._lib.p2o_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    def __init__(self, lib, h):
+        self._lib, self._h = lib, h
+
+    def launch(self, stream=None):
+        _check("p2o_graph_launch", self._lib.p2o_graph_launch(self._h, _stream_handle(stream)))
+
+    def close(self):
+        if self._h is not None:
+            self._lib.p2o_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class P2OApply(torch.autograd.Function):

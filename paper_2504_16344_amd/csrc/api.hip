@@ -79,23 +79,29 @@ void choose_chunks(p2o_plan_s* h, int64_t* n_pc, int64_t* pc_len) {
 }
 
 struct WsLayout {
-  size_t a_off, b_off, total;
+  size_t a_off, b_off, c_off, total;
 };
+
+int64_t round8(int64_t n) { return (n + 7) / 8 * 8; }
 
 // F : a = transformed x [nrhs][nf][Nm], b = partial spectra [nrhs][n_pc][nf][Nd]
 // F*: a = transformed x [nrhs][nf][Nd], b = product      [nrhs][nf][Nm]
+// mixed plans: c = a split into bfloat16 planes [nrhs][nf][4][round8(n_in)]
+// for the matrix-core product.
 WsLayout ws_layout(const p2o_plan_s* h, p2o_op op, int64_t nrhs) {
-  const size_t vb = is_mixed(h->prec) ? 8 : 16;  // complex vector entry
+  const bool mixed = is_mixed(h->prec);
+  const size_t vb = mixed ? 8 : 16;  // complex vector entry
+  const int64_t nin = (op == P2O_F) ? h->Nm : h->Nd;
   WsLayout w{};
+  w.a_off = 0;
   if (op == P2O_F) {
-    w.a_off = 0;
     w.b_off = align_up((size_t)nrhs * h->nf * h->Nm * vb);
-    w.total = w.b_off + align_up((size_t)nrhs * h->n_pc * h->nf * h->Nd * 16);
+    w.c_off = w.b_off + align_up((size_t)nrhs * h->n_pc * h->nf * h->Nd * 16);
   } else {
-    w.a_off = 0;
     w.b_off = align_up((size_t)nrhs * h->nf * h->Nd * vb);
-    w.total = w.b_off + align_up((size_t)nrhs * h->nf * h->Nm * vb);
+    w.c_off = w.b_off + align_up((size_t)nrhs * h->nf * h->Nm * vb);
   }
+  w.total = w.c_off + (mixed ? align_up((size_t)nrhs * h->nf * 4 * round8(nin) * 2) : 0);
   return w;
 }
 
@@ -174,6 +180,8 @@ p2o_status begin_impl(int64_t Nd, int64_t Nm, int64_t Nt, p2o_prec prec,
   h->prec = prec;
   h->ntiles = (Nm + kScaleTile - 1) / kScaleTile;
   choose_chunks(h, &h->n_pc, &h->pc_len);
+  if (prec == P2O_FP64) h->mfma_min_rhs[0] = h->mfma_min_rhs[1] = 0;  // float64 MFMA off by default
+  if (prec == P2O_MIXED_FP16) h->mfma_min_rhs[0] = h->mfma_min_rhs[1] = 0;
   hipError_t e = hipGetDevice(&h->device);
   if (e != hipSuccess) {
     free_plan(h);
@@ -265,12 +273,26 @@ int default_cfg(const p2o_plan_s* h, p2o_op op) {
 }
 
 // The frequency-block product of `op` with candidate `cfg`; `a` is the
-// transformed input, `b` the product (F: partial spectra).
-hipError_t launch_product(const p2o_plan_s* h, p2o_op op, void* a, void* b,
+// transformed input, `b` the product (F: partial spectra), `c` scratch for
+// the bfloat16 operand planes of the mixed matrix-core path.
+bool use_mfma(const p2o_plan_s* h, p2o_op op, int64_t nrhs) {
+  if (h->mfma_min_rhs[op] <= 0 || nrhs < h->mfma_min_rhs[op]) return false;
+  return h->prec == P2O_FP64 || h->prec == P2O_MIXED_BF16 || h->prec == P2O_FAST_BF16;
+}
+
+hipError_t launch_product(const p2o_plan_s* h, p2o_op op, void* a, void* b, void* c,
                           int64_t nrhs, int cfg, hipStream_t s) {
   GemvShape g{h->nf, h->Nd, h->Nm, nrhs, (int)h->n_pc, h->pc_len};
+  const bool mfma = use_mfma(h, op, nrhs);
   if (!is_mixed(h->prec)) {
     const auto* A = static_cast<const cpx<double>*>(h->fhat);
+    if (mfma) {
+      if (op == P2O_F)
+        return launch_gemm_rows_f64(A, static_cast<const cpx<double>*>(a),
+                                    static_cast<cpx<double>*>(b), g, s);
+      return launch_gemm_cols_f64(A, static_cast<const cpx<double>*>(a),
+                                  static_cast<cpx<double>*>(b), g, s);
+    }
     if (op == P2O_F)
       return launch_gemv_rows_f64(A, static_cast<const cpx<double>*>(a),
                                   static_cast<cpx<double>*>(b), g, cfg, s);
@@ -279,6 +301,18 @@ hipError_t launch_product(const p2o_plan_s* h, p2o_op op, void* a, void* b,
   }
   const Fmt16 fmt = fmt_of(h->prec);
   const bool lo = uses_lo(h->prec);
+  if (mfma) {
+    const int64_t nin = (op == P2O_F) ? h->Nm : h->Nd;
+    auto* planes = static_cast<uint16_t*>(c);
+    hipError_t e = launch_split_bf16(static_cast<const cpx<float>*>(a), planes, nrhs * h->nf,
+                                     nin, round8(nin), s);
+    if (e != hipSuccess) return e;
+    if (op == P2O_F)
+      return launch_gemm_rows_bf16(h->fhat, h->scales, planes, static_cast<cpx<double>*>(b),
+                                   g, round8(nin), lo, s);
+    return launch_gemm_cols_bf16(h->fhat, h->scales, planes, static_cast<cpx<float>*>(b), g,
+                                 round8(nin), lo, s);
+  }
   if (op == P2O_F)
     return launch_gemv_rows_mixed(h->fhat, h->scales, static_cast<const cpx<float>*>(a),
                                   static_cast<cpx<double>*>(b), g, fmt, lo, cfg, s);
@@ -354,18 +388,15 @@ p2o_status timed_end(p2o_plan_s* h, p2o_op op, hipStream_t s) {
   return P2O_OK;
 }
 
-p2o_status apply_fp64(p2o_plan_s* h, p2o_op op, const double* x, double* y,
-                      int64_t nrhs, hipStream_t s, double out_scale = 1.0) {
+// Forward transform of x (float64, [nrhs][Nt][n_in]) into the workspace's
+// input-spectrum region (float64 or float32 by plan precision).
+hipError_t enqueue_forward(const p2o_plan_s* h, p2o_op op, const double* x, int64_t nrhs,
+                           hipStream_t s) {
   const WsLayout w = ws_layout(h, op, nrhs);
-  char* ws = static_cast<char*>(h->ws);
-  auto* a = reinterpret_cast<cpx<double>*>(ws + w.a_off);
-  auto* b = reinterpret_cast<cpx<double>*>(ws + w.b_off);
   const int64_t nin = (op == P2O_F) ? h->Nm : h->Nd;
-  const int64_t nout = (op == P2O_F) ? h->Nd : h->Nm;
-
   FftIo f{};
   f.in = x;
-  f.out = a;
+  f.out = static_cast<char*>(h->ws) + w.a_off;
   f.ncols = nin;
   f.in_row = nin;
   f.in_batch = h->Nt * nin;
@@ -373,14 +404,18 @@ p2o_status apply_fp64(p2o_plan_s* h, p2o_op op, const double* x, double* y,
   f.out_batch = h->nf * nin;
   f.nparts = 1;
   f.scale = 1.0;
-  TRY_HIP(launch_rfft_fwd_f64(h->fft, h->tw64, h->perm, f, nrhs, s));
+  if (!is_mixed(h->prec)) return launch_rfft_fwd_f64(h->fft, h->tw64, h->perm, f, nrhs, s);
+  return launch_rfft_fwd_f32(h->fft, h->tw32, h->perm, f, nrhs, s);
+}
 
-  TRY_ST(timed_begin(h, op, s));
-  TRY_HIP(launch_product(h, op, a, b, nrhs, h->cfg[op], s));
-  TRY_ST(timed_end(h, op, s));
-
+// Inverse transform of the product region into y ([nrhs][Nt][n_out]),
+// summing F's partial spectra, truncating to Nt steps, times out_scale.
+hipError_t enqueue_inverse(const p2o_plan_s* h, p2o_op op, double* y, int64_t nrhs,
+                           double out_scale, hipStream_t s) {
+  const WsLayout w = ws_layout(h, op, nrhs);
+  const int64_t nout = (op == P2O_F) ? h->Nd : h->Nm;
   FftIo v{};
-  v.in = b;
+  v.in = static_cast<char*>(h->ws) + w.b_off;
   v.out = y;
   v.ncols = nout;
   v.in_row = nout;
@@ -390,57 +425,20 @@ p2o_status apply_fp64(p2o_plan_s* h, p2o_op op, const double* x, double* y,
   v.out_row = nout;
   v.out_batch = h->Nt * nout;
   v.scale = out_scale / (double)h->L;
-  TRY_HIP(launch_rfft_inv_f64(h->fft, h->tw64, h->perm, v, nrhs, s));
-  return P2O_OK;
+  if (!is_mixed(h->prec)) return launch_rfft_inv_f64(h->fft, h->tw64, h->perm, v, nrhs, s);
+  // F's partial spectra are float64 (combined in float64); F*'s product is float32
+  return launch_rfft_inv_f32(h->fft, h->tw32, h->perm, v, op == P2O_F, nrhs, s);
 }
 
-p2o_status apply_mixed(p2o_plan_s* h, p2o_op op, const double* x, double* y,
-                       int64_t nrhs, hipStream_t s) {
+p2o_status apply_impl(p2o_plan_s* h, p2o_op op, const double* x, double* y, int64_t nrhs,
+                      hipStream_t s, double out_scale = 1.0) {
   const WsLayout w = ws_layout(h, op, nrhs);
   char* ws = static_cast<char*>(h->ws);
-  auto* a = reinterpret_cast<cpx<float>*>(ws + w.a_off);
-  const int64_t nin = (op == P2O_F) ? h->Nm : h->Nd;
-  const int64_t nout = (op == P2O_F) ? h->Nd : h->Nm;
-
-  FftIo f{};
-  f.in = x;
-  f.out = a;
-  f.ncols = nin;
-  f.in_row = nin;
-  f.in_batch = h->Nt * nin;
-  f.out_row = nin;
-  f.out_batch = h->nf * nin;
-  f.nparts = 1;
-  f.scale = 1.0;
-  TRY_HIP(launch_rfft_fwd_f32(h->fft, h->tw32, h->perm, f, nrhs, s));
-
-  FftIo v{};
-  v.out = y;
-  v.ncols = nout;
-  v.in_row = nout;
-  v.out_row = nout;
-  v.out_batch = h->Nt * nout;
-  v.scale = 1.0 / (double)h->L;
+  TRY_HIP(enqueue_forward(h, op, x, nrhs, s));
   TRY_ST(timed_begin(h, op, s));
-  if (op == P2O_F) {
-    auto* parts = reinterpret_cast<cpx<double>*>(ws + w.b_off);
-    TRY_HIP(launch_product(h, op, a, parts, nrhs, h->cfg[op], s));
-    TRY_ST(timed_end(h, op, s));
-    v.in = parts;
-    v.nparts = (int)h->n_pc;
-    v.part_stride = h->nf * nout;
-    v.in_batch = (int64_t)v.nparts * h->nf * nout;
-    TRY_HIP(launch_rfft_inv_f32(h->fft, h->tw32, h->perm, v, true, nrhs, s));
-  } else {
-    auto* prod = reinterpret_cast<cpx<float>*>(ws + w.b_off);
-    TRY_HIP(launch_product(h, op, a, prod, nrhs, h->cfg[op], s));
-    TRY_ST(timed_end(h, op, s));
-    v.in = prod;
-    v.nparts = 1;
-    v.part_stride = 0;
-    v.in_batch = h->nf * nout;
-    TRY_HIP(launch_rfft_inv_f32(h->fft, h->tw32, h->perm, v, false, nrhs, s));
-  }
+  TRY_HIP(launch_product(h, op, ws + w.a_off, ws + w.b_off, ws + w.c_off, nrhs, h->cfg[op], s));
+  TRY_ST(timed_end(h, op, s));
+  TRY_HIP(enqueue_inverse(h, op, y, nrhs, out_scale, s));
   return P2O_OK;
 }
 
@@ -527,8 +525,7 @@ p2o_status p2o_apply(p2o_handle h, p2o_op op, const double* x, double* y,
   (void)hipGetLastError();  // launch checks below must see only our errors
   TRY_ST(ensure_ws(h, nrhs));
   hipStream_t s = (hipStream_t)stream;
-  if (!is_mixed(h->prec)) return apply_fp64(h, op, x, y, nrhs, s);
-  return apply_mixed(h, op, x, y, nrhs, s);
+  return apply_impl(h, op, x, y, nrhs, s);
 }
 
 void p2o_destroy(p2o_handle h) { free_plan(h); }
@@ -593,6 +590,12 @@ p2o_status p2o_set_config(p2o_handle h, p2o_op op, int64_t cfg) {
   return P2O_OK;
 }
 
+p2o_status p2o_set_mfma_threshold(p2o_handle h, p2o_op op, int64_t min_rhs) {
+  if (!h || (op != P2O_F && op != P2O_FADJ)) return P2O_EINVAL;
+  h->mfma_min_rhs[op] = min_rhs;
+  return P2O_OK;
+}
+
 p2o_status p2o_autotune(p2o_handle h, p2o_op op, int reps, double* times_ms,
                         int64_t max_times, int64_t* chosen, void* stream) {
   if (!h || (op != P2O_F && op != P2O_FADJ) || reps < 1 || max_times < 0 ||
@@ -615,10 +618,10 @@ p2o_status p2o_autotune(p2o_handle h, p2o_op op, int reps, double* times_ms,
   for (int c = 0; c < n && err == hipSuccess; ++c) {
     float ms = -1.f;
     if (cfg_valid(h, op, c)) {
-      err = launch_product(h, op, ws + w.a_off, ws + w.b_off, 1, c, s);  // warm-up
+      err = launch_product(h, op, ws + w.a_off, ws + w.b_off, ws + w.c_off, 1, c, s);  // warm-up
       if (err == hipSuccess) err = hipEventRecord(e0, s);
       for (int r = 0; r < reps && err == hipSuccess; ++r)
-        err = launch_product(h, op, ws + w.a_off, ws + w.b_off, 1, c, s);
+        err = launch_product(h, op, ws + w.a_off, ws + w.b_off, ws + w.c_off, 1, c, s);
       if (err == hipSuccess) err = hipEventRecord(e1, s);
       if (err == hipSuccess) err = hipEventSynchronize(e1);
       if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
@@ -715,7 +718,7 @@ p2o_status p2o_hessian_assemble(p2o_handle h, double prior_var,
     fwd.nparts = 1;
     fwd.scale = 1.0;
     TRY_HIP(launch_rfft_fwd_f64(h->fft, h->tw64, h->perm, fwd, nb, s));
-    TRY_HIP(launch_product(h, P2O_F, xh, parts, nb, h->cfg[P2O_F], s));
+    TRY_HIP(launch_product(h, P2O_F, xh, parts, nullptr, nb, h->cfg[P2O_F], s));
     FftIo out{};
     out.in = parts;
     out.out = K + j0 * n;
@@ -778,9 +781,187 @@ p2o_status p2o_posterior_solve(p2o_handle h, double* K, const double* d,
     TRY_HIP(launch_axpy(X, Rr, 1.0, nrhs * n, s));
   }
   TRY_ST(ensure_ws(h, nrhs));
-  TRY_ST(apply_fp64(h, P2O_FADJ, X, m_out, nrhs, s, prior_var));
+  TRY_ST(apply_impl(h, P2O_FADJ, X, m_out, nrhs, s, prior_var));
   TRY_HIP(hipStreamSynchronize(s));
   return P2O_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------ batched instances
+struct p2o_batch_s {
+  std::vector<p2o_handle> plans;
+  BatchClass cls = kClassF64;
+  BatchInst* dev = nullptr;  // work table of the last p2o_batch_apply
+};
+
+struct p2o_graph_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  BatchInst* dev = nullptr;  // work table the captured launch reads
+};
+
+namespace {
+
+BatchClass class_of(p2o_prec p) {
+  switch (p) {
+    case P2O_FP64: return kClassF64;
+    case P2O_MIXED_FP16: return kClassMixedFp16;
+    case P2O_MIXED_BF16: return kClassMixedBf16;
+    case P2O_FAST_BF16: return kClassFastBf16;
+  }
+  return kClassF64;
+}
+
+// Validate the per-instance arguments, reserve workspaces and build the
+// work table (host copy) for one batched apply.
+p2o_status batch_prepare(p2o_batch b, p2o_op op, const double* const* x, double* const* y,
+                         const int64_t* nrhs, std::vector<BatchInst>* table, int64_t* total) {
+  if (!b || !x || !y || !nrhs || (op != P2O_F && op != P2O_FADJ)) return P2O_EINVAL;
+  const size_t n = b->plans.size();
+  table->assign(n, BatchInst{});
+  int64_t units = 0;
+  for (size_t i = 0; i < n; ++i) {
+    p2o_plan_s* h = b->plans[i];
+    if (!x[i] || !y[i] || nrhs[i] < 1 || nrhs[i] > 65535) return P2O_EINVAL;
+    TRY_ST(ensure_ws(h, nrhs[i]));
+    const WsLayout w = ws_layout(h, op, nrhs[i]);
+    char* ws = static_cast<char*>(h->ws);
+    const bool matrix = use_mfma(h, op, nrhs[i]) && h->prec != P2O_MIXED_FP16;
+    BatchInst& I = (*table)[i];
+    I.fhat = h->fhat;
+    I.scales = h->scales;
+    I.in = ws + ((matrix && is_mixed(h->prec)) ? w.c_off : w.a_off);
+    I.out = ws + w.b_off;
+    I.g = GemvShape{h->nf, h->Nd, h->Nm, nrhs[i], (int)h->n_pc, h->pc_len};
+    I.n8 = round8(op == P2O_F ? h->Nm : h->Nd);
+    I.path = matrix ? kPathMatrix : kPathVector;
+    I.unit_begin = units;
+    units += batch_units(b->cls, op, I.path, I.g);
+  }
+  *total = units;
+  return P2O_OK;
+}
+
+// Enqueue one batched apply whose work table is already on the device:
+// every instance's forward transform (and bfloat16 operand split), one
+// persistent product launch, every instance's inverse transform.
+p2o_status batch_enqueue(p2o_batch b, p2o_op op, const double* const* x, double* const* y,
+                         const int64_t* nrhs, const std::vector<BatchInst>& table,
+                         const BatchInst* dev_table, int64_t total, hipStream_t s) {
+  const size_t n = b->plans.size();
+  for (size_t i = 0; i < n; ++i) TRY_HIP(enqueue_forward(b->plans[i], op, x[i], nrhs[i], s));
+  for (size_t i = 0; i < n; ++i) {
+    p2o_plan_s* h = b->plans[i];
+    if (table[i].path == kPathMatrix && is_mixed(h->prec)) {
+      const WsLayout w = ws_layout(h, op, nrhs[i]);
+      char* ws = static_cast<char*>(h->ws);
+      const int64_t nin = (op == P2O_F) ? h->Nm : h->Nd;
+      TRY_HIP(launch_split_bf16(reinterpret_cast<const cpx<float>*>(ws + w.a_off),
+                                reinterpret_cast<uint16_t*>(ws + w.c_off), nrhs[i] * h->nf, nin,
+                                round8(nin), s));
+    }
+  }
+  TRY_HIP(launch_batch_product(b->cls, op, dev_table, (int)n, total, s));
+  for (size_t i = 0; i < n; ++i) TRY_HIP(enqueue_inverse(b->plans[i], op, y[i], nrhs[i], 1.0, s));
+  return P2O_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+p2o_status p2o_batch_create(const p2o_handle* plans, int64_t n, p2o_batch* out) {
+  if (!out) return P2O_EINVAL;
+  *out = nullptr;
+  if (!plans || n < 1 || n > (1 << 20)) return P2O_EINVAL;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!plans[i]) return P2O_EINVAL;
+    if (!plans[i]->ready) return P2O_ESTATE;
+    if (plans[i]->prec != plans[0]->prec || plans[i]->device != plans[0]->device)
+      return P2O_EINVAL;
+    for (int64_t j = 0; j < i; ++j)
+      if (plans[j] == plans[i]) return P2O_EINVAL;  // instances own their workspaces
+  }
+  auto* b = new (std::nothrow) p2o_batch_s;
+  if (!b) return P2O_ENOMEM;
+  b->plans.assign(plans, plans + n);
+  b->cls = class_of(plans[0]->prec);
+  const hipError_t e = hipMalloc((void**)&b->dev, sizeof(BatchInst) * n);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e);
+  }
+  *out = b;
+  return P2O_OK;
+}
+
+p2o_status p2o_batch_apply(p2o_batch b, p2o_op op, const double* const* x, double* const* y,
+                           const int64_t* nrhs, void* stream) {
+  (void)hipGetLastError();
+  std::vector<BatchInst> table;
+  int64_t total = 0;
+  TRY_ST(batch_prepare(b, op, x, y, nrhs, &table, &total));
+  hipStream_t s = (hipStream_t)stream;
+  TRY_HIP(hipStreamSynchronize(s));  // the previous apply has finished reading the table
+  TRY_HIP(hipMemcpy(b->dev, table.data(), sizeof(BatchInst) * table.size(), hipMemcpyHostToDevice));
+  return batch_enqueue(b, op, x, y, nrhs, table, b->dev, total, s);
+}
+
+p2o_status p2o_batch_capture(p2o_batch b, p2o_op op, const double* const* x, double* const* y,
+                             const int64_t* nrhs, void* stream, p2o_graph* out) {
+  if (!out) return P2O_EINVAL;
+  *out = nullptr;
+  (void)hipGetLastError();
+  std::vector<BatchInst> table;
+  int64_t total = 0;
+  TRY_ST(batch_prepare(b, op, x, y, nrhs, &table, &total));
+  TRY_HIP(hipStreamSynchronize((hipStream_t)stream));
+  auto* g = new (std::nothrow) p2o_graph_s;
+  if (!g) return P2O_ENOMEM;
+  hipError_t e = hipMalloc((void**)&g->dev, sizeof(BatchInst) * table.size());
+  if (e == hipSuccess)
+    e = hipMemcpy(g->dev, table.data(), sizeof(BatchInst) * table.size(), hipMemcpyHostToDevice);
+  hipStream_t cs = nullptr;
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  p2o_status st = P2O_OK;
+  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    st = batch_enqueue(b, op, x, y, nrhs, table, g->dev, total, cs);
+    const hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
+    if (st == P2O_OK && e2 != hipSuccess) e = e2;
+  }
+  if (e == hipSuccess && st == P2O_OK) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (cs) (void)hipStreamDestroy(cs);
+  if (e != hipSuccess || st != P2O_OK) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    (void)hipFree(g->dev);
+    delete g;
+    return st != P2O_OK ? st : hip_fail(e);
+  }
+  *out = g;
+  return P2O_OK;
+}
+
+p2o_status p2o_graph_launch(p2o_graph g, void* stream) {
+  if (!g) return P2O_EINVAL;
+  TRY_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return P2O_OK;
+}
+
+void p2o_graph_destroy(p2o_graph g) {
+  if (!g) return;
+  (void)hipGraphExecDestroy(g->exec);
+  (void)hipGraphDestroy(g->graph);
+  (void)hipFree(g->dev);
+  delete g;
+}
+
+void p2o_batch_destroy(p2o_batch b) {
+  if (!b) return;
+  (void)hipFree(b->dev);
+  delete b;
 }
 
 }  // extern "C"

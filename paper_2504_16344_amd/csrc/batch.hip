@@ -1,0 +1,201 @@
+// Persistent product kernel for a batch of independent p2o instances of
+// uneven shape (section "FFT-based Hessian matvecs": every instance is its
+// own block-diagonal Fourier-space product).  One launch covers the
+// frequency-block products of every instance: the units of all instances
+// are numbered consecutively, each wavefront takes units w, w + W, w + 2W,
+// ... (W = wavefronts in the grid, sized to the chip's resident capacity),
+// finds the owning instance by binary search over the instances' first
+// units, and runs that instance's path — the vector-unit kernel for few
+// right-hand sides, the matrix-core kernel for many — through the same
+// wave-level code as the single-plan kernels.  Interleaving keeps every
+// wavefront's mix of large and small instances alike, and neighbouring
+// wavefronts on neighbouring tiles of one instance, which share the vector
+// operand in L2.
+#include "product_units.h"
+
+namespace p2o {
+namespace {
+
+constexpr int kRowsV = 4;   // vector-unit rows per wavefront (F)
+constexpr int kColsV = 2;   // vector-unit column groups per wavefront (F*)
+
+template <int CLS>
+struct ClassTraits;
+template <>
+struct ClassTraits<kClassMixedFp16> { static constexpr Fmt16 fmt = Fmt16::FP16; static constexpr bool lo = true; };
+template <>
+struct ClassTraits<kClassMixedBf16> { static constexpr Fmt16 fmt = Fmt16::BF16; static constexpr bool lo = true; };
+template <>
+struct ClassTraits<kClassFastBf16> { static constexpr Fmt16 fmt = Fmt16::BF16; static constexpr bool lo = false; };
+
+template <int CLS>
+__device__ __forceinline__ void rows_unit(const BatchInst& I, int64_t u) {
+  const GemvShape& g = I.g;
+  if (I.path == kPathMatrix) {
+    const int64_t nmt = (g.Nd + 15) / 16, rest = u / nmt;
+    const int64_t mt = u % nmt, k = rest % g.nf, pc = rest / g.nf;
+    for (int64_t b0 = 0; b0 < g.nrhs; b0 += 64) {
+      const int nb = (int)min((int64_t)64, g.nrhs - b0);
+      if constexpr (CLS == kClassF64) {
+        const auto* A = static_cast<const cpx<double>*>(I.fhat);
+        const auto* X = static_cast<const cpx<double>*>(I.in);
+        auto* P = static_cast<cpx<double>*>(I.out);
+        if (nb > 32) mfma_rows_f64_unit<4>(A, X, P, g, b0, nb, k, mt, pc);
+        else if (nb > 16) mfma_rows_f64_unit<2>(A, X, P, g, b0, nb, k, mt, pc);
+        else mfma_rows_f64_unit<1>(A, X, P, g, b0, nb, k, mt, pc);
+      } else if constexpr (CLS == kClassMixedBf16 || CLS == kClassFastBf16) {
+        constexpr bool LO = ClassTraits<CLS>::lo;
+        const auto* A = static_cast<const uint32_t*>(I.fhat);
+        const auto* X = static_cast<const uint16_t*>(I.in);
+        auto* P = static_cast<cpx<double>*>(I.out);
+        const bool vec = LO ? (g.Nm % 2 == 0) : (g.Nm % 4 == 0);
+        if (vec) {
+          if (nb > 32) mfma_rows_bf16_unit<4, LO, true>(A, I.scales, X, P, g, I.n8, b0, nb, k, mt, pc);
+          else if (nb > 16) mfma_rows_bf16_unit<2, LO, true>(A, I.scales, X, P, g, I.n8, b0, nb, k, mt, pc);
+          else mfma_rows_bf16_unit<1, LO, true>(A, I.scales, X, P, g, I.n8, b0, nb, k, mt, pc);
+        } else {
+          if (nb > 32) mfma_rows_bf16_unit<4, LO, false>(A, I.scales, X, P, g, I.n8, b0, nb, k, mt, pc);
+          else if (nb > 16) mfma_rows_bf16_unit<2, LO, false>(A, I.scales, X, P, g, I.n8, b0, nb, k, mt, pc);
+          else mfma_rows_bf16_unit<1, LO, false>(A, I.scales, X, P, g, I.n8, b0, nb, k, mt, pc);
+        }
+      }
+    }
+    return;
+  }
+  const int64_t nsg = (g.Nd + kRowsV - 1) / kRowsV, rest = u / nsg;
+  const int64_t sg = u % nsg, k = rest % g.nf, pc = rest / g.nf;
+  if constexpr (CLS == kClassF64) {
+    const auto* A = static_cast<const cpx<double>*>(I.fhat);
+    const auto* X = static_cast<const cpx<double>*>(I.in);
+    auto* P = static_cast<cpx<double>*>(I.out);
+    for (int64_t b0 = 0; b0 < g.nrhs;) {
+      const int64_t left = g.nrhs - b0;
+      if (left >= 4) { rows_f64_unit<kRowsV, 4>(A, X, P, g, b0, 4, k, sg, pc); b0 += 4; }
+      else if (left >= 2) { rows_f64_unit<kRowsV, 2>(A, X, P, g, b0, 2, k, sg, pc); b0 += 2; }
+      else { rows_f64_unit<kRowsV, 1>(A, X, P, g, b0, 1, k, sg, pc); b0 += 1; }
+    }
+  } else {
+    constexpr Fmt16 FMT = ClassTraits<CLS>::fmt;
+    constexpr bool LO = ClassTraits<CLS>::lo;
+    for (int64_t b = 0; b < g.nrhs; ++b)
+      rows_mixed_unit<kRowsV, 1, FMT, LO>(I.fhat, I.scales, static_cast<const cpx<float>*>(I.in),
+                                          static_cast<cpx<double>*>(I.out), g, b, k, sg, pc);
+  }
+}
+
+template <int CLS>
+__device__ __forceinline__ void cols_unit(const BatchInst& I, int64_t u) {
+  const GemvShape& g = I.g;
+  if (I.path == kPathMatrix) {
+    const int64_t npt = (g.Nm + 15) / 16;
+    const int64_t pt = u % npt, k = u / npt;
+    for (int64_t b0 = 0; b0 < g.nrhs; b0 += 64) {
+      const int nb = (int)min((int64_t)64, g.nrhs - b0);
+      if constexpr (CLS == kClassF64) {
+        const auto* A = static_cast<const cpx<double>*>(I.fhat);
+        const auto* D = static_cast<const cpx<double>*>(I.in);
+        auto* Y = static_cast<cpx<double>*>(I.out);
+        if (nb > 32) mfma_cols_f64_unit<4>(A, D, Y, g, b0, nb, k, pt);
+        else if (nb > 16) mfma_cols_f64_unit<2>(A, D, Y, g, b0, nb, k, pt);
+        else mfma_cols_f64_unit<1>(A, D, Y, g, b0, nb, k, pt);
+      } else if constexpr (CLS == kClassMixedBf16 || CLS == kClassFastBf16) {
+        constexpr bool LO = ClassTraits<CLS>::lo;
+        const auto* A = static_cast<const uint32_t*>(I.fhat);
+        const auto* D = static_cast<const uint16_t*>(I.in);
+        auto* Y = static_cast<cpx<float>*>(I.out);
+        if (nb > 32) mfma_cols_bf16_unit<4, LO>(A, I.scales, D, Y, g, I.n8, b0, nb, k, pt);
+        else if (nb > 16) mfma_cols_bf16_unit<2, LO>(A, I.scales, D, Y, g, I.n8, b0, nb, k, pt);
+        else mfma_cols_bf16_unit<1, LO>(A, I.scales, D, Y, g, I.n8, b0, nb, k, pt);
+      }
+    }
+    return;
+  }
+  if constexpr (CLS == kClassF64) {
+    const int64_t npg = (g.Nm + 64 * kColsV - 1) / (64 * kColsV);
+    const int64_t pg = u % npg, k = u / npg;
+    const auto* A = static_cast<const cpx<double>*>(I.fhat);
+    const auto* D = static_cast<const cpx<double>*>(I.in);
+    auto* Y = static_cast<cpx<double>*>(I.out);
+    for (int64_t b0 = 0; b0 < g.nrhs;) {
+      const int64_t left = g.nrhs - b0;
+      if (left >= 4) { cols_f64_unit<kColsV, 4>(A, D, Y, g, b0, 4, k, pg); b0 += 4; }
+      else if (left >= 2) { cols_f64_unit<kColsV, 2>(A, D, Y, g, b0, 2, k, pg); b0 += 2; }
+      else { cols_f64_unit<kColsV, 1>(A, D, Y, g, b0, 1, k, pg); b0 += 1; }
+    }
+  } else {
+    constexpr Fmt16 FMT = ClassTraits<CLS>::fmt;
+    constexpr bool LO = ClassTraits<CLS>::lo;
+    const int64_t npg = (g.Nm + 64 * kColsV - 1) / (64 * kColsV);
+    const int64_t pg = u % npg, k = u / npg;
+    for (int64_t b = 0; b < g.nrhs; ++b)
+      cols_mixed_unit<kColsV, 1, FMT, LO>(I.fhat, I.scales, static_cast<const cpx<float>*>(I.in),
+                                          static_cast<cpx<float>*>(I.out), g, b, k, pg);
+  }
+}
+
+template <int CLS, int OP>
+__global__ void __launch_bounds__(256)
+batch_product_kernel(const BatchInst* __restrict__ insts, int n, int64_t total) {
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  for (int64_t u = (int64_t)blockIdx.x * 4 + wave_id_in_block(); u < total; u += nwaves) {
+    int lo = 0, hi = n - 1;  // last instance with unit_begin <= u
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (insts[mid].unit_begin <= u) lo = mid;
+      else hi = mid - 1;
+    }
+    const BatchInst I = insts[lo];
+    if constexpr (OP == P2O_F) rows_unit<CLS>(I, u - I.unit_begin);
+    else cols_unit<CLS>(I, u - I.unit_begin);
+  }
+}
+
+template <int CLS, int OP>
+hipError_t launch_one(const BatchInst* insts, int n, int64_t total, hipStream_t s) {
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_product_kernel<CLS, OP>, 256, 0);
+  if (e != hipSuccess) return e;
+  int64_t blocks = (int64_t)std::max(1, cus) * std::max(1, per_cu);
+  blocks = std::min<int64_t>(blocks, (total + 3) / 4);
+  if (blocks < 1) return hipSuccess;
+  hipLaunchKernelGGL((batch_product_kernel<CLS, OP>), dim3((unsigned)blocks), dim3(256), 0, s,
+                     insts, n, total);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int64_t batch_units(BatchClass cls, p2o_op op, int path, const GemvShape& g) {
+  (void)cls;
+  if (op == P2O_F) {
+    const int64_t tile = path == kPathMatrix ? 16 : kRowsV;
+    return g.nf * ((g.Nd + tile - 1) / tile) * g.n_pc;
+  }
+  const int64_t cols = path == kPathMatrix ? 16 : 64 * kColsV;
+  return g.nf * ((g.Nm + cols - 1) / cols);
+}
+
+hipError_t launch_batch_product(BatchClass cls, p2o_op op, const BatchInst* insts, int n,
+                                int64_t total_units, hipStream_t s) {
+  const bool f = op == P2O_F;
+  switch (cls) {
+    case kClassF64:
+      return f ? launch_one<kClassF64, P2O_F>(insts, n, total_units, s)
+               : launch_one<kClassF64, P2O_FADJ>(insts, n, total_units, s);
+    case kClassMixedFp16:
+      return f ? launch_one<kClassMixedFp16, P2O_F>(insts, n, total_units, s)
+               : launch_one<kClassMixedFp16, P2O_FADJ>(insts, n, total_units, s);
+    case kClassMixedBf16:
+      return f ? launch_one<kClassMixedBf16, P2O_F>(insts, n, total_units, s)
+               : launch_one<kClassMixedBf16, P2O_FADJ>(insts, n, total_units, s);
+    case kClassFastBf16:
+      return f ? launch_one<kClassFastBf16, P2O_F>(insts, n, total_units, s)
+               : launch_one<kClassFastBf16, P2O_FADJ>(insts, n, total_units, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace p2o

@@ -115,6 +115,50 @@ hipError_t launch_quantise(const cpx<double>* chunk, int64_t nf, int64_t Nd,
                            float* scales, Fmt16 fmt, bool use_lo,
                            hipStream_t s);
 
+// Many right-hand sides on the float64 matrix cores (same operands and
+// outputs as the row / column kernels above, all nrhs in passes of 64).
+hipError_t launch_gemm_rows_f64(const cpx<double>* A, const cpx<double>* X,
+                                cpx<double>* P, const GemvShape& g, hipStream_t s);
+hipError_t launch_gemm_cols_f64(const cpx<double>* A, const cpx<double>* D,
+                                cpx<double>* Y, const GemvShape& g, hipStream_t s);
+
+// Many right-hand sides on the bfloat16 matrix cores (bfloat16 block
+// storage).  Vector operands are pre-split by launch_split_bf16 into four
+// bfloat16 planes per (rhs, k), each of n8 = roundup(n, 8) entries.
+hipError_t launch_split_bf16(const cpx<float>* in, uint16_t* out, int64_t count, int64_t n,
+                             int64_t n8, hipStream_t s);
+hipError_t launch_gemm_rows_bf16(const void* A, const float* scales, const uint16_t* Xs,
+                                 cpx<double>* P, const GemvShape& g, int64_t n8, bool lo,
+                                 hipStream_t s);
+hipError_t launch_gemm_cols_bf16(const void* A, const float* scales, const uint16_t* Ds,
+                                 cpx<float>* Y, const GemvShape& g, int64_t nd8, bool lo,
+                                 hipStream_t s);
+
+// ---------------------------------------------------- batched instances
+// One instance of a batched product: its frequency blocks, operands and
+// shape, the kernel path it takes, and its range of work units in the
+// batch (units are wavefront-sized pieces: a frequency and a tile of
+// sensors or columns, with all of the instance's right-hand sides).
+enum BatchPath : int { kPathVector = 0, kPathMatrix = 1 };
+enum BatchClass : int { kClassF64 = 0, kClassMixedFp16 = 1, kClassMixedBf16 = 2, kClassFastBf16 = 3 };
+
+struct BatchInst {
+  const void* fhat;
+  const float* scales;
+  const void* in;      // transformed input, or its bfloat16 planes (matrix path, mixed)
+  void* out;           // F: partial spectra, F*: transformed output
+  GemvShape g;
+  int64_t n8;          // bfloat16 plane pitch
+  int64_t unit_begin;  // first unit of this instance in the batch
+  int path;
+};
+
+int64_t batch_units(BatchClass cls, p2o_op op, int path, const GemvShape& g);
+// One persistent launch over all instances' units (instances sorted by
+// unit_begin, device array).
+hipError_t launch_batch_product(BatchClass cls, p2o_op op, const BatchInst* insts, int n,
+                                int64_t total_units, hipStream_t s);
+
 // ------------------------------------------------------- inversion kernels
 hipError_t launch_unit_adjoint_spectra(const cpx<double>* A, const cpx<double>* tw,
                                        cpx<double>* xh, int64_t nf, int64_t Nd,
@@ -150,6 +194,7 @@ struct p2o_plan_s {
   int64_t pc_len = 0;                // F product: columns per chunk
   int64_t cols_done = 0;             // setup progress
   int cfg[2] = {0, 0};               // product-kernel candidate per op
+  int64_t mfma_min_rhs[2] = {8, 8};  // from this many RHS on, matrix cores (set per precision at setup)
   bool ready = false;
   void* scratch = nullptr;           // setup chunk staging (mixed)
   size_t scratch_bytes = 0;

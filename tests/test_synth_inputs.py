@@ -31,3 +31,9 @@ def test_streams_differ_and_are_normal():
     for x in (a, b, c):
         assert abs(x.mean()) < 0.01 and abs(x.std() - 1) < 0.01
         assert abs(np.mean(x ** 4) - 3) < 0.1
+
+
+def test_uniform_ints_range_and_offsets():
+    a = S.uniform_ints(4, S.ARRAY_SHAPES, 3000, 50, 600)
+    assert a.min() >= 50 and a.max() <= 600 and len(set(a.tolist())) > 400
+    np.testing.assert_array_equal(S.uniform_ints(4, S.ARRAY_SHAPES, 10, 50, 600, offset=5), a[5:15])
