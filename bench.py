@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--budget-gb", type=float, default=200.0,
                     help="batch workload: device memory per wave of resident instances")
+    ap.add_argument("--no-inversion", action="store_true",
+                    help="skip the K-assembly / posterior-solve timing (100x5000x200)")
     ap.add_argument("--no-fp64-loop", action="store_true",
                     help="batch workload: skip the instance-by-instance float64 comparison")
     return ap.parse_args()
@@ -353,6 +355,45 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_inversion(torch, S, P):
+    """K = Gn + F Gp F* (20000 x 20000) and the posterior mean at the
+    100 x 5000 x 200 inversion workload: wall time of each call."""
+    Nd, Nm, Nt, seed = 100, 5000, 200, 5
+    stream = torch.cuda.current_stream()
+    env = torch.from_numpy(S.envelope(Nt, 40.0, 1.0 / np.sqrt(Nm))).cuda()
+    plan = make_plan(P, S, torch, "fp64", Nd, Nm, Nt, env, seed, stream)
+    n = Nt * Nd
+    m_true = torch.empty((Nt, Nm), dtype=torch.float64, device="cuda")
+    S.device_normals(m_true.data_ptr(), m_true.numel(), 0, seed, S.ARRAY_M, 1.0, stream.cuda_stream)
+    d_clean = plan.F(m_true)
+    s2 = 1e-2 * float((d_clean ** 2).mean())
+    eps = torch.empty_like(d_clean)
+    S.device_normals(eps.data_ptr(), eps.numel(), 0, seed, S.ARRAY_NOISE, 1.0, stream.cuda_stream)
+    d_obs = d_clean + (s2 ** 0.5) * eps
+    nv = torch.full((n,), s2, dtype=torch.float64, device="cuda")
+    K = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    plan.hessian(0.25, nv, out=K)  # warm-up (also allocates)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.hessian(0.25, nv, out=K)
+    torch.cuda.synchronize()
+    t_k = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    m = plan.posterior(K, d_obs, 0.25, refine_steps=1)
+    torch.cuda.synchronize()
+    t_m = time.perf_counter() - t0
+    # MAP optimality residual F* Gn^-1 (F m - d) + m / Gp, relative to m / Gp
+    g = plan.FT((plan.F(m) - d_obs) / s2) + m / 0.25
+    res = (torch.linalg.norm(g) / torch.linalg.norm(m / 0.25)).item()
+    plan.close()
+    del K
+    torch.cuda.empty_cache()
+    units = n
+    return {"workload": f"Nd={Nd} Nm={Nm} Nt={Nt}, K {n}x{n} float64",
+            "hessian_assemble_s": round(t_k, 3), "unit_vectors_per_s": round(units / t_k, 1),
+            "posterior_solve_s": round(t_m, 3), "map_gradient_rel": res}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -495,6 +536,9 @@ def main():
     }
     if "fp64" in results and head != "fp64":
         out["speedup_vs_fp64"] = round(results["fp64"]["ms_per_step"] / h["ms_per_step"], 3)
+    if not args.no_inversion:
+        out["inversion"] = bench_inversion(torch, S, P)
+        print(f"[bench] inversion: {out['inversion']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(torch, S, args, nf, h["step_bytes"], env)
     print(json.dumps(out), flush=True)

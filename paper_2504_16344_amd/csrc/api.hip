@@ -180,7 +180,6 @@ p2o_status begin_impl(int64_t Nd, int64_t Nm, int64_t Nt, p2o_prec prec,
   h->prec = prec;
   h->ntiles = (Nm + kScaleTile - 1) / kScaleTile;
   choose_chunks(h, &h->n_pc, &h->pc_len);
-  if (prec == P2O_FP64) h->mfma_min_rhs[0] = h->mfma_min_rhs[1] = 0;  // float64 MFMA off by default
   if (prec == P2O_MIXED_FP16) h->mfma_min_rhs[0] = h->mfma_min_rhs[1] = 0;
   hipError_t e = hipGetDevice(&h->device);
   if (e != hipSuccess) {

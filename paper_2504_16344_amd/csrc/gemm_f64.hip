@@ -4,9 +4,10 @@
 // vectors at once, so each frequency block is streamed once per 64
 // right-hand sides instead of once per vector.
 //
-// MFMA operand layout (16x16x4, float64): lane l supplies A[l % 16][l / 16]
-// and B[l / 16][l % 16]; accumulator element i of lane l is
-// D[4 (l / 16) + i][l % 16].  The contraction index of one instruction is
+// MFMA operand layout (16x16x4, float64, checked on the device): lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator element i
+// of lane l is D[(l / 16) + 4 i][l % 16] (rows interleave, unlike the
+// 16-bit 16x16 shapes, where it is D[4 (l / 16) + i][l % 16]).  The contraction index of one instruction is
 // mapped to the entries p = base + 8 (l / 16) + j of the j-th instruction of
 // a 32-entry chunk, for both operands, so every lane reads 8 consecutive
 // entries (128 contiguous bytes) and the sum over the chunk is unchanged.

@@ -404,7 +404,7 @@ __device__ __forceinline__ void mfma_rows_f64_unit(const cpx<double>* __restrict
     if (b >= nb) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int64_t s = mt * 16 + 4 * kg + i;
+      const int64_t s = mt * 16 + kg + 4 * i;  // float64 accumulator rows interleave
       if (s < g.Nd)
         P[(((b0 + b) * g.n_pc + pc) * g.nf + k) * g.Nd + s] = {accr[t][i], acci[t][i]};
     }
@@ -457,7 +457,7 @@ __device__ __forceinline__ void mfma_cols_f64_unit(const cpx<double>* __restrict
   for (int t = 0; t < MT; ++t)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int b = t * 16 + 4 * kg + i;
+      const int b = t * 16 + kg + 4 * i;  // float64 accumulator rows interleave
       if (b < nb) Y[((b0 + b) * g.nf + k) * g.Nm + p] = {accr[t][i], acci[t][i]};
     }
 }

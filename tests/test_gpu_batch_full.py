@@ -1,0 +1,85 @@
+"""The batched uneven-instance workload at its real sizes: the first five
+instances of the seeded 64-instance draw (Nt = 420, Nd in 50..600, Nm in
+1000..20000, 1..256 right-hand sides), set up from blocks generated on the
+device, applied in one batch (bf16 hi+lo, matrix cores where the RHS count
+calls for it) and checked on sampled outputs, each computed one by one by
+the oracle from block rows / columns the generator redraws on the host."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import p2o_synth as S
+import paper_2504_16344_amd as P
+
+pytestmark = pytest.mark.gpu
+
+SEED, NT, N_ALL, N_TEST = 4, 420, 64, 5
+
+
+def _plan(i, Nd, Nm, prec):
+    env_np = S.envelope(NT, 80.0, 1.0 / np.sqrt(Nm))
+    env = torch.from_numpy(env_np).cuda()
+    plan = P.Plan.begin(Nd, Nm, NT, prec)
+    stream = torch.cuda.current_stream()
+    for p0 in range(0, Nm, 2048):
+        p1 = min(Nm, p0 + 2048)
+        chunk = torch.empty((NT, Nd, p1 - p0), dtype=torch.float64, device="cuda")
+        S.device_blocks(chunk.data_ptr(), NT, Nd, Nm, p0, p1, 1000 * SEED + i, env.data_ptr(),
+                        stream.cuda_stream)
+        plan.setup_columns(chunk, p0, p1)
+    plan.setup_end()
+    return plan, env_np
+
+
+def test_batched_instances_full_size_sampled():
+    Nd = S.uniform_ints(SEED, S.ARRAY_SHAPES, N_ALL, 50, 600)[:N_TEST]
+    Nm = S.uniform_ints(SEED, S.ARRAY_SHAPES, N_ALL, 1000, 20000, offset=N_ALL)[:N_TEST]
+    R = S.uniform_ints(SEED, S.ARRAY_SHAPES, N_ALL, 1, 256, offset=2 * N_ALL)[:N_TEST]
+    stream = torch.cuda.current_stream()
+    plans, envs, ms, ds = [], [], [], []
+    for i in range(N_TEST):
+        print(f"\n[batch full] instance {i}: Nd={Nd[i]} Nm={Nm[i]} R={R[i]}", flush=True)
+        p, env = _plan(i, int(Nd[i]), int(Nm[i]), "mixed_bf16")
+        plans.append(p)
+        envs.append(env)
+        m = torch.empty((int(R[i]), NT, int(Nm[i])), dtype=torch.float64, device="cuda")
+        d = torch.empty((int(R[i]), NT, int(Nd[i])), dtype=torch.float64, device="cuda")
+        S.device_normals(m.data_ptr(), m.numel(), 0, 1000 * SEED + i, S.ARRAY_M, 1.0, stream.cuda_stream)
+        S.device_normals(d.data_ptr(), d.numel(), 0, 1000 * SEED + i, S.ARRAY_D, 1.0, stream.cuda_stream)
+        ms.append(m)
+        ds.append(d)
+    batch = P.Batch(plans)
+    yF = batch.apply(P.OP_F, ms)
+    yA = batch.apply(P.OP_FADJ, ds)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    worst = 0.0
+    for i in range(N_TEST):
+        nd, nm, r = int(Nd[i]), int(Nm[i]), int(R[i])
+        inst = 1000 * SEED + i
+        for _ in range(2):
+            b = int(rng.integers(r))
+            s, t = int(rng.integers(nd)), int(rng.integers(NT))
+            rows = S.blocks(inst, nd, nm, NT, envs[i], s=[s])[:, 0, :]
+            m_b = S.vector(inst, S.ARRAY_M, NT * nm, offset=b * NT * nm).reshape(NT, nm)
+            ref = oracle.F_entry(rows, m_b, t)
+            got = float(yF[i][b, t, s])
+            # scale: the size of the terms being summed
+            scale = np.sqrt(sum(float(rows[t - j] @ rows[t - j]) * float(m_b[j] @ m_b[j]) / nm
+                                for j in range(t + 1)))
+            err = abs(got - ref) / scale
+            worst = max(worst, err)
+            p = int(rng.integers(nm))
+            cols = S.blocks(inst, nd, nm, NT, envs[i], p=[p])[:, :, 0]
+            d_b = S.vector(inst, S.ARRAY_D, NT * nd, offset=b * NT * nd).reshape(NT, nd)
+            refa = oracle.Fadj_entry(cols, d_b, t)
+            gota = float(yA[i][b, t, p])
+            scalea = np.sqrt(sum(float(cols[k] @ cols[k]) for k in range(NT - t)) * nd / nd)
+            erra = abs(gota - refa) / scalea
+            worst = max(worst, erra)
+            print(f"  inst {i} rhs {b}: F[{t},{s}] err {err:.2e}  F*[{t},{p}] err {erra:.2e}", flush=True)
+    assert worst <= 1e-5
+    batch.close()
+    for p in plans:
+        p.close()

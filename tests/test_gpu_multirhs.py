@@ -16,8 +16,6 @@ SHAPES = [(1, 1, 1, 1), (37, 300, 13, 5), (17, 1000, 97, 20), (130, 1028, 33, 70
           (600, 96, 420, 3), (100, 777, 40, 33)]
 
 
-@pytest.mark.skip(reason="float64 MFMA lane layout did not match the assumed one on the device; "
-                         "the float64 matrix-core path is off by default until it is corrected")
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
 def test_mfma_and_vector_paths_match_oracle(shape):
     Nd, Nm, Nt, nrhs = shape
