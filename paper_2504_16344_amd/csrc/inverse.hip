@@ -189,22 +189,26 @@ syrk_update(double* __restrict__ K, int64_t n, int64_t j0, int bs) {
 
 // ------------------------------------------------------ triangular solves
 // Y is [nrhs][n].  Forward: L y = b block by block.
-// Solve the diagonal block in place: y[j0:j0+bs] = L11^{-1} y[j0:j0+bs].
+// Solve the diagonal block in place, y[j0:j0+bs] = L11^{-1} y[j0:j0+bs]:
+// lane i holds row i; at step c lane c finishes y_c, which is broadcast and
+// removed from the rows below it (column-oriented substitution).
 __global__ void __launch_bounds__(64)
 trsv_lower_diag(const double* __restrict__ K, double* __restrict__ Y, int64_t n,
                 int64_t nrhs, int64_t j0, int bs) {
   __shared__ double l[kNb][kNb + 1];
-  const int tid = threadIdx.x;
+  const int lane = threadIdx.x;
   for (int i = 0; i < bs; ++i)
-    for (int j = tid; j < bs; j += 64) l[i][j] = (j <= i) ? K[(j0 + i) * n + j0 + j] : 0.0;
+    for (int j = lane; j < bs; j += 64) l[i][j] = (j <= i) ? K[(j0 + i) * n + j0 + j] : 0.0;
   __syncthreads();
-  for (int64_t r = tid; r < nrhs; r += 64) {
+  for (int64_t r = 0; r < nrhs; ++r) {
     double* y = Y + r * n + j0;
+    double v = (lane < bs) ? y[lane] : 0.0;
     for (int c = 0; c < bs; ++c) {
-      double s = y[c];
-      for (int t = 0; t < c; ++t) s -= l[c][t] * y[t];
-      y[c] = s / l[c][c];
+      const double yc = __shfl(v / l[c][c], c, 64);
+      if (lane == c) v = yc;
+      else if (lane > c) v -= l[lane][c] * yc;
     }
+    if (lane < bs) y[lane] = v;
   }
 }
 
@@ -248,24 +252,31 @@ trsv_upper_partial(const double* __restrict__ K, const double* __restrict__ Y,
   }
 }
 
+// Backward diagonal block: x = L11^{-T} (y - sum of the partials); lane c
+// holds unknown c; at step t lane t finishes x_t, which is broadcast and
+// removed from the unknowns above it.
 __global__ void __launch_bounds__(64)
 trsv_upper_diag(const double* __restrict__ K, double* __restrict__ Y,
                 const double* __restrict__ part, int nparts, int64_t n, int64_t nrhs,
                 int64_t j0, int bs) {
   __shared__ double l[kNb][kNb + 1];
-  const int tid = threadIdx.x;
+  const int lane = threadIdx.x;
   for (int i = 0; i < bs; ++i)
-    for (int j = tid; j < bs; j += 64) l[i][j] = (j <= i) ? K[(j0 + i) * n + j0 + j] : 0.0;
+    for (int j = lane; j < bs; j += 64) l[i][j] = (j <= i) ? K[(j0 + i) * n + j0 + j] : 0.0;
   __syncthreads();
-  for (int64_t r = tid; r < nrhs; r += 64) {
+  for (int64_t r = 0; r < nrhs; ++r) {
     double* y = Y + r * n + j0;
-    for (int w = 0; w < nparts; ++w)
-      for (int c = 0; c < bs; ++c) y[c] -= part[((int64_t)w * nrhs + r) * kNb + c];
-    for (int c = bs - 1; c >= 0; --c) {
-      double s = y[c];
-      for (int t = c + 1; t < bs; ++t) s -= l[t][c] * y[t];
-      y[c] = s / l[c][c];
+    double v = 0.0;
+    if (lane < bs) {
+      v = y[lane];
+      for (int w = 0; w < nparts; ++w) v -= part[((int64_t)w * nrhs + r) * kNb + lane];
     }
+    for (int t = bs - 1; t >= 0; --t) {
+      const double xt = __shfl(v / l[t][t], t, 64);
+      if (lane == t) v = xt;
+      else if (lane < t) v -= l[t][lane] * xt;
+    }
+    if (lane < bs) y[lane] = v;
   }
 }
 
