@@ -304,7 +304,8 @@ hipError_t launch_product(const p2o_plan_s* h, p2o_op op, void* a, void* b, void
     const int64_t nin = (op == P2O_F) ? h->Nm : h->Nd;
     auto* planes = static_cast<uint16_t*>(c);
     hipError_t e = launch_split_bf16(static_cast<const cpx<float>*>(a), planes, nrhs * h->nf,
-                                     nin, round8(nin), s);
+                                     nin, round8(nin), op == P2O_F ? h->scales : nullptr,
+                                     h->nf, s);
     if (e != hipSuccess) return e;
     if (op == P2O_F)
       return launch_gemm_rows_bf16(h->fhat, h->scales, planes, static_cast<cpx<double>*>(b),
@@ -858,7 +859,7 @@ p2o_status batch_enqueue(p2o_batch b, p2o_op op, const double* const* x, double*
       const int64_t nin = (op == P2O_F) ? h->Nm : h->Nd;
       TRY_HIP(launch_split_bf16(reinterpret_cast<const cpx<float>*>(ws + w.a_off),
                                 reinterpret_cast<uint16_t*>(ws + w.c_off), nrhs[i] * h->nf, nin,
-                                round8(nin), s));
+                                round8(nin), op == P2O_F ? h->scales : nullptr, h->nf, s));
     }
   }
   TRY_HIP(launch_batch_product(b->cls, op, dev_table, (int)n, total, s));

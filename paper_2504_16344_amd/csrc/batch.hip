@@ -1,16 +1,16 @@
 // Persistent product kernel for a batch of independent p2o instances of
 // uneven shape (section "FFT-based Hessian matvecs": every instance is its
 // own block-diagonal Fourier-space product).  One launch covers the
-// frequency-block products of every instance: the units of all instances
-// are numbered consecutively, each wavefront takes units w, w + W, w + 2W,
-// ... (W = wavefronts in the grid, sized to the chip's resident capacity),
-// finds the owning instance by binary search over the instances' first
-// units, and runs that instance's path — the vector-unit kernel for few
-// right-hand sides, the matrix-core kernel for many — through the same
-// wave-level code as the single-plan kernels.  Interleaving keeps every
-// wavefront's mix of large and small instances alike, and neighbouring
-// wavefronts on neighbouring tiles of one instance, which share the vector
-// operand in L2.
+// frequency-block products of every instance: the workgroup units of all
+// instances are numbered consecutively, each workgroup takes units w,
+// w + W, w + 2W, ... (W = workgroups in the grid, sized to the chip's
+// resident capacity), finds the owning instance by binary search over the
+// instances' first units, and runs that instance's path — four vector-unit
+// wavefront units for few right-hand sides, one matrix-core workgroup tile
+// for many — through the same code as the single-plan kernels.
+// Interleaving keeps every workgroup's mix of large and small instances
+// alike, and neighbouring workgroups on neighbouring tiles of one instance,
+// which share the vector operand in L2.
 #include "product_units.h"
 
 namespace p2o {
@@ -29,10 +29,21 @@ template <>
 struct ClassTraits<kClassFastBf16> { static constexpr Fmt16 fmt = Fmt16::BF16; static constexpr bool lo = false; };
 
 template <int CLS>
-__device__ __forceinline__ void rows_unit(const BatchInst& I, int64_t u) {
+constexpr int stage_bytes() {
+  return CLS == kClassF64 ? stage_bytes_f64(4) : (CLS == kClassMixedFp16 ? 16 : stage_bytes_bf16(4));
+}
+
+// Vector-path wave units of one instance (a workgroup unit is 4 of them).
+__device__ __forceinline__ int64_t vector_wave_units(p2o_op op, const GemvShape& g) {
+  if (op == P2O_F) return g.nf * ((g.Nd + kRowsV - 1) / kRowsV) * g.n_pc;
+  return g.nf * ((g.Nm + 64 * kColsV - 1) / (64 * kColsV));
+}
+
+template <int CLS>
+__device__ __forceinline__ void rows_unit(const BatchInst& I, int64_t u, void* lds) {
   const GemvShape& g = I.g;
   if (I.path == kPathMatrix) {
-    const int64_t nmt = (g.Nd + 15) / 16, rest = u / nmt;
+    const int64_t nmt = (g.Nd + kWgTile - 1) / kWgTile, rest = u / nmt;
     const int64_t mt = u % nmt, k = rest % g.nf, pc = rest / g.nf;
     for (int64_t b0 = 0; b0 < g.nrhs; b0 += 64) {
       const int nb = (int)min((int64_t)64, g.nrhs - b0);
@@ -40,9 +51,9 @@ __device__ __forceinline__ void rows_unit(const BatchInst& I, int64_t u) {
         const auto* A = static_cast<const cpx<double>*>(I.fhat);
         const auto* X = static_cast<const cpx<double>*>(I.in);
         auto* P = static_cast<cpx<double>*>(I.out);
-        if (nb > 32) mfma_rows_f64_unit<4>(A, X, P, g, b0, nb, k, mt, pc);
-        else if (nb > 16) mfma_rows_f64_unit<2>(A, X, P, g, b0, nb, k, mt, pc);
-        else mfma_rows_f64_unit<1>(A, X, P, g, b0, nb, k, mt, pc);
+        if (nb > 32) mfma_rows_f64_wg<4>(A, X, P, g, b0, nb, k, mt, pc, lds);
+        else if (nb > 16) mfma_rows_f64_wg<2>(A, X, P, g, b0, nb, k, mt, pc, lds);
+        else mfma_rows_f64_wg<1>(A, X, P, g, b0, nb, k, mt, pc, lds);
       } else if constexpr (CLS == kClassMixedBf16 || CLS == kClassFastBf16) {
         constexpr bool LO = ClassTraits<CLS>::lo;
         const auto* A = static_cast<const uint32_t*>(I.fhat);
@@ -50,20 +61,22 @@ __device__ __forceinline__ void rows_unit(const BatchInst& I, int64_t u) {
         auto* P = static_cast<cpx<double>*>(I.out);
         const bool vec = LO ? (g.Nm % 2 == 0) : (g.Nm % 4 == 0);
         if (vec) {
-          if (nb > 32) mfma_rows_bf16_unit<4, LO, true>(A, I.scales, X, P, g, I.n8, b0, nb, k, mt, pc);
-          else if (nb > 16) mfma_rows_bf16_unit<2, LO, true>(A, I.scales, X, P, g, I.n8, b0, nb, k, mt, pc);
-          else mfma_rows_bf16_unit<1, LO, true>(A, I.scales, X, P, g, I.n8, b0, nb, k, mt, pc);
+          if (nb > 32) mfma_rows_bf16_wg<4, LO, true>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
+          else if (nb > 16) mfma_rows_bf16_wg<2, LO, true>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
+          else mfma_rows_bf16_wg<1, LO, true>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
         } else {
-          if (nb > 32) mfma_rows_bf16_unit<4, LO, false>(A, I.scales, X, P, g, I.n8, b0, nb, k, mt, pc);
-          else if (nb > 16) mfma_rows_bf16_unit<2, LO, false>(A, I.scales, X, P, g, I.n8, b0, nb, k, mt, pc);
-          else mfma_rows_bf16_unit<1, LO, false>(A, I.scales, X, P, g, I.n8, b0, nb, k, mt, pc);
+          if (nb > 32) mfma_rows_bf16_wg<4, LO, false>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
+          else if (nb > 16) mfma_rows_bf16_wg<2, LO, false>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
+          else mfma_rows_bf16_wg<1, LO, false>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
         }
       }
     }
     return;
   }
-  const int64_t nsg = (g.Nd + kRowsV - 1) / kRowsV, rest = u / nsg;
-  const int64_t sg = u % nsg, k = rest % g.nf, pc = rest / g.nf;
+  const int64_t wu = u * 4 + wave_id_in_block();
+  if (wu >= vector_wave_units(P2O_F, g)) return;
+  const int64_t nsg = (g.Nd + kRowsV - 1) / kRowsV, rest = wu / nsg;
+  const int64_t sg = wu % nsg, k = rest % g.nf, pc = rest / g.nf;
   if constexpr (CLS == kClassF64) {
     const auto* A = static_cast<const cpx<double>*>(I.fhat);
     const auto* X = static_cast<const cpx<double>*>(I.in);
@@ -84,10 +97,10 @@ __device__ __forceinline__ void rows_unit(const BatchInst& I, int64_t u) {
 }
 
 template <int CLS>
-__device__ __forceinline__ void cols_unit(const BatchInst& I, int64_t u) {
+__device__ __forceinline__ void cols_unit(const BatchInst& I, int64_t u, void* lds) {
   const GemvShape& g = I.g;
   if (I.path == kPathMatrix) {
-    const int64_t npt = (g.Nm + 15) / 16;
+    const int64_t npt = (g.Nm + kWgTile - 1) / kWgTile;
     const int64_t pt = u % npt, k = u / npt;
     for (int64_t b0 = 0; b0 < g.nrhs; b0 += 64) {
       const int nb = (int)min((int64_t)64, g.nrhs - b0);
@@ -95,24 +108,26 @@ __device__ __forceinline__ void cols_unit(const BatchInst& I, int64_t u) {
         const auto* A = static_cast<const cpx<double>*>(I.fhat);
         const auto* D = static_cast<const cpx<double>*>(I.in);
         auto* Y = static_cast<cpx<double>*>(I.out);
-        if (nb > 32) mfma_cols_f64_unit<4>(A, D, Y, g, b0, nb, k, pt);
-        else if (nb > 16) mfma_cols_f64_unit<2>(A, D, Y, g, b0, nb, k, pt);
-        else mfma_cols_f64_unit<1>(A, D, Y, g, b0, nb, k, pt);
+        if (nb > 32) mfma_cols_f64_wg<4>(A, D, Y, g, b0, nb, k, pt, lds);
+        else if (nb > 16) mfma_cols_f64_wg<2>(A, D, Y, g, b0, nb, k, pt, lds);
+        else mfma_cols_f64_wg<1>(A, D, Y, g, b0, nb, k, pt, lds);
       } else if constexpr (CLS == kClassMixedBf16 || CLS == kClassFastBf16) {
         constexpr bool LO = ClassTraits<CLS>::lo;
         const auto* A = static_cast<const uint32_t*>(I.fhat);
         const auto* D = static_cast<const uint16_t*>(I.in);
         auto* Y = static_cast<cpx<float>*>(I.out);
-        if (nb > 32) mfma_cols_bf16_unit<4, LO>(A, I.scales, D, Y, g, I.n8, b0, nb, k, pt);
-        else if (nb > 16) mfma_cols_bf16_unit<2, LO>(A, I.scales, D, Y, g, I.n8, b0, nb, k, pt);
-        else mfma_cols_bf16_unit<1, LO>(A, I.scales, D, Y, g, I.n8, b0, nb, k, pt);
+        if (nb > 32) mfma_cols_bf16_wg<4, LO>(A, I.scales, D, Y, g, I.n8, b0, nb, k, pt, lds);
+        else if (nb > 16) mfma_cols_bf16_wg<2, LO>(A, I.scales, D, Y, g, I.n8, b0, nb, k, pt, lds);
+        else mfma_cols_bf16_wg<1, LO>(A, I.scales, D, Y, g, I.n8, b0, nb, k, pt, lds);
       }
     }
     return;
   }
+  const int64_t wu = u * 4 + wave_id_in_block();
+  if (wu >= vector_wave_units(P2O_FADJ, g)) return;
+  const int64_t npg = (g.Nm + 64 * kColsV - 1) / (64 * kColsV);
+  const int64_t pg = wu % npg, k = wu / npg;
   if constexpr (CLS == kClassF64) {
-    const int64_t npg = (g.Nm + 64 * kColsV - 1) / (64 * kColsV);
-    const int64_t pg = u % npg, k = u / npg;
     const auto* A = static_cast<const cpx<double>*>(I.fhat);
     const auto* D = static_cast<const cpx<double>*>(I.in);
     auto* Y = static_cast<cpx<double>*>(I.out);
@@ -125,19 +140,20 @@ __device__ __forceinline__ void cols_unit(const BatchInst& I, int64_t u) {
   } else {
     constexpr Fmt16 FMT = ClassTraits<CLS>::fmt;
     constexpr bool LO = ClassTraits<CLS>::lo;
-    const int64_t npg = (g.Nm + 64 * kColsV - 1) / (64 * kColsV);
-    const int64_t pg = u % npg, k = u / npg;
     for (int64_t b = 0; b < g.nrhs; ++b)
       cols_mixed_unit<kColsV, 1, FMT, LO>(I.fhat, I.scales, static_cast<const cpx<float>*>(I.in),
                                           static_cast<cpx<float>*>(I.out), g, b, k, pg);
   }
 }
 
+// The grid is a multiple of 8 workgroups; each XCD takes a contiguous range
+// of units per round, so neighbouring tiles of one instance share its L2.
 template <int CLS, int OP>
 __global__ void __launch_bounds__(256)
 batch_product_kernel(const BatchInst* __restrict__ insts, int n, int64_t total) {
-  const int64_t nwaves = (int64_t)gridDim.x * 4;
-  for (int64_t u = (int64_t)blockIdx.x * 4 + wave_id_in_block(); u < total; u += nwaves) {
+  __shared__ __align__(16) char lds[stage_bytes<CLS>()];
+  const int64_t grid = gridDim.x;
+  for (int64_t u = xcd_local_tile(blockIdx.x, grid); u < total; u += grid) {
     int lo = 0, hi = n - 1;  // last instance with unit_begin <= u
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -145,8 +161,8 @@ batch_product_kernel(const BatchInst* __restrict__ insts, int n, int64_t total) 
       else hi = mid - 1;
     }
     const BatchInst I = insts[lo];
-    if constexpr (OP == P2O_F) rows_unit<CLS>(I, u - I.unit_begin);
-    else cols_unit<CLS>(I, u - I.unit_begin);
+    if constexpr (OP == P2O_F) rows_unit<CLS>(I, u - I.unit_begin, lds);
+    else cols_unit<CLS>(I, u - I.unit_begin, lds);
   }
 }
 
@@ -159,8 +175,9 @@ hipError_t launch_one(const BatchInst* insts, int n, int64_t total, hipStream_t 
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_product_kernel<CLS, OP>, 256, 0);
   if (e != hipSuccess) return e;
   int64_t blocks = (int64_t)std::max(1, cus) * std::max(1, per_cu);
-  blocks = std::min<int64_t>(blocks, (total + 3) / 4);
+  blocks = std::min<int64_t>(blocks, total);
   if (blocks < 1) return hipSuccess;
+  blocks = (blocks + kXcds - 1) / kXcds * kXcds;
   hipLaunchKernelGGL((batch_product_kernel<CLS, OP>), dim3((unsigned)blocks), dim3(256), 0, s,
                      insts, n, total);
   return hipGetLastError();
@@ -170,12 +187,13 @@ hipError_t launch_one(const BatchInst* insts, int n, int64_t total, hipStream_t 
 
 int64_t batch_units(BatchClass cls, p2o_op op, int path, const GemvShape& g) {
   (void)cls;
-  if (op == P2O_F) {
-    const int64_t tile = path == kPathMatrix ? 16 : kRowsV;
-    return g.nf * ((g.Nd + tile - 1) / tile) * g.n_pc;
+  if (path == kPathMatrix) {
+    if (op == P2O_F) return g.nf * ((g.Nd + kWgTile - 1) / kWgTile) * g.n_pc;
+    return g.nf * ((g.Nm + kWgTile - 1) / kWgTile);
   }
-  const int64_t cols = path == kPathMatrix ? 16 : 64 * kColsV;
-  return g.nf * ((g.Nm + cols - 1) / cols);
+  const int64_t waves = op == P2O_F ? g.nf * ((g.Nd + kRowsV - 1) / kRowsV) * g.n_pc
+                                    : g.nf * ((g.Nm + 64 * kColsV - 1) / (64 * kColsV));
+  return (waves + 3) / 4;
 }
 
 hipError_t launch_batch_product(BatchClass cls, p2o_op op, const BatchInst* insts, int n,

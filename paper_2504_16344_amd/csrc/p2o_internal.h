@@ -125,8 +125,9 @@ hipError_t launch_gemm_cols_f64(const cpx<double>* A, const cpx<double>* D,
 // Many right-hand sides on the bfloat16 matrix cores (bfloat16 block
 // storage).  Vector operands are pre-split by launch_split_bf16 into four
 // bfloat16 planes per (rhs, k), each of n8 = roundup(n, 8) entries.
+// scales: F's column sub-block scales (folded into the planes) or nullptr.
 hipError_t launch_split_bf16(const cpx<float>* in, uint16_t* out, int64_t count, int64_t n,
-                             int64_t n8, hipStream_t s);
+                             int64_t n8, const float* scales, int64_t nf, hipStream_t s);
 hipError_t launch_gemm_rows_bf16(const void* A, const float* scales, const uint16_t* Xs,
                                  cpx<double>* P, const GemvShape& g, int64_t n8, bool lo,
                                  hipStream_t s);

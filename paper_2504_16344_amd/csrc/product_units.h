@@ -1,11 +1,11 @@
-// Wave-level bodies of the frequency-block product kernels (section
+// Bodies of the frequency-block product kernels (section
 // "FFT-based Hessian matvecs", item (iii): one complex block product per
-// frequency).  Every function here is executed by a whole 64-lane wavefront
-// with wave-uniform arguments naming one unit of work (frequency k, a tile
-// of sensors or columns, a column chunk, a range of right-hand sides); the
-// per-kernel launchers decode those from the grid, and the persistent
-// multi-instance kernel decodes them from its work ranges, so both run the
-// same code.  See gemv.hip, gemm_f64.hip and gemm_bf16.hip for the design
+// frequency).  The vector-unit functions are executed by one 64-lane
+// wavefront, the matrix-core functions by a whole 256-thread workgroup, with
+// uniform arguments naming one unit of work (frequency k, a tile of sensors
+// or columns, a column chunk, a range of right-hand sides); the per-kernel
+// launchers decode those from the grid, and the persistent multi-instance
+// kernel decodes them from its work ranges, so both run the same code.  See gemv.hip, gemm_f64.hip and gemm_bf16.hip for the design
 // of each family.
 #pragma once
 
@@ -356,47 +356,272 @@ __device__ __forceinline__ void cols_mixed_unit(const void* __restrict__ A,
   }
 }
 
-// --------------------------------------------------- matrix-core units, f64
+// ------------------------------------------------------ matrix-core units
+// Workgroup-cooperative: the 4 wavefronts of a 256-thread workgroup cover 64
+// rows (F) or 64 columns (F*) of one frequency and walk the contraction in
+// 32-entry chunks.  Each chunk of the vector operand (all right-hand sides
+// of the pass) is staged in LDS once per workgroup and read by all 4
+// wavefronts, so vector traffic per block byte is a quarter of what one
+// wavefront alone would fetch; block entries stream from HBM straight into
+// the matrix-core operands.  The loop is software-pipelined over a double
+// LDS buffer: a wavefront first issues the next chunk's vector loads, then
+// its block loads, then runs the current chunk's products, and only then
+// waits for the vector loads (which were issued first, so the block loads
+// stay in flight) to store them into the other buffer; one barrier per
+// chunk.  All wavefronts of the workgroup must call a unit together.
+constexpr int kWgTile = 64;  // rows (F) / columns (F*) per workgroup
+constexpr int kXcds = 8;
+
+// LDS bytes of the double stage buffer for 16 NT right-hand sides.
+__host__ __device__ constexpr int stage_bytes_f64(int nt) { return 2 * 32 * (16 * nt + 1) * 16; }
+__host__ __device__ constexpr int stage_bytes_bf16(int nt) { return 2 * 16 * (16 * nt + 1) * 16; }
+
+// Workgroups are handed to the 8 XCDs round-robin by workgroup index, and
+// each XCD has its own L2.  For a grid padded to a multiple of 8, this maps
+// the workgroup index so every XCD runs a contiguous range of tiles:
+// neighbouring tiles (same frequency, same vector chunks) then meet in one
+// L2 instead of being spread over all eight.
+__device__ __forceinline__ int64_t xcd_local_tile(int64_t bid, int64_t grid) {
+  return (bid % kXcds) * (grid / kXcds) + bid / kXcds;
+}
+
+// ---- vector-operand staging: global -> registers (issued early) -> LDS.
+// The loads fetch raw values from clamped, valid addresses; the stores
+// (which wait for the loads anyway) zero the positions past `end` or past
+// the nb right-hand sides of the pass, so nothing between the two has to
+// wait for the data.
+// float64 vectors: entries [base, base + 32) of vector rows b0 .. b0 + 16 NT - 1
+// (row b at src + ((b0 + b) nf + k) len), stored as s[entry * (16 NT + 1) + b].
 template <int NT>
-__device__ __forceinline__ void mfma_rows_f64_unit(const cpx<double>* __restrict__ A, const cpx<double>* __restrict__ X,
-              cpx<double>* __restrict__ P, GemvShape g, int64_t b0, int nb, int64_t k, int64_t mt, int64_t pc) {
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ void stage_f64_load(const cpx<double>* __restrict__ src, int64_t nf,
+                                               int64_t k, int64_t len, int64_t b0, int nb,
+                                               int64_t base, int64_t end,
+                                               cpx<double> (&v)[2 * NT]) {
+#pragma unroll
+  for (int i = 0; i < 2 * NT; ++i) {
+    const int e = threadIdx.x + 256 * i, ent = e & 31, b = e >> 5;
+    const bool ok = b < nb && base + ent < end;
+    v[i] = src[ok ? ((b0 + b) * nf + k) * len + base + ent : 0];
+  }
+}
+
+template <int NT>
+__device__ __forceinline__ void stage_f64_store(const cpx<double> (&v)[2 * NT], int nb,
+                                                int64_t base, int64_t end, cpx<double>* s) {
+  constexpr int PP = NT * 16 + 1;
+#pragma unroll
+  for (int i = 0; i < 2 * NT; ++i) {
+    const int e = threadIdx.x + 256 * i, ent = e & 31, b = e >> 5;
+    const bool ok = b < nb && base + ent < end;
+    s[ent * PP + b] = ok ? v[i] : cpx<double>{0, 0};
+  }
+}
+
+// bfloat16 planes: 8-entry parts of the 4 planes of each vector row.
+template <int NT>
+__device__ __forceinline__ void stage_planes_load(const uint16_t* __restrict__ planes,
+                                                  int64_t nf, int64_t k, int64_t n8, int64_t b0,
+                                                  int nb, int64_t base, int64_t end,
+                                                  u4v (&v)[NT]) {
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    const int part = e & 3, plane = (e >> 2) & 3, b = e >> 4;
+    const int64_t q = base + 8 * part;
+    const bool ok = b < nb && q < end;
+    v[i] = ld16(planes + (ok ? (((b0 + b) * nf + k) * 4 + plane) * n8 + q : 0));
+  }
+}
+
+__device__ __forceinline__ u4v stage_part(const u4v& v, int e, int nb, int64_t base,
+                                          int64_t end) {
+  const bool ok = (e >> 4) < nb && base + 8 * (e & 3) < end;
+  return ok ? v : (u4v){0, 0, 0, 0};
+}
+
+// F*'s layout: s[(plane * 4 + part) * (16 NT + 1) + b] holds sensors
+// base + 8 part .. + 7 of one plane.
+template <int NT>
+__device__ __forceinline__ void stage_planes_store_cols(const u4v (&v)[NT], int nb, int64_t base,
+                                                        int64_t end, u4v* s) {
+  constexpr int PP = NT * 16 + 1;
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    s[(((e >> 2) & 3) * 4 + (e & 3)) * PP + (e >> 4)] = stage_part(v[i], e, nb, base, end);
+  }
+}
+
+// Entry of matrix-core slot j (0..7) of lane group kg within a 32-entry
+// chunk, for F's bfloat16 products: the 4 lane groups of a row read one
+// contiguous 64-byte span per load (hi+lo entries are 8 bytes, hi-only 4).
+template <bool LO>
+__device__ __forceinline__ int row_slot_entry(int kg, int j) {
+  return LO ? 8 * (j >> 1) + 2 * kg + (j & 1) : 16 * (j >> 2) + 4 * kg + (j & 3);
+}
+
+// F's layout, slot order: s[(plane * 4 + kg) * (16 NT + 1) + b] holds the 8
+// values of slots 0..7 of lane group kg; each loaded part (8 consecutive
+// entries) is scattered as 4 pairs.
+template <int NT, bool LO>
+__device__ __forceinline__ void stage_planes_store_rows(const u4v (&v)[NT], int nb, int64_t base,
+                                                        int64_t end, u4v* s) {
+  constexpr int PP = NT * 16 + 1;
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    const int e = threadIdx.x + 256 * i;
+    const int part = e & 3, plane = (e >> 2) & 3, b = e >> 4;
+    const u4v x = stage_part(v[i], e, nb, base, end);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {  // pair of chunk entries o, o + 1
+      const int o = 8 * part + 2 * u;
+      const int kgd = LO ? u : (o & 15) >> 2;
+      const int w = LO ? part : 2 * (o >> 4) + ((o & 3) >> 1);
+      reinterpret_cast<uint32_t*>(s + (plane * 4 + kgd) * PP + b)[w] = x[u];
+    }
+  }
+}
+
+// ---- block-operand loads (non-temporal, straight into registers).
+// Every load here and in the staging helpers is issued unconditionally, so
+// the loop bodies stay straight-line and the compiler's wait before the LDS
+// store counts only the vector loads, leaving the block loads in flight.  A
+// block lane past the end of the contraction reads a clamped, valid address;
+// its value is a finite block entry and meets the zero that the stage
+// stores for that vector position, so it adds exactly nothing.
+// F, float64: instruction j takes entry base + 4 j + kg, so the 4 lane
+// groups of a row read 64 contiguous bytes per load.
+__device__ __forceinline__ void load_row_f64(const cpx<double>* __restrict__ Arow, int64_t base,
+                                             int kg, int64_t end, cpx<double> (&a)[8]) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int64_t e = base + 4 * j + kg;
+    a[j] = ld_block(Arow + (e < end ? e : 0));
+  }
+}
+
+// F*, float64: sensors q .. q + 7 of one column.
+__device__ __forceinline__ void load_col_f64(const cpx<double>* __restrict__ Acol, int64_t q,
+                                             int64_t Nd, int64_t Nm, cpx<double> (&f)[8]) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    f[j] = ld_block(Acol + (q + j < Nd ? (q + j) * Nm : 0));
+  }
+}
+
+// F, bfloat16 words (hi, lo) of slots 0..7 of lane group kg, chunk at
+// `base`; entries at or past `end` read the row's first entry instead.  With
+// VEC the row is 16-byte aligned and `end` a multiple of the entries per
+// load, so each 16-byte load is wholly in or out.
+template <bool LO, bool VEC>
+__device__ __forceinline__ void load_row_slots(const uint32_t* __restrict__ Arow, int64_t base,
+                                               int kg, int64_t end, uint32_t (&w0)[8],
+                                               uint32_t (&w1)[8]) {
+  constexpr int WPE = LO ? 2 : 1;
+  if constexpr (VEC && LO) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {  // entries base + 8 h + 2 kg + {0, 1}
+      const int64_t e = base + 8 * h + 2 * kg;
+      const u4v v = __builtin_nontemporal_load(reinterpret_cast<const u4v*>(Arow + 2 * (e < end ? e : 0)));
+      w0[2 * h] = v[0];
+      w1[2 * h] = v[1];
+      w0[2 * h + 1] = v[2];
+      w1[2 * h + 1] = v[3];
+    }
+  } else if constexpr (VEC) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {  // entries base + 16 h + 4 kg + {0..3}
+      const int64_t e = base + 16 * h + 4 * kg;
+      const u4v v = __builtin_nontemporal_load(reinterpret_cast<const u4v*>(Arow + (e < end ? e : 0)));
+#pragma unroll
+      for (int c = 0; c < 4; ++c) w0[4 * h + c] = v[c];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) w1[j] = 0u;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int64_t e = base + row_slot_entry<LO>(kg, j);
+      const uint32_t* at = Arow + (e < end ? e : 0) * WPE;
+      w0[j] = __builtin_nontemporal_load(at);
+      w1[j] = LO ? __builtin_nontemporal_load(at + 1) : 0u;
+    }
+  }
+}
+
+// F*, bfloat16 words of sensors q .. q + 7 of one column.
+template <bool LO>
+__device__ __forceinline__ void load_col8(const uint32_t* __restrict__ Acol, int64_t q,
+                                          int64_t Nd, int64_t Nm, uint32_t (&w0)[8],
+                                          uint32_t (&w1)[8]) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int64_t r = q + j < Nd ? q + j : 0;
+    if constexpr (LO) {
+      const u2v x = __builtin_nontemporal_load(reinterpret_cast<const u2v*>(Acol + r * Nm * 2));
+      w0[j] = x[0];
+      w1[j] = x[1];
+    } else {
+      w0[j] = __builtin_nontemporal_load(Acol + r * Nm);
+      w1[j] = 0u;
+    }
+  }
+}
+
+// ---- units
+// F, float64: rows mt*64 + 16 w .. of frequency k, column chunk pc, right-hand
+// sides b0 .. b0 + nb - 1 (nb <= 16 NT).
+template <int NT>
+__device__ __forceinline__ void mfma_rows_f64_wg(const cpx<double>* __restrict__ A,
+                                                 const cpx<double>* __restrict__ X,
+                                                 cpx<double>* __restrict__ P, GemvShape g,
+                                                 int64_t b0, int nb, int64_t k, int64_t mt,
+                                                 int64_t pc, void* lds) {
+  constexpr int PP = NT * 16 + 1, BUF = 32 * PP;
+  cpx<double>* sx = static_cast<cpx<double>*>(lds);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, kg = lane >> 4;
   const int64_t p0 = pc * g.pc_len;
   const int64_t p1 = min(p0 + g.pc_len, g.Nm);
-  const int col = lane & 15, kg = lane >> 4;
-  const int64_t srow = min(mt * 16 + col, g.Nd - 1);  // A row this lane supplies
-  const cpx<double>* __restrict__ Arow = A + (k * g.Nd + srow) * g.Nm;
-  const cpx<double>* Xrow[NT];
-  bool xok[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int b = t * 16 + col;
-    xok[t] = b < nb;
-    Xrow[t] = X + ((b0 + (xok[t] ? b : 0)) * g.nf + k) * g.Nm;
-  }
+  const int64_t row0 = mt * kWgTile + 16 * wave;
+  const cpx<double>* __restrict__ Arow = A + (k * g.Nd + min(row0 + col, g.Nd - 1)) * g.Nm;
   d4v accr[NT], acci[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) accr[t] = acci[t] = (d4v){0, 0, 0, 0};
-
+  cpx<double> a[8];
+  {
+    cpx<double> v[2 * NT];
+    stage_f64_load<NT>(X, g.nf, k, g.Nm, b0, nb, p0, p1, v);
+    load_row_f64(Arow, p0, kg, p1, a);
+    stage_f64_store<NT>(v, nb, p0, p1, sx);
+  }
+  __syncthreads();
+  int cur = 0;
   for (int64_t base = p0; base < p1; base += 32) {
-    const int64_t q = base + 8 * kg;
-    cpx<double> a[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) a[j] = (q + j < p1) ? ld_block(Arow + q + j) : cpx<double>{0, 0};
+    const int64_t nend = base + 32 < p1 ? p1 : 0;  // 0: past the last chunk, all lanes off
+    cpx<double> v[2 * NT], an[8];
+    stage_f64_load<NT>(X, g.nf, k, g.Nm, b0, nb, base + 32, nend, v);
+    __builtin_amdgcn_sched_barrier(0);  // vector loads first, then block loads
+    load_row_f64(Arow, base + 32, kg, nend, an);
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+    const cpx<double>* xs = sx + cur * BUF;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      cpx<double> x[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
-        x[j] = (xok[t] && q + j < p1) ? Xrow[t][q + j] : cpx<double>{0, 0};
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        accr[t] = mfma64(a[j].x, x[j].x, accr[t]);
-        accr[t] = mfma64(a[j].y, -x[j].y, accr[t]);
-        acci[t] = mfma64(a[j].x, x[j].y, acci[t]);
-        acci[t] = mfma64(a[j].y, x[j].x, acci[t]);
+      for (int j = 0; j < 8; ++j) {  // re / im chains alternate
+        const cpx<double> x = xs[(4 * j + kg) * PP + t * 16 + col];
+        accr[t] = mfma64(a[j].x, x.x, accr[t]);
+        acci[t] = mfma64(a[j].x, x.y, acci[t]);
+        accr[t] = mfma64(a[j].y, -x.y, accr[t]);
+        acci[t] = mfma64(a[j].y, x.x, acci[t]);
       }
     }
+    __builtin_amdgcn_sched_barrier(0);  // the store waits for the vector loads: after the products
+    stage_f64_store<NT>(v, nb, base + 32, nend, sx + (cur ^ 1) * BUF);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[j] = an[j];
+    __syncthreads();
+    cur ^= 1;
   }
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -404,54 +629,65 @@ __device__ __forceinline__ void mfma_rows_f64_unit(const cpx<double>* __restrict
     if (b >= nb) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int64_t s = mt * 16 + kg + 4 * i;  // float64 accumulator rows interleave
+      const int64_t s = row0 + kg + 4 * i;  // float64 accumulator rows interleave
       if (s < g.Nd)
         P[(((b0 + b) * g.n_pc + pc) * g.nf + k) * g.Nd + s] = {accr[t][i], acci[t][i]};
     }
   }
 }
 
+// F*, float64: columns pt*64 + 16 w .., X^T = Dhat^T conj(Fhat) over all sensors.
 template <int MT>
-__device__ __forceinline__ void mfma_cols_f64_unit(const cpx<double>* __restrict__ A, const cpx<double>* __restrict__ D,
-              cpx<double>* __restrict__ Y, GemvShape g, int64_t b0, int nb, int64_t k, int64_t pt) {
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ void mfma_cols_f64_wg(const cpx<double>* __restrict__ A,
+                                                 const cpx<double>* __restrict__ D,
+                                                 cpx<double>* __restrict__ Y, GemvShape g,
+                                                 int64_t b0, int nb, int64_t k, int64_t pt,
+                                                 void* lds) {
+  constexpr int PP = MT * 16 + 1, BUF = 32 * PP;
+  cpx<double>* sd = static_cast<cpx<double>*>(lds);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, kg = lane >> 4;
-  const int64_t pcol = min(pt * 16 + col, g.Nm - 1);  // Fhat column this lane supplies
-  const cpx<double>* __restrict__ Ak = A + k * g.Nd * g.Nm + pcol;
-  const cpx<double>* Drow[MT];
-  bool dok[MT];
-#pragma unroll
-  for (int t = 0; t < MT; ++t) {
-    const int b = t * 16 + col;
-    dok[t] = b < nb;
-    Drow[t] = D + ((b0 + (dok[t] ? b : 0)) * g.nf + k) * g.Nd;
-  }
+  const int64_t col0 = pt * kWgTile + 16 * wave;
+  const cpx<double>* __restrict__ Ak = A + k * g.Nd * g.Nm + min(col0 + col, g.Nm - 1);
   d4v accr[MT], acci[MT];
 #pragma unroll
   for (int t = 0; t < MT; ++t) accr[t] = acci[t] = (d4v){0, 0, 0, 0};
-
+  cpx<double> f[8];
+  {
+    cpx<double> v[2 * MT];
+    stage_f64_load<MT>(D, g.nf, k, g.Nd, b0, nb, 0, g.Nd, v);
+    load_col_f64(Ak, 8 * kg, g.Nd, g.Nm, f);
+    stage_f64_store<MT>(v, nb, 0, g.Nd, sd);
+  }
+  __syncthreads();
+  int cur = 0;
   for (int64_t base = 0; base < g.Nd; base += 32) {
-    const int64_t q = base + 8 * kg;
-    cpx<double> f[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-      f[j] = (q + j < g.Nd) ? ld_block(Ak + (q + j) * g.Nm) : cpx<double>{0, 0};
+    const int64_t nend = base + 32 < g.Nd ? g.Nd : 0;  // 0: past the last chunk
+    cpx<double> v[2 * MT], fn[8];
+    stage_f64_load<MT>(D, g.nf, k, g.Nd, b0, nb, base + 32, nend, v);
+    __builtin_amdgcn_sched_barrier(0);  // vector loads first, then block loads
+    load_col_f64(Ak, base + 32 + 8 * kg, nend, g.Nm, fn);
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+    const cpx<double>* ds = sd + cur * BUF;
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
-      cpx<double> d[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
-        d[j] = (dok[t] && q + j < g.Nd) ? Drow[t][q + j] : cpx<double>{0, 0};
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {  // x += conj(f) d
-        accr[t] = mfma64(d[j].x, f[j].x, accr[t]);
-        accr[t] = mfma64(d[j].y, f[j].y, accr[t]);
-        acci[t] = mfma64(d[j].y, f[j].x, acci[t]);
-        acci[t] = mfma64(-d[j].x, f[j].y, acci[t]);
+      for (int j = 0; j < 8; ++j) {  // x += conj(f) d; re / im chains alternate
+        const cpx<double> d = ds[(8 * kg + j) * PP + t * 16 + col];
+        accr[t] = mfma64(d.x, f[j].x, accr[t]);
+        acci[t] = mfma64(d.y, f[j].x, acci[t]);
+        accr[t] = mfma64(d.y, f[j].y, accr[t]);
+        acci[t] = mfma64(-d.x, f[j].y, acci[t]);
       }
     }
+    __builtin_amdgcn_sched_barrier(0);  // the store waits for the vector loads: after the products
+    stage_f64_store<MT>(v, nb, base + 32, nend, sd + (cur ^ 1) * BUF);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) f[j] = fn[j];
+    __syncthreads();
+    cur ^= 1;
   }
-  const int64_t p = pt * 16 + col;
+  const int64_t p = col0 + col;
   if (p >= g.Nm) return;
 #pragma unroll
   for (int t = 0; t < MT; ++t)
@@ -462,112 +698,79 @@ __device__ __forceinline__ void mfma_cols_f64_unit(const cpx<double>* __restrict
     }
 }
 
-// ------------------------------------------------ matrix-core units, bf16
+// F on the bfloat16 matrix cores.  The vector planes carry the column
+// sub-block scales already (folded in by the split kernel), so the whole
+// column chunk accumulates in float32 matrix-core accumulators; the real and
+// imaginary accumulation chains alternate.
 template <int NT, bool LO, bool VEC>
-__device__ __forceinline__ void mfma_rows_bf16_unit(const uint32_t* __restrict__ A, const float* __restrict__ scales,
-               const uint16_t* __restrict__ Xs, cpx<double>* __restrict__ P, GemvShape g,
-               int64_t n8, int64_t b0, int nb, int64_t k, int64_t mt, int64_t pc) {
-  constexpr int WPE = LO ? 2 : 1;  // words per entry
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ void mfma_rows_bf16_wg(const uint32_t* __restrict__ A,
+                                                  const uint16_t* __restrict__ Xs,
+                                                  cpx<double>* __restrict__ P, GemvShape g,
+                                                  int64_t n8, int64_t b0, int nb, int64_t k,
+                                                  int64_t mt, int64_t pc, void* lds) {
+  constexpr int WPE = LO ? 2 : 1;
+  constexpr int PP = NT * 16 + 1, BUF = 16 * PP;
+  u4v* sx = static_cast<u4v*>(lds);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, kg = lane >> 4;
   const int64_t p0 = pc * g.pc_len;
   const int64_t p1 = min(p0 + g.pc_len, g.Nm);
-  const int col = lane & 15, kg = lane >> 4;
-  const int64_t srow = min(mt * 16 + col, g.Nd - 1);
-  const uint32_t* __restrict__ Arow = A + (k * g.Nd + srow) * g.Nm * WPE;
-  const int64_t ntiles = (g.Nm + kScaleTile - 1) / kScaleTile;
-  const float* __restrict__ sk = scales + k * ntiles;
-  const uint16_t* Xb[NT];
-  bool xok[NT];
+  const int64_t row0 = mt * kWgTile + 16 * wave;
+  const uint32_t* __restrict__ Arow = A + (k * g.Nd + min(row0 + col, g.Nd - 1)) * g.Nm * WPE;
+  f4v tr[NT], ti[NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int b = t * 16 + col;
-    xok[t] = b < nb;
-    Xb[t] = Xs + ((b0 + (xok[t] ? b : 0)) * g.nf + k) * 4 * n8;
+  for (int t = 0; t < NT; ++t) tr[t] = ti[t] = (f4v){0, 0, 0, 0};
+  uint32_t w0[8], w1[8];
+  {
+    u4v v[NT];
+    stage_planes_load<NT>(Xs, g.nf, k, n8, b0, nb, p0, p1, v);
+    load_row_slots<LO, VEC>(Arow, p0, kg, p1, w0, w1);
+    stage_planes_store_rows<NT, LO>(v, nb, p0, p1, sx);
   }
-  double accr[NT][4], acci[NT][4];
+  __syncthreads();
+  int cur = 0;
+  for (int64_t base = p0; base < p1; base += 32) {
+    const int64_t nend = base + 32 < p1 ? p1 : 0;  // 0: past the last chunk
+    // unpack this chunk's block words, then reuse them for the next loads
+    const u4v hr = lows(w0), hi = highs(w0);
+    const u4v nhi = neg(hi);
+    u4v lr = {0, 0, 0, 0}, li = {0, 0, 0, 0}, nli = {0, 0, 0, 0};
+    if constexpr (LO) {
+      lr = lows(w1);
+      li = highs(w1);
+      nli = neg(li);
+    }
+    u4v v[NT];
+    stage_planes_load<NT>(Xs, g.nf, k, n8, b0, nb, base + 32, nend, v);
+    __builtin_amdgcn_sched_barrier(0);  // vector loads first, then block loads
+    load_row_slots<LO, VEC>(Arow, base + 32, kg, nend, w0, w1);
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+    const u4v* xs = sx + cur * BUF;
 #pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) accr[t][i] = acci[t][i] = 0.0;
-
-  // walk the chunk in pieces that never straddle a 256-column scale tile
-  for (int64_t tb = p0, te; tb < p1; tb = te) {
-    te = min((tb / kScaleTile + 1) * kScaleTile, p1);
-    f4v tr[NT], ti[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) tr[t] = ti[t] = (f4v){0, 0, 0, 0};
-    for (int64_t base = tb; base < te; base += 32) {
-      const int64_t q = base + 8 * kg;
-      uint32_t w0[8], w1[8];
-      if (VEC && q + 8 <= te) {
-        if constexpr (LO) {
-#pragma unroll
-          for (int h = 0; h < 4; ++h) {
-            const u4v v = __builtin_nontemporal_load(reinterpret_cast<const u4v*>(Arow + 2 * (q + 2 * h)));
-            w0[2 * h] = v[0];
-            w1[2 * h] = v[1];
-            w0[2 * h + 1] = v[2];
-            w1[2 * h + 1] = v[3];
-          }
-        } else {
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const u4v v = __builtin_nontemporal_load(reinterpret_cast<const u4v*>(Arow + q + 4 * h));
-#pragma unroll
-            for (int e = 0; e < 4; ++e) w0[4 * h + e] = v[e];
-          }
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const bool ok = q + j < te;
-          w0[j] = ok ? Arow[(q + j) * WPE] : 0u;
-          w1[j] = (LO && ok) ? Arow[(q + j) * WPE + 1] : 0u;
-        }
-      }
-      const u4v hr = lows(w0), hi = highs(w0);
-      const u4v nhi = neg(hi);
-      u4v lr = {0, 0, 0, 0}, li = {0, 0, 0, 0}, nli = {0, 0, 0, 0};
+    for (int t = 0; t < NT; ++t) {
+      const int b = t * 16 + col;
+      const u4v xrh = xs[(0 * 4 + kg) * PP + b], xrl = xs[(1 * 4 + kg) * PP + b];
+      const u4v xih = xs[(2 * 4 + kg) * PP + b], xil = xs[(3 * 4 + kg) * PP + b];
+      // re: Hr xr - Hi xi ; im: Hr xi + Hi xr   (each with hi/lo splits)
+      tr[t] = mma(hr, xrh, tr[t]);
+      ti[t] = mma(hr, xih, ti[t]);
+      tr[t] = mma(hr, xrl, tr[t]);
+      ti[t] = mma(hr, xil, ti[t]);
+      tr[t] = mma(nhi, xih, tr[t]);
+      ti[t] = mma(hi, xrh, ti[t]);
+      tr[t] = mma(nhi, xil, tr[t]);
+      ti[t] = mma(hi, xrl, ti[t]);
       if constexpr (LO) {
-        lr = lows(w1);
-        li = highs(w1);
-        nli = neg(li);
-      }
-      const bool qok = q < te;
-#pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        u4v xrh = {0, 0, 0, 0}, xrl = xrh, xih = xrh, xil = xrh;
-        if (xok[t] && qok) {
-          xrh = ld16(Xb[t] + 0 * n8 + q);
-          xrl = ld16(Xb[t] + 1 * n8 + q);
-          xih = ld16(Xb[t] + 2 * n8 + q);
-          xil = ld16(Xb[t] + 3 * n8 + q);
-        }
-        // re: Hr xr - Hi xi ; im: Hr xi + Hi xr   (each with hi/lo splits)
-        tr[t] = mma(hr, xrh, tr[t]);
-        tr[t] = mma(hr, xrl, tr[t]);
-        tr[t] = mma(nhi, xih, tr[t]);
-        tr[t] = mma(nhi, xil, tr[t]);
-        ti[t] = mma(hr, xih, ti[t]);
-        ti[t] = mma(hr, xil, ti[t]);
-        ti[t] = mma(hi, xrh, ti[t]);
-        ti[t] = mma(hi, xrl, ti[t]);
-        if constexpr (LO) {
-          tr[t] = mma(lr, xrh, tr[t]);
-          tr[t] = mma(nli, xih, tr[t]);
-          ti[t] = mma(lr, xih, ti[t]);
-          ti[t] = mma(li, xrh, ti[t]);
-        }
+        tr[t] = mma(lr, xrh, tr[t]);
+        ti[t] = mma(lr, xih, ti[t]);
+        tr[t] = mma(nli, xih, tr[t]);
+        ti[t] = mma(li, xrh, ti[t]);
       }
     }
-    const double sc = (double)sk[tb / kScaleTile];
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        accr[t][i] += sc * (double)tr[t][i];
-        acci[t][i] += sc * (double)ti[t][i];
-      }
+    __builtin_amdgcn_sched_barrier(0);  // the store waits for the vector loads: after the products
+    stage_planes_store_rows<NT, LO>(v, nb, base + 32, nend, sx + (cur ^ 1) * BUF);
+    __syncthreads();
+    cur ^= 1;
   }
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -575,87 +778,85 @@ __device__ __forceinline__ void mfma_rows_bf16_unit(const uint32_t* __restrict__
     if (b >= nb) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int64_t s = mt * 16 + 4 * kg + i;
+      const int64_t s = row0 + 4 * kg + i;
       if (s < g.Nd)
-        P[(((b0 + b) * g.n_pc + pc) * g.nf + k) * g.Nd + s] = {accr[t][i], acci[t][i]};
+        P[(((b0 + b) * g.n_pc + pc) * g.nf + k) * g.Nd + s] = {(double)tr[t][i], (double)ti[t][i]};
     }
   }
 }
 
+// F* on the bfloat16 matrix cores: X^T = Dhat^T conj(Fhat), contraction over
+// all sensors; the column scale is applied to the float32 result.
 template <int MT, bool LO>
-__device__ __forceinline__ void mfma_cols_bf16_unit(const uint32_t* __restrict__ A, const float* __restrict__ scales,
-               const uint16_t* __restrict__ Ds, cpx<float>* __restrict__ Y, GemvShape g,
-               int64_t nd8, int64_t b0, int nb, int64_t k, int64_t pt) {
+__device__ __forceinline__ void mfma_cols_bf16_wg(const uint32_t* __restrict__ A,
+                                                  const float* __restrict__ scales,
+                                                  const uint16_t* __restrict__ Ds,
+                                                  cpx<float>* __restrict__ Y, GemvShape g,
+                                                  int64_t nd8, int64_t b0, int nb, int64_t k,
+                                                  int64_t pt, void* lds) {
   constexpr int WPE = LO ? 2 : 1;
-  const int lane = threadIdx.x & 63;
+  constexpr int PP = MT * 16 + 1, BUF = 16 * PP;
+  u4v* sd = static_cast<u4v*>(lds);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, kg = lane >> 4;
-  const int64_t pcol = min(pt * 16 + col, g.Nm - 1);
-  const uint32_t* __restrict__ Ak = A + (k * g.Nd * g.Nm + pcol) * WPE;
-  const uint16_t* Db[MT];
-  bool dok[MT];
-#pragma unroll
-  for (int t = 0; t < MT; ++t) {
-    const int b = t * 16 + col;
-    dok[t] = b < nb;
-    Db[t] = Ds + ((b0 + (dok[t] ? b : 0)) * g.nf + k) * 4 * nd8;
-  }
+  const int64_t col0 = pt * kWgTile + 16 * wave;
+  const uint32_t* __restrict__ Ak = A + (k * g.Nd * g.Nm + min(col0 + col, g.Nm - 1)) * WPE;
   f4v xr[MT], xi[MT];
 #pragma unroll
   for (int t = 0; t < MT; ++t) xr[t] = xi[t] = (f4v){0, 0, 0, 0};
-
+  uint32_t w0[8], w1[8];
+  {
+    u4v v[MT];
+    stage_planes_load<MT>(Ds, g.nf, k, nd8, b0, nb, 0, g.Nd, v);
+    load_col8<LO>(Ak, 8 * kg, g.Nd, g.Nm, w0, w1);
+    stage_planes_store_cols<MT>(v, nb, 0, g.Nd, sd);
+  }
+  __syncthreads();
+  int cur = 0;
   for (int64_t base = 0; base < g.Nd; base += 32) {
-    const int64_t q = base + 8 * kg;
-    uint32_t w0[8], w1[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const bool ok = q + j < g.Nd;
-      if constexpr (LO) {
-        const u2v v = ok ? __builtin_nontemporal_load(
-                               reinterpret_cast<const u2v*>(Ak + (q + j) * g.Nm * 2))
-                         : (u2v){0u, 0u};
-        w0[j] = v[0];
-        w1[j] = v[1];
-      } else {
-        w0[j] = ok ? __builtin_nontemporal_load(Ak + (q + j) * g.Nm) : 0u;
-        w1[j] = 0u;
-      }
-    }
+    const int64_t nend = base + 32 < g.Nd ? g.Nd : 0;  // 0: past the last chunk
+    // unpack this chunk's block words, then reuse them for the next loads
     const u4v fr = lows(w0), fi = highs(w0);
     const u4v nfi = neg(fi);
-    u4v lr = {0, 0, 0, 0}, nli = {0, 0, 0, 0};
+    u4v lr = {0, 0, 0, 0}, li = {0, 0, 0, 0}, nli = {0, 0, 0, 0};
     if constexpr (LO) {
       lr = lows(w1);
-      nli = neg(highs(w1));
+      li = highs(w1);
+      nli = neg(li);
     }
-    const u4v li = neg(nli);
-    const bool qok = q < g.Nd;
+    u4v v[MT];
+    stage_planes_load<MT>(Ds, g.nf, k, nd8, b0, nb, base + 32, nend, v);
+    __builtin_amdgcn_sched_barrier(0);  // vector loads first, then block loads
+    load_col8<LO>(Ak, base + 32 + 8 * kg, nend, g.Nm, w0, w1);
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+    const u4v* ds = sd + cur * BUF;
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
-      u4v drh = {0, 0, 0, 0}, drl = drh, dih = drh, dil = drh;
-      if (dok[t] && qok) {
-        drh = ld16(Db[t] + 0 * nd8 + q);
-        drl = ld16(Db[t] + 1 * nd8 + q);
-        dih = ld16(Db[t] + 2 * nd8 + q);
-        dil = ld16(Db[t] + 3 * nd8 + q);
-      }
+      const int b = t * 16 + col;
+      const u4v drh = ds[(0 * 4 + kg) * PP + b], drl = ds[(1 * 4 + kg) * PP + b];
+      const u4v dih = ds[(2 * 4 + kg) * PP + b], dil = ds[(3 * 4 + kg) * PP + b];
       // x += conj(f) d: re = dr fr + di fi ; im = di fr - dr fi
       xr[t] = mma(drh, fr, xr[t]);
-      xr[t] = mma(drl, fr, xr[t]);
-      xr[t] = mma(dih, fi, xr[t]);
-      xr[t] = mma(dil, fi, xr[t]);
       xi[t] = mma(dih, fr, xi[t]);
+      xr[t] = mma(drl, fr, xr[t]);
       xi[t] = mma(dil, fr, xi[t]);
+      xr[t] = mma(dih, fi, xr[t]);
       xi[t] = mma(drh, nfi, xi[t]);
+      xr[t] = mma(dil, fi, xr[t]);
       xi[t] = mma(drl, nfi, xi[t]);
       if constexpr (LO) {
         xr[t] = mma(drh, lr, xr[t]);
-        xr[t] = mma(dih, li, xr[t]);
         xi[t] = mma(dih, lr, xi[t]);
+        xr[t] = mma(dih, li, xr[t]);
         xi[t] = mma(drh, nli, xi[t]);
       }
     }
+    __builtin_amdgcn_sched_barrier(0);  // the store waits for the vector loads: after the products
+    stage_planes_store_cols<MT>(v, nb, base + 32, nend, sd + (cur ^ 1) * BUF);
+    __syncthreads();
+    cur ^= 1;
   }
-  const int64_t p = pt * 16 + col;
+  const int64_t p = col0 + col;
   if (p >= g.Nm) return;
   const int64_t ntiles = (g.Nm + kScaleTile - 1) / kScaleTile;
   const float sc = scales[k * ntiles + p / kScaleTile];
