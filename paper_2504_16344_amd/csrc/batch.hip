@@ -18,6 +18,9 @@ namespace {
 
 constexpr int kRowsV = 4;   // vector-unit rows per wavefront (F)
 constexpr int kColsV = 2;   // vector-unit column groups per wavefront (F*)
+// Load ring depth of the matrix-core units here: this kernel inlines every
+// path, and a shallower ring keeps the largest one within 256 registers.
+constexpr int kBatchRing = 2;
 
 template <int CLS>
 struct ClassTraits;
@@ -33,7 +36,23 @@ constexpr int stage_bytes() {
   return CLS == kClassF64 ? stage_bytes_f64(4) : (CLS == kClassMixedFp16 ? 16 : stage_bytes_bf16(4));
 }
 
-// Vector-path wave units of one instance (a workgroup unit is 4 of them).
+// Workgroup size per class: the bfloat16 matrix-core units run 8 wavefronts.
+template <int CLS>
+constexpr int class_threads() {
+  return (CLS == kClassMixedBf16 || CLS == kClassFastBf16) ? kBf16Threads : 256;
+}
+
+__host__ __device__ constexpr int class_threads_rt(int cls) {
+  return (cls == kClassMixedBf16 || cls == kClassFastBf16) ? kBf16Threads : 256;
+}
+
+// Matrix-path tile (rows for F, columns for F*) per class.
+__host__ __device__ constexpr int class_tile(int cls) {
+  return cls == kClassF64 ? kWgTile : kBf16Tile;
+}
+
+// Vector-path wave units of one instance (a workgroup unit is
+// threads / 64 of them).
 __device__ __forceinline__ int64_t vector_wave_units(p2o_op op, const GemvShape& g) {
   if (op == P2O_F) return g.nf * ((g.Nd + kRowsV - 1) / kRowsV) * g.n_pc;
   return g.nf * ((g.Nm + 64 * kColsV - 1) / (64 * kColsV));
@@ -43,7 +62,8 @@ template <int CLS>
 __device__ __forceinline__ void rows_unit(const BatchInst& I, int64_t u, void* lds) {
   const GemvShape& g = I.g;
   if (I.path == kPathMatrix) {
-    const int64_t nmt = (g.Nd + kWgTile - 1) / kWgTile, rest = u / nmt;
+    constexpr int64_t tile = class_tile(CLS);
+    const int64_t nmt = (g.Nd + tile - 1) / tile, rest = u / nmt;
     const int64_t mt = u % nmt, k = rest % g.nf, pc = rest / g.nf;
     for (int64_t b0 = 0; b0 < g.nrhs; b0 += 64) {
       const int nb = (int)min((int64_t)64, g.nrhs - b0);
@@ -61,19 +81,19 @@ __device__ __forceinline__ void rows_unit(const BatchInst& I, int64_t u, void* l
         auto* P = static_cast<cpx<double>*>(I.out);
         const bool vec = LO ? (g.Nm % 2 == 0) : (g.Nm % 4 == 0);
         if (vec) {
-          if (nb > 32) mfma_rows_bf16_wg<4, LO, true>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
-          else if (nb > 16) mfma_rows_bf16_wg<2, LO, true>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
-          else mfma_rows_bf16_wg<1, LO, true>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
+          if (nb > 32) mfma_rows_bf16_wg<4, LO, true, kBatchRing>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
+          else if (nb > 16) mfma_rows_bf16_wg<2, LO, true, kBatchRing>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
+          else mfma_rows_bf16_wg<1, LO, true, kBatchRing>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
         } else {
-          if (nb > 32) mfma_rows_bf16_wg<4, LO, false>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
-          else if (nb > 16) mfma_rows_bf16_wg<2, LO, false>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
-          else mfma_rows_bf16_wg<1, LO, false>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
+          if (nb > 32) mfma_rows_bf16_wg<4, LO, false, kBatchRing>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
+          else if (nb > 16) mfma_rows_bf16_wg<2, LO, false, kBatchRing>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
+          else mfma_rows_bf16_wg<1, LO, false, kBatchRing>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
         }
       }
     }
     return;
   }
-  const int64_t wu = u * 4 + wave_id_in_block();
+  const int64_t wu = u * (class_threads<CLS>() / 64) + wave_id_in_block();
   if (wu >= vector_wave_units(P2O_F, g)) return;
   const int64_t nsg = (g.Nd + kRowsV - 1) / kRowsV, rest = wu / nsg;
   const int64_t sg = wu % nsg, k = rest % g.nf, pc = rest / g.nf;
@@ -100,7 +120,8 @@ template <int CLS>
 __device__ __forceinline__ void cols_unit(const BatchInst& I, int64_t u, void* lds) {
   const GemvShape& g = I.g;
   if (I.path == kPathMatrix) {
-    const int64_t npt = (g.Nm + kWgTile - 1) / kWgTile;
+    constexpr int64_t tile = class_tile(CLS);
+    const int64_t npt = (g.Nm + tile - 1) / tile;
     const int64_t pt = u % npt, k = u / npt;
     for (int64_t b0 = 0; b0 < g.nrhs; b0 += 64) {
       const int nb = (int)min((int64_t)64, g.nrhs - b0);
@@ -116,14 +137,14 @@ __device__ __forceinline__ void cols_unit(const BatchInst& I, int64_t u, void* l
         const auto* A = static_cast<const uint32_t*>(I.fhat);
         const auto* D = static_cast<const uint16_t*>(I.in);
         auto* Y = static_cast<cpx<float>*>(I.out);
-        if (nb > 32) mfma_cols_bf16_wg<4, LO>(A, I.scales, D, Y, g, I.n8, b0, nb, k, pt, lds);
-        else if (nb > 16) mfma_cols_bf16_wg<2, LO>(A, I.scales, D, Y, g, I.n8, b0, nb, k, pt, lds);
-        else mfma_cols_bf16_wg<1, LO>(A, I.scales, D, Y, g, I.n8, b0, nb, k, pt, lds);
+        if (nb > 32) mfma_cols_bf16_wg<4, LO, kBatchRing>(A, I.scales, D, Y, g, I.n8, b0, nb, k, pt, lds);
+        else if (nb > 16) mfma_cols_bf16_wg<2, LO, kBatchRing>(A, I.scales, D, Y, g, I.n8, b0, nb, k, pt, lds);
+        else mfma_cols_bf16_wg<1, LO, kBatchRing>(A, I.scales, D, Y, g, I.n8, b0, nb, k, pt, lds);
       }
     }
     return;
   }
-  const int64_t wu = u * 4 + wave_id_in_block();
+  const int64_t wu = u * (class_threads<CLS>() / 64) + wave_id_in_block();
   if (wu >= vector_wave_units(P2O_FADJ, g)) return;
   const int64_t npg = (g.Nm + 64 * kColsV - 1) / (64 * kColsV);
   const int64_t pg = wu % npg, k = wu / npg;
@@ -149,7 +170,7 @@ __device__ __forceinline__ void cols_unit(const BatchInst& I, int64_t u, void* l
 // The grid is a multiple of 8 workgroups; each XCD takes a contiguous range
 // of units per round, so neighbouring tiles of one instance share its L2.
 template <int CLS, int OP>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(class_threads<CLS>())
 batch_product_kernel(const BatchInst* __restrict__ insts, int n, int64_t total) {
   __shared__ __align__(16) char lds[stage_bytes<CLS>()];
   const int64_t grid = gridDim.x;
@@ -172,28 +193,30 @@ hipError_t launch_one(const BatchInst* insts, int n, int64_t total, hipStream_t 
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_product_kernel<CLS, OP>, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_product_kernel<CLS, OP>,
+                                                     class_threads<CLS>(), 0);
   if (e != hipSuccess) return e;
   int64_t blocks = (int64_t)std::max(1, cus) * std::max(1, per_cu);
   blocks = std::min<int64_t>(blocks, total);
   if (blocks < 1) return hipSuccess;
   blocks = (blocks + kXcds - 1) / kXcds * kXcds;
-  hipLaunchKernelGGL((batch_product_kernel<CLS, OP>), dim3((unsigned)blocks), dim3(256), 0, s,
-                     insts, n, total);
+  hipLaunchKernelGGL((batch_product_kernel<CLS, OP>), dim3((unsigned)blocks),
+                     dim3(class_threads<CLS>()), 0, s, insts, n, total);
   return hipGetLastError();
 }
 
 }  // namespace
 
 int64_t batch_units(BatchClass cls, p2o_op op, int path, const GemvShape& g) {
-  (void)cls;
   if (path == kPathMatrix) {
-    if (op == P2O_F) return g.nf * ((g.Nd + kWgTile - 1) / kWgTile) * g.n_pc;
-    return g.nf * ((g.Nm + kWgTile - 1) / kWgTile);
+    const int64_t tile = class_tile(cls);
+    if (op == P2O_F) return g.nf * ((g.Nd + tile - 1) / tile) * g.n_pc;
+    return g.nf * ((g.Nm + tile - 1) / tile);
   }
   const int64_t waves = op == P2O_F ? g.nf * ((g.Nd + kRowsV - 1) / kRowsV) * g.n_pc
                                     : g.nf * ((g.Nm + 64 * kColsV - 1) / (64 * kColsV));
-  return (waves + 3) / 4;
+  const int64_t per = class_threads_rt(cls) / 64;
+  return (waves + per - 1) / per;
 }
 
 hipError_t launch_batch_product(BatchClass cls, p2o_op op, const BatchInst* insts, int n,

@@ -18,12 +18,12 @@
 // the 4 lane groups of a block row read one contiguous 64-byte span per
 // load, and stages the vector planes in LDS in the same slot order.
 //
-// F  ("rows"): workgroup = 64 sensors x (16 NT) right-hand sides of one
+// F  ("rows"): workgroup = 128 sensors x (16 NT) right-hand sides of one
 //    frequency and one column chunk; the column sub-block scales are folded
 //    into the vector planes (exact: powers of two), so the chunk accumulates
 //    in float32 on the matrix cores.
 // F* ("cols"): X^T = Dhat^T conj(Fhat): workgroup = (16 MT) right-hand
-//    sides x 64 columns; contraction over all sensors; the column scale is
+//    sides x 128 columns; contraction over all sensors; the column scale is
 //    applied to the float32 result.
 // Vector operands come pre-split in four bfloat16 planes per (rhs, k):
 // [re hi][re lo][im hi][im lo], each padded to a multiple of 8 entries.
@@ -33,12 +33,12 @@ namespace p2o {
 namespace {
 
 template <int NT, bool LO, bool VEC>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kBf16Threads)
 gemm_rows_bf16(const uint32_t* __restrict__ A, const uint16_t* __restrict__ Xs,
                cpx<double>* __restrict__ P, GemvShape g, int64_t n8, int64_t b0, int nb) {
   __shared__ __align__(16) char lds[stage_bytes_bf16(NT)];
   const int64_t tile = xcd_local_tile(blockIdx.x, gridDim.x);
-  const int64_t nmt = (g.Nd + kWgTile - 1) / kWgTile;
+  const int64_t nmt = (g.Nd + kBf16Tile - 1) / kBf16Tile;
   const int64_t rest = tile / nmt;
   const int64_t pc = rest / g.nf;
   if (pc >= g.n_pc) return;  // grid padding: the whole workgroup leaves
@@ -46,13 +46,13 @@ gemm_rows_bf16(const uint32_t* __restrict__ A, const uint16_t* __restrict__ Xs,
 }
 
 template <int MT, bool LO>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kBf16Threads)
 gemm_cols_bf16(const uint32_t* __restrict__ A, const float* __restrict__ scales,
                const uint16_t* __restrict__ Ds, cpx<float>* __restrict__ Y, GemvShape g,
                int64_t nd8, int64_t b0, int nb) {
   __shared__ __align__(16) char lds[stage_bytes_bf16(MT)];
   const int64_t tile = xcd_local_tile(blockIdx.x, gridDim.x);
-  const int64_t npt = (g.Nm + kWgTile - 1) / kWgTile;
+  const int64_t npt = (g.Nm + kBf16Tile - 1) / kBf16Tile;
   const int64_t k = tile / npt;
   if (k >= g.nf) return;
   mfma_cols_bf16_wg<MT, LO>(A, scales, Ds, Y, g, nd8, b0, nb, k, tile % npt, lds);
@@ -100,15 +100,15 @@ unsigned padded_grid(int64_t tiles) { return (unsigned)((tiles + kXcds - 1) / kX
 template <bool LO, bool VEC>
 hipError_t rows_passes(const uint32_t* A, const uint16_t* Xs, cpx<double>* P,
                        const GemvShape& g, int64_t n8, hipStream_t s) {
-  const unsigned grid = padded_grid(((g.Nd + kWgTile - 1) / kWgTile) * g.nf * g.n_pc);
+  const unsigned grid = padded_grid(((g.Nd + kBf16Tile - 1) / kBf16Tile) * g.nf * g.n_pc);
   for (int64_t b0 = 0; b0 < g.nrhs; b0 += 64) {
     const int nb = (int)std::min<int64_t>(64, g.nrhs - b0);
     if (nb > 32)
-      hipLaunchKernelGGL((gemm_rows_bf16<4, LO, VEC>), dim3(grid), dim3(256), 0, s, A, Xs, P, g, n8, b0, nb);
+      hipLaunchKernelGGL((gemm_rows_bf16<4, LO, VEC>), dim3(grid), dim3(kBf16Threads), 0, s, A, Xs, P, g, n8, b0, nb);
     else if (nb > 16)
-      hipLaunchKernelGGL((gemm_rows_bf16<2, LO, VEC>), dim3(grid), dim3(256), 0, s, A, Xs, P, g, n8, b0, nb);
+      hipLaunchKernelGGL((gemm_rows_bf16<2, LO, VEC>), dim3(grid), dim3(kBf16Threads), 0, s, A, Xs, P, g, n8, b0, nb);
     else
-      hipLaunchKernelGGL((gemm_rows_bf16<1, LO, VEC>), dim3(grid), dim3(256), 0, s, A, Xs, P, g, n8, b0, nb);
+      hipLaunchKernelGGL((gemm_rows_bf16<1, LO, VEC>), dim3(grid), dim3(kBf16Threads), 0, s, A, Xs, P, g, n8, b0, nb);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -118,15 +118,15 @@ hipError_t rows_passes(const uint32_t* A, const uint16_t* Xs, cpx<double>* P,
 template <bool LO>
 hipError_t cols_passes(const uint32_t* A, const float* sc, const uint16_t* Ds,
                        cpx<float>* Y, const GemvShape& g, int64_t nd8, hipStream_t s) {
-  const unsigned grid = padded_grid(((g.Nm + kWgTile - 1) / kWgTile) * g.nf);
+  const unsigned grid = padded_grid(((g.Nm + kBf16Tile - 1) / kBf16Tile) * g.nf);
   for (int64_t b0 = 0; b0 < g.nrhs; b0 += 64) {
     const int nb = (int)std::min<int64_t>(64, g.nrhs - b0);
     if (nb > 32)
-      hipLaunchKernelGGL((gemm_cols_bf16<4, LO>), dim3(grid), dim3(256), 0, s, A, sc, Ds, Y, g, nd8, b0, nb);
+      hipLaunchKernelGGL((gemm_cols_bf16<4, LO>), dim3(grid), dim3(kBf16Threads), 0, s, A, sc, Ds, Y, g, nd8, b0, nb);
     else if (nb > 16)
-      hipLaunchKernelGGL((gemm_cols_bf16<2, LO>), dim3(grid), dim3(256), 0, s, A, sc, Ds, Y, g, nd8, b0, nb);
+      hipLaunchKernelGGL((gemm_cols_bf16<2, LO>), dim3(grid), dim3(kBf16Threads), 0, s, A, sc, Ds, Y, g, nd8, b0, nb);
     else
-      hipLaunchKernelGGL((gemm_cols_bf16<1, LO>), dim3(grid), dim3(256), 0, s, A, sc, Ds, Y, g, nd8, b0, nb);
+      hipLaunchKernelGGL((gemm_cols_bf16<1, LO>), dim3(grid), dim3(kBf16Threads), 0, s, A, sc, Ds, Y, g, nd8, b0, nb);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -369,7 +369,9 @@ __device__ __forceinline__ void cols_mixed_unit(const void* __restrict__ A,
 // waits for the vector loads (which were issued first, so the block loads
 // stay in flight) to store them into the other buffer; one barrier per
 // chunk.  All wavefronts of the workgroup must call a unit together.
-constexpr int kWgTile = 64;  // rows (F) / columns (F*) per workgroup
+constexpr int kWgTile = 64;       // float64 units: rows (F) / columns (F*) per workgroup
+constexpr int kBf16Threads = 512;  // bfloat16 units: 8 wavefronts per workgroup
+constexpr int kBf16Tile = 128;     // bfloat16 units: rows (F) / columns (F*) per workgroup
 constexpr int kXcds = 8;
 
 // LDS bytes of the double stage buffer for 16 NT right-hand sides.
@@ -417,18 +419,22 @@ __device__ __forceinline__ void stage_f64_store(const cpx<double> (&v)[2 * NT], 
   }
 }
 
-// bfloat16 planes: 8-entry parts of the 4 planes of each vector row.
-template <int NT>
+// bfloat16 planes: 8-entry parts of the 4 planes of each vector row
+// (256 NT parts per chunk), spread over TH threads, PER parts each.
+template <int NT, int TH>
+constexpr int parts_per_thread() { return (256 * NT + TH - 1) / TH; }
+
+template <int NT, int TH>
 __device__ __forceinline__ void stage_planes_load(const uint16_t* __restrict__ planes,
                                                   int64_t nf, int64_t k, int64_t n8, int64_t b0,
                                                   int nb, int64_t base, int64_t end,
-                                                  u4v (&v)[NT]) {
+                                                  u4v (&v)[parts_per_thread<NT, TH>()]) {
 #pragma unroll
-  for (int i = 0; i < NT; ++i) {
-    const int e = threadIdx.x + 256 * i;
+  for (int i = 0; i < parts_per_thread<NT, TH>(); ++i) {
+    const int e = threadIdx.x + TH * i;
     const int part = e & 3, plane = (e >> 2) & 3, b = e >> 4;
     const int64_t q = base + 8 * part;
-    const bool ok = b < nb && q < end;
+    const bool ok = e < 256 * NT && b < nb && q < end;
     v[i] = ld16(planes + (ok ? (((b0 + b) * nf + k) * 4 + plane) * n8 + q : 0));
   }
 }
@@ -441,14 +447,16 @@ __device__ __forceinline__ u4v stage_part(const u4v& v, int e, int nb, int64_t b
 
 // F*'s layout: s[(plane * 4 + part) * (16 NT + 1) + b] holds sensors
 // base + 8 part .. + 7 of one plane.
-template <int NT>
-__device__ __forceinline__ void stage_planes_store_cols(const u4v (&v)[NT], int nb, int64_t base,
-                                                        int64_t end, u4v* s) {
+template <int NT, int TH>
+__device__ __forceinline__ void stage_planes_store_cols(const u4v (&v)[parts_per_thread<NT, TH>()],
+                                                        int nb, int64_t base, int64_t end,
+                                                        u4v* s) {
   constexpr int PP = NT * 16 + 1;
 #pragma unroll
-  for (int i = 0; i < NT; ++i) {
-    const int e = threadIdx.x + 256 * i;
-    s[(((e >> 2) & 3) * 4 + (e & 3)) * PP + (e >> 4)] = stage_part(v[i], e, nb, base, end);
+  for (int i = 0; i < parts_per_thread<NT, TH>(); ++i) {
+    const int e = threadIdx.x + TH * i;
+    if (256 * NT % TH == 0 || e < 256 * NT)
+      s[(((e >> 2) & 3) * 4 + (e & 3)) * PP + (e >> 4)] = stage_part(v[i], e, nb, base, end);
   }
 }
 
@@ -463,13 +471,15 @@ __device__ __forceinline__ int row_slot_entry(int kg, int j) {
 // F's layout, slot order: s[(plane * 4 + kg) * (16 NT + 1) + b] holds the 8
 // values of slots 0..7 of lane group kg; each loaded part (8 consecutive
 // entries) is scattered as 4 pairs.
-template <int NT, bool LO>
-__device__ __forceinline__ void stage_planes_store_rows(const u4v (&v)[NT], int nb, int64_t base,
-                                                        int64_t end, u4v* s) {
+template <int NT, bool LO, int TH>
+__device__ __forceinline__ void stage_planes_store_rows(const u4v (&v)[parts_per_thread<NT, TH>()],
+                                                        int nb, int64_t base, int64_t end,
+                                                        u4v* s) {
   constexpr int PP = NT * 16 + 1;
 #pragma unroll
-  for (int i = 0; i < NT; ++i) {
-    const int e = threadIdx.x + 256 * i;
+  for (int i = 0; i < parts_per_thread<NT, TH>(); ++i) {
+    const int e = threadIdx.x + TH * i;
+    if (!(256 * NT % TH == 0 || e < 256 * NT)) continue;
     const int part = e & 3, plane = (e >> 2) & 3, b = e >> 4;
     const u4v x = stage_part(v[i], e, nb, base, end);
 #pragma unroll
@@ -698,11 +708,96 @@ __device__ __forceinline__ void mfma_cols_f64_wg(const cpx<double>* __restrict__
     }
 }
 
+// ---- bfloat16 matrix-core units.  The block loads run RING chunks ahead of
+// the products through a ring of registers (unrolled, so every ring slot is
+// a fixed register set): with a 32-entry chunk per step, one chunk in
+// flight per wavefront is far too little to cover loaded HBM latency at
+// these tile sizes, while the LDS vector stage is prefetched one chunk
+// ahead (it hits in L2).
+
+// Unpacked block operands of one chunk: real / imaginary hi parts, their
+// negations where a product needs them, and the lo parts.
+struct BlockOps {
+  u4v hr, hi, nhi, lr, li, nli;
+};
+
+template <bool LO>
+__device__ __forceinline__ BlockOps unpack_block(const uint32_t (&w0)[8], const uint32_t (&w1)[8]) {
+  BlockOps o;
+  o.hr = lows(w0);
+  o.hi = highs(w0);
+  o.nhi = neg(o.hi);
+  o.lr = o.li = o.nli = (u4v){0, 0, 0, 0};
+  if constexpr (LO) {
+    o.lr = lows(w1);
+    o.li = highs(w1);
+    o.nli = neg(o.li);
+  }
+  return o;
+}
+
+// F chunk: t[b] += Fhat[rows, chunk] X[chunk, b] for the 16 NT right-hand
+// sides; re: Hr xr - Hi xi, im: Hr xi + Hi xr, each with hi/lo splits.
+template <int NT, bool LO>
+__device__ __forceinline__ void rows_bf16_products(const BlockOps& a, const u4v* xs, int kg,
+                                                   int col, f4v (&tr)[NT], f4v (&ti)[NT]) {
+  constexpr int PP = NT * 16 + 1;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int b = t * 16 + col;
+    const u4v xrh = xs[(0 * 4 + kg) * PP + b], xrl = xs[(1 * 4 + kg) * PP + b];
+    const u4v xih = xs[(2 * 4 + kg) * PP + b], xil = xs[(3 * 4 + kg) * PP + b];
+    tr[t] = mma(a.hr, xrh, tr[t]);
+    ti[t] = mma(a.hr, xih, ti[t]);
+    tr[t] = mma(a.hr, xrl, tr[t]);
+    ti[t] = mma(a.hr, xil, ti[t]);
+    tr[t] = mma(a.nhi, xih, tr[t]);
+    ti[t] = mma(a.hi, xrh, ti[t]);
+    tr[t] = mma(a.nhi, xil, tr[t]);
+    ti[t] = mma(a.hi, xrl, ti[t]);
+    if constexpr (LO) {
+      tr[t] = mma(a.lr, xrh, tr[t]);
+      ti[t] = mma(a.lr, xih, ti[t]);
+      tr[t] = mma(a.nli, xih, tr[t]);
+      ti[t] = mma(a.li, xrh, ti[t]);
+    }
+  }
+}
+
+// F* chunk: x[b] += conj(f) d[b]: re = dr fr + di fi, im = di fr - dr fi.
+template <int MT, bool LO>
+__device__ __forceinline__ void cols_bf16_products(const BlockOps& f, const u4v* ds, int kg,
+                                                   int col, f4v (&xr)[MT], f4v (&xi)[MT]) {
+  constexpr int PP = MT * 16 + 1;
+#pragma unroll
+  for (int t = 0; t < MT; ++t) {
+    const int b = t * 16 + col;
+    const u4v drh = ds[(0 * 4 + kg) * PP + b], drl = ds[(1 * 4 + kg) * PP + b];
+    const u4v dih = ds[(2 * 4 + kg) * PP + b], dil = ds[(3 * 4 + kg) * PP + b];
+    xr[t] = mma(drh, f.hr, xr[t]);
+    xi[t] = mma(dih, f.hr, xi[t]);
+    xr[t] = mma(drl, f.hr, xr[t]);
+    xi[t] = mma(dil, f.hr, xi[t]);
+    xr[t] = mma(dih, f.hi, xr[t]);
+    xi[t] = mma(drh, f.nhi, xi[t]);
+    xr[t] = mma(dil, f.hi, xr[t]);
+    xi[t] = mma(drl, f.nhi, xi[t]);
+    if constexpr (LO) {
+      xr[t] = mma(drh, f.lr, xr[t]);
+      xi[t] = mma(dih, f.lr, xi[t]);
+      xr[t] = mma(dih, f.li, xr[t]);
+      xi[t] = mma(drh, f.nli, xi[t]);
+    }
+  }
+}
+
+// Default load ring depth (chunks in flight per wavefront).
+constexpr int kRing = 3;
+
 // F on the bfloat16 matrix cores.  The vector planes carry the column
 // sub-block scales already (folded in by the split kernel), so the whole
-// column chunk accumulates in float32 matrix-core accumulators; the real and
-// imaginary accumulation chains alternate.
-template <int NT, bool LO, bool VEC>
+// column chunk accumulates in float32 matrix-core accumulators.
+template <int NT, bool LO, bool VEC, int RING = kRing>
 __device__ __forceinline__ void mfma_rows_bf16_wg(const uint32_t* __restrict__ A,
                                                   const uint16_t* __restrict__ Xs,
                                                   cpx<double>* __restrict__ P, GemvShape g,
@@ -715,63 +810,49 @@ __device__ __forceinline__ void mfma_rows_bf16_wg(const uint32_t* __restrict__ A
   const int col = lane & 15, kg = lane >> 4;
   const int64_t p0 = pc * g.pc_len;
   const int64_t p1 = min(p0 + g.pc_len, g.Nm);
-  const int64_t row0 = mt * kWgTile + 16 * wave;
+  const int64_t nch = (p1 - p0 + 31) / 32;
+  const int64_t row0 = mt * kBf16Tile + 16 * wave;
   const uint32_t* __restrict__ Arow = A + (k * g.Nd + min(row0 + col, g.Nd - 1)) * g.Nm * WPE;
   f4v tr[NT], ti[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) tr[t] = ti[t] = (f4v){0, 0, 0, 0};
-  uint32_t w0[8], w1[8];
-  {
-    u4v v[NT];
-    stage_planes_load<NT>(Xs, g.nf, k, n8, b0, nb, p0, p1, v);
-    load_row_slots<LO, VEC>(Arow, p0, kg, p1, w0, w1);
-    stage_planes_store_rows<NT, LO>(v, nb, p0, p1, sx);
-  }
-  __syncthreads();
-  int cur = 0;
-  for (int64_t base = p0; base < p1; base += 32) {
-    const int64_t nend = base + 32 < p1 ? p1 : 0;  // 0: past the last chunk
-    // unpack this chunk's block words, then reuse them for the next loads
-    const u4v hr = lows(w0), hi = highs(w0);
-    const u4v nhi = neg(hi);
-    u4v lr = {0, 0, 0, 0}, li = {0, 0, 0, 0}, nli = {0, 0, 0, 0};
-    if constexpr (LO) {
-      lr = lows(w1);
-      li = highs(w1);
-      nli = neg(li);
-    }
-    u4v v[NT];
-    stage_planes_load<NT>(Xs, g.nf, k, n8, b0, nb, base + 32, nend, v);
-    __builtin_amdgcn_sched_barrier(0);  // vector loads first, then block loads
-    load_row_slots<LO, VEC>(Arow, base + 32, kg, nend, w0, w1);
-    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
-    const u4v* xs = sx + cur * BUF;
+  // chunk c uses ring slot c % RING for its block words and for its vector
+  // stage; both are loaded RING chunks ahead, vector part first, so every
+  // wait (in-order load counter) targets loads issued RING steps earlier.
+  uint32_t r0[RING][8], r1[RING][8];
+  constexpr int PER = parts_per_thread<NT, kBf16Threads>();
+  u4v xv[RING][PER];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      const int b = t * 16 + col;
-      const u4v xrh = xs[(0 * 4 + kg) * PP + b], xrl = xs[(1 * 4 + kg) * PP + b];
-      const u4v xih = xs[(2 * 4 + kg) * PP + b], xil = xs[(3 * 4 + kg) * PP + b];
-      // re: Hr xr - Hi xi ; im: Hr xi + Hi xr   (each with hi/lo splits)
-      tr[t] = mma(hr, xrh, tr[t]);
-      ti[t] = mma(hr, xih, ti[t]);
-      tr[t] = mma(hr, xrl, tr[t]);
-      ti[t] = mma(hr, xil, ti[t]);
-      tr[t] = mma(nhi, xih, tr[t]);
-      ti[t] = mma(hi, xrh, ti[t]);
-      tr[t] = mma(nhi, xil, tr[t]);
-      ti[t] = mma(hi, xrl, ti[t]);
-      if constexpr (LO) {
-        tr[t] = mma(lr, xrh, tr[t]);
-        ti[t] = mma(lr, xih, ti[t]);
-        tr[t] = mma(nli, xih, tr[t]);
-        ti[t] = mma(li, xrh, ti[t]);
-      }
-    }
-    __builtin_amdgcn_sched_barrier(0);  // the store waits for the vector loads: after the products
-    stage_planes_store_rows<NT, LO>(v, nb, base + 32, nend, sx + (cur ^ 1) * BUF);
+  for (int d = 0; d < RING; ++d)
+    stage_planes_load<NT, kBf16Threads>(Xs, g.nf, k, n8, b0, nb, p0 + 32 * d, d < nch ? p1 : 0, xv[d]);
+#pragma unroll
+  for (int d = 0; d < RING; ++d)
+    load_row_slots<LO, VEC>(Arow, p0 + 32 * d, kg, d < nch ? p1 : 0, r0[d], r1[d]);
+  stage_planes_store_rows<NT, LO, kBf16Threads>(xv[0], nb, p0, p1, sx);
+  __syncthreads();
+  // the main loop runs whole ring turns (straight-line, so the compiler's
+  // waits track each slot exactly), the tail the remaining chunks
+  auto step = [&](int64_t c, int d) {
+    const int64_t base = p0 + 32 * c;
+    const BlockOps a = unpack_block<LO>(r0[d], r1[d]);
+    const int64_t ahead = base + 32 * RING, aend = c + RING < nch ? p1 : 0;
+    stage_planes_load<NT, kBf16Threads>(Xs, g.nf, k, n8, b0, nb, ahead, aend, xv[d]);
+    load_row_slots<LO, VEC>(Arow, ahead, kg, aend, r0[d], r1[d]);
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+    rows_bf16_products<NT, LO>(a, sx + (c & 1) * BUF, kg, col, tr, ti);
+    __builtin_amdgcn_sched_barrier(0);  // the store waits for its loads: after the products
+    stage_planes_store_rows<NT, LO, kBf16Threads>(xv[(d + 1) % RING], nb, base + 32, c + 1 < nch ? p1 : 0,
+                                    sx + ((c + 1) & 1) * BUF);
     __syncthreads();
-    cur ^= 1;
+  };
+  const int64_t nfull = nch / RING * RING;
+  for (int64_t c0 = 0; c0 < nfull; c0 += RING) {
+#pragma unroll
+    for (int d = 0; d < RING; ++d) step(c0 + d, d);
   }
+#pragma unroll
+  for (int d = 0; d < RING - 1; ++d)
+    if (nfull + d < nch) step(nfull + d, d);
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int b = t * 16 + col;
@@ -787,7 +868,7 @@ __device__ __forceinline__ void mfma_rows_bf16_wg(const uint32_t* __restrict__ A
 
 // F* on the bfloat16 matrix cores: X^T = Dhat^T conj(Fhat), contraction over
 // all sensors; the column scale is applied to the float32 result.
-template <int MT, bool LO>
+template <int MT, bool LO, int RING = kRing>
 __device__ __forceinline__ void mfma_cols_bf16_wg(const uint32_t* __restrict__ A,
                                                   const float* __restrict__ scales,
                                                   const uint16_t* __restrict__ Ds,
@@ -799,63 +880,45 @@ __device__ __forceinline__ void mfma_cols_bf16_wg(const uint32_t* __restrict__ A
   u4v* sd = static_cast<u4v*>(lds);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, kg = lane >> 4;
-  const int64_t col0 = pt * kWgTile + 16 * wave;
+  const int64_t nch = (g.Nd + 31) / 32;
+  const int64_t col0 = pt * kBf16Tile + 16 * wave;
   const uint32_t* __restrict__ Ak = A + (k * g.Nd * g.Nm + min(col0 + col, g.Nm - 1)) * WPE;
   f4v xr[MT], xi[MT];
 #pragma unroll
   for (int t = 0; t < MT; ++t) xr[t] = xi[t] = (f4v){0, 0, 0, 0};
-  uint32_t w0[8], w1[8];
-  {
-    u4v v[MT];
-    stage_planes_load<MT>(Ds, g.nf, k, nd8, b0, nb, 0, g.Nd, v);
-    load_col8<LO>(Ak, 8 * kg, g.Nd, g.Nm, w0, w1);
-    stage_planes_store_cols<MT>(v, nb, 0, g.Nd, sd);
-  }
-  __syncthreads();
-  int cur = 0;
-  for (int64_t base = 0; base < g.Nd; base += 32) {
-    const int64_t nend = base + 32 < g.Nd ? g.Nd : 0;  // 0: past the last chunk
-    // unpack this chunk's block words, then reuse them for the next loads
-    const u4v fr = lows(w0), fi = highs(w0);
-    const u4v nfi = neg(fi);
-    u4v lr = {0, 0, 0, 0}, li = {0, 0, 0, 0}, nli = {0, 0, 0, 0};
-    if constexpr (LO) {
-      lr = lows(w1);
-      li = highs(w1);
-      nli = neg(li);
-    }
-    u4v v[MT];
-    stage_planes_load<MT>(Ds, g.nf, k, nd8, b0, nb, base + 32, nend, v);
-    __builtin_amdgcn_sched_barrier(0);  // vector loads first, then block loads
-    load_col8<LO>(Ak, base + 32 + 8 * kg, nend, g.Nm, w0, w1);
-    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
-    const u4v* ds = sd + cur * BUF;
+  // ring and loop structure as in the F unit
+  uint32_t r0[RING][8], r1[RING][8];
+  constexpr int PER = parts_per_thread<MT, kBf16Threads>();
+  u4v dv[RING][PER];
 #pragma unroll
-    for (int t = 0; t < MT; ++t) {
-      const int b = t * 16 + col;
-      const u4v drh = ds[(0 * 4 + kg) * PP + b], drl = ds[(1 * 4 + kg) * PP + b];
-      const u4v dih = ds[(2 * 4 + kg) * PP + b], dil = ds[(3 * 4 + kg) * PP + b];
-      // x += conj(f) d: re = dr fr + di fi ; im = di fr - dr fi
-      xr[t] = mma(drh, fr, xr[t]);
-      xi[t] = mma(dih, fr, xi[t]);
-      xr[t] = mma(drl, fr, xr[t]);
-      xi[t] = mma(dil, fr, xi[t]);
-      xr[t] = mma(dih, fi, xr[t]);
-      xi[t] = mma(drh, nfi, xi[t]);
-      xr[t] = mma(dil, fi, xr[t]);
-      xi[t] = mma(drl, nfi, xi[t]);
-      if constexpr (LO) {
-        xr[t] = mma(drh, lr, xr[t]);
-        xi[t] = mma(dih, lr, xi[t]);
-        xr[t] = mma(dih, li, xr[t]);
-        xi[t] = mma(drh, nli, xi[t]);
-      }
-    }
-    __builtin_amdgcn_sched_barrier(0);  // the store waits for the vector loads: after the products
-    stage_planes_store_cols<MT>(v, nb, base + 32, nend, sd + (cur ^ 1) * BUF);
+  for (int d = 0; d < RING; ++d)
+    stage_planes_load<MT, kBf16Threads>(Ds, g.nf, k, nd8, b0, nb, 32 * d, d < nch ? g.Nd : 0, dv[d]);
+#pragma unroll
+  for (int d = 0; d < RING; ++d)
+    load_col8<LO>(Ak, 32 * d + 8 * kg, d < nch ? g.Nd : 0, g.Nm, r0[d], r1[d]);
+  stage_planes_store_cols<MT, kBf16Threads>(dv[0], nb, 0, g.Nd, sd);
+  __syncthreads();
+  auto step = [&](int64_t c, int d) {
+    const int64_t base = 32 * c;
+    const BlockOps f = unpack_block<LO>(r0[d], r1[d]);
+    const int64_t ahead = base + 32 * RING, aend = c + RING < nch ? g.Nd : 0;
+    stage_planes_load<MT, kBf16Threads>(Ds, g.nf, k, nd8, b0, nb, ahead, aend, dv[d]);
+    load_col8<LO>(Ak, ahead + 8 * kg, aend, g.Nm, r0[d], r1[d]);
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+    cols_bf16_products<MT, LO>(f, sd + (c & 1) * BUF, kg, col, xr, xi);
+    __builtin_amdgcn_sched_barrier(0);  // the store waits for its loads: after the products
+    stage_planes_store_cols<MT, kBf16Threads>(dv[(d + 1) % RING], nb, base + 32, c + 1 < nch ? g.Nd : 0,
+                                sd + ((c + 1) & 1) * BUF);
     __syncthreads();
-    cur ^= 1;
+  };
+  const int64_t nfull = nch / RING * RING;
+  for (int64_t c0 = 0; c0 < nfull; c0 += RING) {
+#pragma unroll
+    for (int d = 0; d < RING; ++d) step(c0 + d, d);
   }
+#pragma unroll
+  for (int d = 0; d < RING - 1; ++d)
+    if (nfull + d < nch) step(nfull + d, d);
   const int64_t p = col0 + col;
   if (p >= g.Nm) return;
   const int64_t ntiles = (g.Nm + kScaleTile - 1) / kScaleTile;
