@@ -88,20 +88,30 @@ int64_t round8(int64_t n) { return (n + 7) / 8 * 8; }
 // F*: a = transformed x [nrhs][nf][Nd], b = product      [nrhs][nf][Nm]
 // mixed plans: c = a split into bfloat16 planes [nrhs][nf][4][round8(n_in)]
 // for the matrix-core product.
+bool use_mfma(const p2o_plan_s* h, p2o_op op, int64_t nrhs) {
+  if (h->mfma_min_rhs[op] <= 0 || nrhs < h->mfma_min_rhs[op]) return false;
+  return h->prec == P2O_FP64 || h->prec == P2O_MIXED_BF16 || h->prec == P2O_FAST_BF16;
+}
+
+// bfloat16 matrix-core products: the forward transform writes the operand
+// planes directly (no float32 spectra in between).
+bool planes_path(const p2o_plan_s* h, p2o_op op, int64_t nrhs) {
+  return is_mixed(h->prec) && use_mfma(h, op, nrhs);
+}
+
 WsLayout ws_layout(const p2o_plan_s* h, p2o_op op, int64_t nrhs) {
-  const bool mixed = is_mixed(h->prec);
-  const size_t vb = mixed ? 8 : 16;  // complex vector entry
+  const bool planes = planes_path(h, op, nrhs);
+  const size_t vb = is_mixed(h->prec) ? 8 : 16;  // complex vector entry
   const int64_t nin = (op == P2O_F) ? h->Nm : h->Nd;
+  const size_t a_bytes = planes ? 0 : (size_t)nrhs * h->nf * nin * vb;
+  const size_t b_bytes = (op == P2O_F) ? (size_t)nrhs * h->n_pc * h->nf * h->Nd * 16
+                                       : (size_t)nrhs * h->nf * h->Nm * vb;
+  const size_t c_bytes = planes ? (size_t)nrhs * h->nf * 4 * round8(nin) * 2 : 0;
   WsLayout w{};
   w.a_off = 0;
-  if (op == P2O_F) {
-    w.b_off = align_up((size_t)nrhs * h->nf * h->Nm * vb);
-    w.c_off = w.b_off + align_up((size_t)nrhs * h->n_pc * h->nf * h->Nd * 16);
-  } else {
-    w.b_off = align_up((size_t)nrhs * h->nf * h->Nd * vb);
-    w.c_off = w.b_off + align_up((size_t)nrhs * h->nf * h->Nm * vb);
-  }
-  w.total = w.c_off + (mixed ? align_up((size_t)nrhs * h->nf * 4 * round8(nin) * 2) : 0);
+  w.b_off = align_up(a_bytes);
+  w.c_off = w.b_off + align_up(b_bytes);
+  w.total = w.c_off + align_up(c_bytes);
   return w;
 }
 
@@ -274,11 +284,6 @@ int default_cfg(const p2o_plan_s* h, p2o_op op) {
 // The frequency-block product of `op` with candidate `cfg`; `a` is the
 // transformed input, `b` the product (F: partial spectra), `c` scratch for
 // the bfloat16 operand planes of the mixed matrix-core path.
-bool use_mfma(const p2o_plan_s* h, p2o_op op, int64_t nrhs) {
-  if (h->mfma_min_rhs[op] <= 0 || nrhs < h->mfma_min_rhs[op]) return false;
-  return h->prec == P2O_FP64 || h->prec == P2O_MIXED_BF16 || h->prec == P2O_FAST_BF16;
-}
-
 hipError_t launch_product(const p2o_plan_s* h, p2o_op op, void* a, void* b, void* c,
                           int64_t nrhs, int cfg, hipStream_t s) {
   GemvShape g{h->nf, h->Nd, h->Nm, nrhs, (int)h->n_pc, h->pc_len};
@@ -300,13 +305,9 @@ hipError_t launch_product(const p2o_plan_s* h, p2o_op op, void* a, void* b, void
   }
   const Fmt16 fmt = fmt_of(h->prec);
   const bool lo = uses_lo(h->prec);
-  if (mfma) {
+  if (mfma) {  // operand planes written by the forward transform
     const int64_t nin = (op == P2O_F) ? h->Nm : h->Nd;
     auto* planes = static_cast<uint16_t*>(c);
-    hipError_t e = launch_split_bf16(static_cast<const cpx<float>*>(a), planes, nrhs * h->nf,
-                                     nin, round8(nin), op == P2O_F ? h->scales : nullptr,
-                                     h->nf, s);
-    if (e != hipSuccess) return e;
     if (op == P2O_F)
       return launch_gemm_rows_bf16(h->fhat, h->scales, planes, static_cast<cpx<double>*>(b),
                                    g, round8(nin), lo, s);
@@ -404,6 +405,13 @@ hipError_t enqueue_forward(const p2o_plan_s* h, p2o_op op, const double* x, int6
   f.out_batch = h->nf * nin;
   f.nparts = 1;
   f.scale = 1.0;
+  if (planes_path(h, op, nrhs)) {
+    f.out = nullptr;
+    f.planes = reinterpret_cast<uint16_t*>(static_cast<char*>(h->ws) + w.c_off);
+    f.n8 = round8(nin);
+    f.nbins = h->nf;
+    f.col_scales = (op == P2O_F) ? h->scales : nullptr;  // F's operand carries the scales
+  }
   if (!is_mixed(h->prec)) return launch_rfft_fwd_f64(h->fft, h->tw64, h->perm, f, nrhs, s);
   return launch_rfft_fwd_f32(h->fft, h->tw32, h->perm, f, nrhs, s);
 }
@@ -844,24 +852,14 @@ p2o_status batch_prepare(p2o_batch b, p2o_op op, const double* const* x, double*
 }
 
 // Enqueue one batched apply whose work table is already on the device:
-// every instance's forward transform (and bfloat16 operand split), one
-// persistent product launch, every instance's inverse transform.
+// every instance's forward transform (writing the bfloat16 operand planes
+// for matrix-core instances), one persistent product launch, every
+// instance's inverse transform.
 p2o_status batch_enqueue(p2o_batch b, p2o_op op, const double* const* x, double* const* y,
                          const int64_t* nrhs, const std::vector<BatchInst>& table,
                          const BatchInst* dev_table, int64_t total, hipStream_t s) {
   const size_t n = b->plans.size();
   for (size_t i = 0; i < n; ++i) TRY_HIP(enqueue_forward(b->plans[i], op, x[i], nrhs[i], s));
-  for (size_t i = 0; i < n; ++i) {
-    p2o_plan_s* h = b->plans[i];
-    if (table[i].path == kPathMatrix && is_mixed(h->prec)) {
-      const WsLayout w = ws_layout(h, op, nrhs[i]);
-      char* ws = static_cast<char*>(h->ws);
-      const int64_t nin = (op == P2O_F) ? h->Nm : h->Nd;
-      TRY_HIP(launch_split_bf16(reinterpret_cast<const cpx<float>*>(ws + w.a_off),
-                                reinterpret_cast<uint16_t*>(ws + w.c_off), nrhs[i] * h->nf, nin,
-                                round8(nin), op == P2O_F ? h->scales : nullptr, h->nf, s));
-    }
-  }
   TRY_HIP(launch_batch_product(b->cls, op, dev_table, (int)n, total, s));
   for (size_t i = 0; i < n; ++i) TRY_HIP(enqueue_inverse(b->plans[i], op, y[i], nrhs[i], 1.0, s));
   return P2O_OK;

@@ -16,6 +16,7 @@
 // The inverse runs the same steps backwards and writes only the first Nt
 // real samples, which is the truncation back to the Toeplitz block.
 #include <cmath>
+#include <type_traits>
 
 #include "p2o_internal.h"
 
@@ -183,6 +184,61 @@ __device__ void dif_all_stages(cpx<T>* buf, const FftDesc& d,
 }
 
 // Forward: x (float64 rows 0..Nt-1 of each column) -> X[k], k = 0..N.
+// Bin k of the real transform from the half-length complex transform in
+// `buf`: X = a/2 - i w e / 2 with a = Zk + conj Zn, e = Zk - conj Zn.
+template <typename T>
+__device__ __forceinline__ cpx<T> split_bin(const cpx<T>* buf, const cpx<T>* __restrict__ tw,
+                                            const int* __restrict__ perm, int N, int logC,
+                                            int k, int c, T half) {
+  const int k1 = (k == N) ? 0 : k;
+  const int k2 = (k == 0) ? 0 : N - k;
+  const cpx<T> zk = buf[(perm[k1] << logC) + c];
+  const cpx<T> zn = buf[(perm[k2] << logC) + c];
+  const cpx<T> w = tw[k];
+  const T ar = zk.x + zn.x, ai = zk.y - zn.y;
+  const T er = zk.x - zn.x, ei = zk.y + zn.y;
+  const T wer = w.x * er - w.y * ei, wei = w.x * ei + w.y * er;
+  return {half * (ar + wei), half * (ai - wer)};
+}
+
+// Bins written as four bfloat16 planes per (batch, bin): re hi, re lo,
+// im hi, im lo (x = hi + lo, each rounded to nearest even), after the
+// optional power-of-two column scale (exact).  The block holding the last
+// columns also zeroes the padding columns ncols..n8-1.
+__device__ __forceinline__ void write_planes(const cpx<float>* buf, const cpx<float>* __restrict__ tw,
+                                             const int* __restrict__ perm, const FftIo& io,
+                                             int logC, int N, int ncol, int64_t c0, int64_t b,
+                                             int tid, int nthr) {
+  const int C = 1 << logC;
+  uint16_t* __restrict__ pl = io.planes + b * io.nbins * 4 * io.n8;
+  const int64_t tiles = (io.ncols + kScaleTile - 1) / kScaleTile;
+  for (int idx = tid; idx < ((N + 1) << logC); idx += nthr) {
+    const int k = idx >> logC, c = idx & (C - 1);
+    if (c >= ncol) continue;
+    cpx<float> v = split_bin<float>(buf, tw, perm, N, logC, k, c, 0.5f);
+    if (io.col_scales) {
+      const float sc = io.col_scales[k * tiles + (c0 + c) / kScaleTile];
+      v.x *= sc;
+      v.y *= sc;
+    }
+    const uint16_t rh = bf16_rne(v.x), ih = bf16_rne(v.y);
+    const uint16_t rl = bf16_rne(v.x - __uint_as_float((uint32_t)rh << 16));
+    const uint16_t il = bf16_rne(v.y - __uint_as_float((uint32_t)ih << 16));
+    uint16_t* o = pl + (int64_t)k * 4 * io.n8 + c0 + c;
+    o[0] = rh;
+    o[io.n8] = rl;
+    o[2 * io.n8] = ih;
+    o[3 * io.n8] = il;
+  }
+  if (c0 + C >= io.ncols) {
+    const int pad = (int)(io.n8 - io.ncols);
+    for (int idx = tid; idx < (N + 1) * 4 * pad; idx += nthr) {
+      const int row = idx / pad;  // k * 4 + plane
+      pl[(int64_t)row * io.n8 + io.ncols + idx % pad] = 0;
+    }
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(512)
 rfft_fwd_kernel(FftDesc d, const cpx<T>* __restrict__ tw,
@@ -212,19 +268,16 @@ rfft_fwd_kernel(FftDesc d, const cpx<T>* __restrict__ tw,
   dif_all_stages<T>(buf, d, tw, false, logC, tid, nthr);
 
   const T half = (T)0.5;
+  if constexpr (std::is_same<T, float>::value) {
+    if (io.planes) {
+      write_planes(buf, tw, perm, io, logC, N, ncol, c0, b, tid, nthr);
+      return;
+    }
+  }
   for (int idx = tid; idx < ((N + 1) << logC); idx += nthr) {
     const int k = idx >> logC, c = idx & (C - 1);
     if (c >= ncol) continue;
-    const int k1 = (k == N) ? 0 : k;
-    const int k2 = (k == 0) ? 0 : N - k;
-    const cpx<T> zk = buf[(perm[k1] << logC) + c];
-    const cpx<T> zn = buf[(perm[k2] << logC) + c];
-    const cpx<T> w = tw[k];
-    // a = Zk + conj Zn, e = Zk - conj Zn, X = a/2 - i w e / 2
-    const T ar = zk.x + zn.x, ai = zk.y - zn.y;
-    const T er = zk.x - zn.x, ei = zk.y + zn.y;
-    const T wer = w.x * er - w.y * ei, wei = w.x * ei + w.y * er;
-    out[(int64_t)k * io.out_row + c] = {half * (ar + wei), half * (ai - wer)};
+    out[(int64_t)k * io.out_row + c] = split_bin<T>(buf, tw, perm, N, logC, k, c, half);
   }
 }
 

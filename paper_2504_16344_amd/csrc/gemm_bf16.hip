@@ -25,8 +25,9 @@
 // F* ("cols"): X^T = Dhat^T conj(Fhat): workgroup = (16 MT) right-hand
 //    sides x 128 columns; contraction over all sensors; the column scale is
 //    applied to the float32 result.
-// Vector operands come pre-split in four bfloat16 planes per (rhs, k):
-// [re hi][re lo][im hi][im lo], each padded to a multiple of 8 entries.
+// Vector operands arrive as four bfloat16 planes per (rhs, k), written by
+// the forward transform: [re hi][re lo][im hi][im lo], each padded to a
+// multiple of 8 entries.
 #include "product_units.h"
 
 namespace p2o {
@@ -56,43 +57,6 @@ gemm_cols_bf16(const uint32_t* __restrict__ A, const float* __restrict__ scales,
   const int64_t k = tile / npt;
   if (k >= g.nf) return;
   mfma_cols_bf16_wg<MT, LO>(A, scales, Ds, Y, g, nd8, b0, nb, k, tile % npt, lds);
-}
-
-__device__ __forceinline__ uint16_t bf16_rne(float x) {
-  const uint32_t u = __float_as_uint(x);
-  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
-
-// in: [count][n] complex float32 -> out: [count][4][n8] bfloat16 planes
-// (re hi, re lo, im hi, im lo), zero in the padding n..n8-1.  With `scales`
-// (F's operand), entry e of row c = b * nf + k is first multiplied by the
-// power-of-two scale of sub-block (k, e / 256), which is exact.
-__global__ void __launch_bounds__(256)
-split_bf16(const cpx<float>* __restrict__ in, uint16_t* __restrict__ out, int64_t count,
-           int64_t n, int64_t n8, const float* __restrict__ scales, int64_t nf) {
-  const int64_t total = count * n8;
-  const int64_t ntiles = (n + kScaleTile - 1) / kScaleTile;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t c = idx / n8, e = idx % n8;
-    cpx<float> v = {0.f, 0.f};
-    if (e < n) {
-      v = in[c * n + e];
-      if (scales) {
-        const float sc = scales[(c % nf) * ntiles + e / kScaleTile];
-        v.x *= sc;
-        v.y *= sc;
-      }
-    }
-    const uint16_t rh = bf16_rne(v.x), ih = bf16_rne(v.y);
-    const uint16_t rl = bf16_rne(v.x - __uint_as_float((uint32_t)rh << 16));
-    const uint16_t il = bf16_rne(v.y - __uint_as_float((uint32_t)ih << 16));
-    uint16_t* o = out + c * 4 * n8 + e;
-    o[0] = rh;
-    o[n8] = rl;
-    o[2 * n8] = ih;
-    o[3 * n8] = il;
-  }
 }
 
 unsigned padded_grid(int64_t tiles) { return (unsigned)((tiles + kXcds - 1) / kXcds * kXcds); }
@@ -135,21 +99,13 @@ hipError_t cols_passes(const uint32_t* A, const float* sc, const uint16_t* Ds,
 
 }  // namespace
 
-hipError_t launch_split_bf16(const cpx<float>* in, uint16_t* out, int64_t count, int64_t n,
-                             int64_t n8, const float* scales, int64_t nf, hipStream_t s) {
-  const int64_t total = count * n8;
-  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 1 << 20));
-  hipLaunchKernelGGL(split_bf16, dim3(g), dim3(256), 0, s, in, out, count, n, n8, scales, nf);
-  return hipGetLastError();
-}
-
 hipError_t launch_gemm_rows_bf16(const void* A, const float* scales, const uint16_t* Xs,
                                  cpx<double>* P, const GemvShape& g, int64_t n8, bool lo,
                                  hipStream_t s) {
   const auto* a = static_cast<const uint32_t*>(A);
   // 16-byte loads need every row start aligned: Nm even (hi+lo), Nm % 4 == 0 (hi only)
   const bool vec = lo ? (g.Nm % 2 == 0) : (g.Nm % 4 == 0);
-  (void)scales;  // folded into the vector planes by launch_split_bf16
+  (void)scales;  // folded into the vector planes by the forward transform
   if (lo) return vec ? rows_passes<true, true>(a, Xs, P, g, n8, s)
                      : rows_passes<true, false>(a, Xs, P, g, n8, s);
   return vec ? rows_passes<false, true>(a, Xs, P, g, n8, s)

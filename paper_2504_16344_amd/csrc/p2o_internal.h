@@ -25,6 +25,12 @@ struct cpx {
 // undone on the way out.  Output bins are 0..N (nf = N + 1).
 constexpr int kMaxStages = 24;
 
+// float32 -> bfloat16 bits, round to nearest even (finite inputs).
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
 struct FftDesc {
   int N;    // complex length L/2
   int L;    // real embedding length
@@ -48,6 +54,15 @@ struct FftIo {
   int nparts;          // inverse only: number of partial spectra summed
   int64_t part_stride; // inverse only: element stride between partials
   double scale;        // inverse only: output multiplier (1/L folded in)
+  // Forward float32 only: when `planes` is set, the bins are written as the
+  // four bfloat16 planes of the matrix-core products instead of to `out`:
+  // planes[((b nbins + k) 4 + q) n8 + c], q = re hi, re lo, im hi, im lo
+  // (x = hi + lo, each rounded to nearest even), optionally multiplied by
+  // the column sub-block scales first; padding columns ncols..n8-1 are zero.
+  uint16_t* planes;
+  int64_t n8;            // plane pitch (ncols rounded up to 8)
+  int64_t nbins;         // frequency bins per batch (nf)
+  const float* col_scales;  // [nbins][ceil(ncols / kScaleTile)] or nullptr
 };
 
 int64_t smooth_length(int64_t Nt);  // L: smallest even 7-smooth >= 2*Nt
@@ -123,11 +138,10 @@ hipError_t launch_gemm_cols_f64(const cpx<double>* A, const cpx<double>* D,
                                 cpx<double>* Y, const GemvShape& g, hipStream_t s);
 
 // Many right-hand sides on the bfloat16 matrix cores (bfloat16 block
-// storage).  Vector operands are pre-split by launch_split_bf16 into four
-// bfloat16 planes per (rhs, k), each of n8 = roundup(n, 8) entries.
-// scales: F's column sub-block scales (folded into the planes) or nullptr.
-hipError_t launch_split_bf16(const cpx<float>* in, uint16_t* out, int64_t count, int64_t n,
-                             int64_t n8, const float* scales, int64_t nf, hipStream_t s);
+// storage).  Vector operands are the four bfloat16 planes per (rhs, k)
+// written by the forward transform (FftIo::planes), each of
+// n8 = roundup(n, 8) entries; F's planes carry the column scales.
+
 hipError_t launch_gemm_rows_bf16(const void* A, const float* scales, const uint16_t* Xs,
                                  cpx<double>* P, const GemvShape& g, int64_t n8, bool lo,
                                  hipStream_t s);

@@ -795,7 +795,7 @@ __device__ __forceinline__ void cols_bf16_products(const BlockOps& f, const u4v*
 constexpr int kRing = 3;
 
 // F on the bfloat16 matrix cores.  The vector planes carry the column
-// sub-block scales already (folded in by the split kernel), so the whole
+// sub-block scales already (folded in by the forward transform), so the whole
 // column chunk accumulates in float32 matrix-core accumulators.
 template <int NT, bool LO, bool VEC, int RING = kRing>
 __device__ __forceinline__ void mfma_rows_bf16_wg(const uint32_t* __restrict__ A,
