@@ -31,6 +31,7 @@ PEAK_HBM_GBS = 8000.0
 ENTRY_BYTES = {"fp64": 16, "mixed_fp16": 8, "mixed_bf16": 8, "fast_bf16": 4}
 VEC_BYTES = {"fp64": 16, "mixed_fp16": 8, "mixed_bf16": 8, "fast_bf16": 8}
 SCALE_TILE = 256
+DEFAULT_PRECS = "mixed_bf16,fp64,mixed_fp16"
 
 
 def parse():
@@ -43,15 +44,18 @@ def parse():
     ap.add_argument("--Nt", type=int, default=420)
     ap.add_argument("--tau", type=float, default=80.0)
     ap.add_argument("--seed", type=int, default=3)
-    ap.add_argument("--precs", default="mixed_bf16,fp64,mixed_fp16")
+    ap.add_argument("--precs", default=DEFAULT_PRECS)
     ap.add_argument("--cpu-cols", type=int, default=40000,
                     help="columns of the workload the CPU oracle baseline runs on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-gb", type=float, default=4.0,
                     help="size of the plain device copy timed as the measured HBM ceiling")
-    ap.add_argument("--workload", default="single", choices=["single", "batch"],
+    ap.add_argument("--workload", default="single", choices=["single", "batch", "mrhs"],
                     help="single: the 600x40000x420 F+F* step (default); batch: 64 uneven "
-                         "instances with 1..256 right-hand sides each")
+                         "instances with 1..256 right-hand sides each; mrhs: one plan, "
+                         "--nrhs right-hand sides per apply (matrix-core products)")
+    ap.add_argument("--nrhs", type=int, default=64,
+                    help="mrhs workload: right-hand sides per apply")
     ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--budget-gb", type=float, default=200.0,
                     help="batch workload: device memory per wave of resident instances")
@@ -354,6 +358,146 @@ def bench_batch(args):
         out["rel_err_vs_fp64_max"] = max(errs)
     print(json.dumps(out), flush=True)
 
+PEAK_TFLOPS = {"fp64": 78.6, "mixed_bf16": 2500.0, "fast_bf16": 2500.0}
+# matrix-core flops per useful flop: bfloat16 hi+lo splits form H xh + H xl + Lo xh
+SPLIT_FACTOR = {"fp64": 1, "mixed_bf16": 3, "fast_bf16": 2}
+
+
+def mrhs_product_bytes(prec, op, Nd, Nm, nf, n_pc, B):
+    """Algorithmic HBM bytes of one matrix-core product launch sequence for B
+    right-hand sides: the blocks once per pass of 64, plus the vector operand
+    read and the product written, per right-hand side."""
+    passes = (B + 63) // 64
+    blocks = nf * Nd * Nm * ENTRY_BYTES[prec] * passes
+    scales = 0 if prec == "fp64" else nf * ((Nm + SCALE_TILE - 1) // SCALE_TILE) * 4 * passes
+    r8 = lambda n: (n + 7) // 8 * 8
+    if prec == "fp64":
+        vin = nf * (Nm if op == "F" else Nd) * 16
+        vout = n_pc * nf * Nd * 16 if op == "F" else nf * Nm * 16
+    else:  # four bfloat16 planes in; F partial spectra float64, F* float32 out
+        vin = nf * r8(Nm if op == "F" else Nd) * 8
+        vout = n_pc * nf * Nd * 16 if op == "F" else nf * Nm * 8
+    return blocks + scales + B * (vin + vout)
+
+
+def bench_mrhs(args):
+    """One plan at the 600 x 40000 x 420 shape, applies on --nrhs right-hand
+    sides: the per-frequency products run as complex GEMMs on the matrix
+    cores.  Reports per-op product-kernel times against the MFMA and HBM
+    rooflines, and the mixed paths' error against float64 on the same inputs."""
+    import torch
+    import p2o_synth as S
+    import paper_2504_16344_amd as P
+
+    Nd, Nm, Nt, B = args.Nd, args.Nm, args.Nt, args.nrhs
+    L = P.smooth_length(Nt)
+    nf = L // 2 + 1
+    n_pc = n_chunks(Nd, Nm, nf)
+    precs = [p.strip() for p in args.precs.split(",") if p.strip()]
+    if args.precs == DEFAULT_PRECS:
+        precs = ["mixed_bf16", "fp64"]
+    precs = [p for p in precs if p in PEAK_TFLOPS]
+    stream = torch.cuda.current_stream()
+    env_dev = torch.from_numpy(S.envelope(Nt, args.tau, 1.0 / np.sqrt(Nm))).cuda()
+    m = torch.empty((B, Nt, Nm), dtype=torch.float64, device="cuda")
+    d = torch.empty((B, Nt, Nd), dtype=torch.float64, device="cuda")
+    S.device_normals(m.data_ptr(), m.numel(), 0, args.seed, S.ARRAY_M, 1.0, stream.cuda_stream)
+    S.device_normals(d.data_ptr(), d.numel(), 0, args.seed, S.ARRAY_D, 1.0, stream.cuda_stream)
+    flops = 8 * nf * Nd * Nm * B
+    copy = measured_copy(torch, args.copy_gb) if args.copy_gb > 0 else None
+    results, ref = {}, None
+    order = (["fp64"] if "fp64" in precs else []) + [p for p in precs if p != "fp64"]
+    for prec in order:
+        plan = make_plan(P, S, torch, prec, Nd, Nm, Nt, env_dev, args.seed, stream)
+        plan.reserve(B)
+        yF = torch.empty((B, Nt, Nd), dtype=torch.float64, device="cuda")
+        yA = torch.empty((B, Nt, Nm), dtype=torch.float64, device="cuda")
+        for _ in range(args.warmup):
+            plan.F(m, out=yF)
+            plan.FT(d, out=yA)
+        torch.cuda.synchronize()
+        plan.set_kernel_timing(True)
+        plan.kernel_time(P.OP_F)
+        plan.kernel_time(P.OP_FADJ)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record()
+        for _ in range(args.steps):
+            plan.F(m, out=yF)
+        ev[1].record()
+        for _ in range(args.steps):
+            plan.FT(d, out=yA)
+        ev[2].record()
+        torch.cuda.synchronize()
+        kF, nF = plan.kernel_time(P.OP_F)
+        kA, nA = plan.kernel_time(P.OP_FADJ)
+        plan.set_kernel_timing(False)
+        r = {"apply_ms": {"F": ev[0].elapsed_time(ev[1]) / args.steps,
+                          "FADJ": ev[1].elapsed_time(ev[2]) / args.steps},
+             "product_kernel_ms": {"F": kF / max(nF, 1), "FADJ": kA / max(nA, 1)},
+             "roofline": {}}
+        for op in ("F", "FADJ"):
+            ms = r["product_kernel_ms"][op]
+            nbytes = mrhs_product_bytes(prec, op, Nd, Nm, nf, n_pc, B)
+            hw = flops * SPLIT_FACTOR[prec]
+            t_hbm = nbytes / (PEAK_HBM_GBS * 1e9)
+            t_mfma = hw / (PEAK_TFLOPS[prec] * 1e12)
+            gbs = nbytes / (ms * 1e-3) / 1e9
+            tfs = hw / (ms * 1e-3) / 1e12
+            if t_mfma >= t_hbm:
+                rf = {"bound": "mfma", "achieved": round(tfs, 2), "peak": PEAK_TFLOPS[prec],
+                      "unit": "TFLOP/s", "frac": round(tfs / PEAK_TFLOPS[prec], 4)}
+            else:
+                rf = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                      "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4)}
+            rf.update({"traffic": None, "avg_ms": round(ms, 4), "bytes_per_launch": nbytes,
+                       "mfma_flops_per_launch": hw, "hbm_gbs": round(gbs, 1),
+                       "mfma_tflops": round(tfs, 2),
+                       "mfma_frac": round(tfs / PEAK_TFLOPS[prec], 4)})
+            r["roofline"][op] = rf
+        r["ms_per_step"] = r["apply_ms"]["F"] + r["apply_ms"]["FADJ"]
+        r["step_bytes"] = (mrhs_product_bytes(prec, "F", Nd, Nm, nf, n_pc, B)
+                           + mrhs_product_bytes(prec, "FADJ", Nd, Nm, nf, 1, B)
+                           + B * (Nt * Nm * 8 * 2 + Nt * Nd * 8 * 2))
+        if prec == "fp64":
+            ref = (yF, yA)  # kept as the reference (no copy: the counter calibration
+            #                 takes the largest device copy in the run to be the 4 GB one)
+        elif ref is not None:
+            r["rel_err_vs_fp64"] = {
+                "F": (torch.linalg.norm(yF - ref[0]) / torch.linalg.norm(ref[0])).item(),
+                "FADJ": (torch.linalg.norm(yA - ref[1]) / torch.linalg.norm(ref[1])).item()}
+        results[prec] = r
+        print(f"[mrhs] {prec}: F {r['apply_ms']['F']:.2f} ms (product {r['product_kernel_ms']['F']:.2f}),"
+              f" F* {r['apply_ms']['FADJ']:.2f} ms (product {r['product_kernel_ms']['FADJ']:.2f})",
+              file=sys.stderr, flush=True)
+        plan.close()
+        del plan, yF, yA
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    head = precs[0]
+    h = results[head]
+    dom = max(("F", "FADJ"), key=lambda o: h["product_kernel_ms"][o])
+    out = {
+        "metric": "multi-RHS F/F* apply time and product-kernel roofline (matrix cores) "
+                  f"@Nd={Nd},Nt={Nt}; mixed vs FP64",
+        "value": round(h["step_bytes"] / (h["ms_per_step"] * 1e-3) / 1e9, 1),
+        "unit": "GB/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(h["ms_per_step"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "mixed_bf16": "bf16x2/f32", "fast_bf16": "bf16/f32"}[head],
+        "data": "synthetic (seeded counter-based normals, generated on device)",
+        "config": {"workload": f"p2o F+F* on {B} right-hand sides, Nd={Nd} Nm={Nm} Nt={Nt} "
+                               f"(L={L}, {nf} frequency blocks), precision {head}",
+                   "Nd": Nd, "Nm": Nm, "Nt": Nt, "nrhs": B, "precision": head},
+        "roofline": h["roofline"][dom],
+        "roofline_other": h["roofline"]["FADJ" if dom == "F" else "F"],
+        "paths": results,
+        "measured_copy": copy,
+    }
+    if "fp64" in results and head != "fp64":
+        out["speedup_vs_fp64"] = round(results["fp64"]["ms_per_step"] / h["ms_per_step"], 3)
+    print(json.dumps(out), flush=True)
+
 
 def bench_inversion(torch, S, P):
     """K = Gn + F Gp F* (20000 x 20000) and the posterior mean at the
@@ -402,6 +546,8 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "mrhs":
+        return bench_mrhs(args)
     import torch
     import p2o_synth as S
     import paper_2504_16344_amd as P

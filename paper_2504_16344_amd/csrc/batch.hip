@@ -11,7 +11,7 @@
 // Interleaving keeps every workgroup's mix of large and small instances
 // alike, and neighbouring workgroups on neighbouring tiles of one instance,
 // which share the vector operand in L2.
-#include "product_units.h"
+#include "matrix_units.h"
 
 namespace p2o {
 namespace {

@@ -28,7 +28,7 @@
 // Vector operands arrive as four bfloat16 planes per (rhs, k), written by
 // the forward transform: [re hi][re lo][im hi][im lo], each padded to a
 // multiple of 8 entries.
-#include "product_units.h"
+#include "matrix_units.h"
 
 namespace p2o {
 namespace {

@@ -23,7 +23,7 @@
 //    all sensors s, written straight to the transformed parameter vector.
 // Complex products use four real products each: re = ar br - ai bi,
 // im = ar bi + ai br (the minus sign is folded into an operand).
-#include "product_units.h"
+#include "matrix_units.h"
 
 namespace p2o {
 namespace {
