@@ -500,8 +500,10 @@ def bench_mrhs(args):
 
 
 def bench_inversion(torch, S, P):
-    """K = Gn + F Gp F* (20000 x 20000) and the posterior mean at the
-    100 x 5000 x 200 inversion workload: wall time of each call."""
+    """K = Gn + F Gp F* (20000 x 20000), the posterior mean, and the QoI
+    posterior (Q, Gamma_post(q)) with its online prediction q = Q d at the
+    100 x 5000 x 200 inversion workload with 21 QoI locations: wall time of
+    each call (the prediction by events)."""
     Nd, Nm, Nt, seed = 100, 5000, 200, 5
     stream = torch.cuda.current_stream()
     env = torch.from_numpy(S.envelope(Nt, 40.0, 1.0 / np.sqrt(Nm))).cuda()
@@ -529,13 +531,40 @@ def bench_inversion(torch, S, P):
     # MAP optimality residual F* Gn^-1 (F m - d) + m / Gp, relative to m / Gp
     g = plan.FT((plan.F(m) - d_obs) / s2) + m / 0.25
     res = (torch.linalg.norm(g) / torch.linalg.norm(m / 0.25)).item()
+    # Phases 3-4 with the paper's 21 QoI locations: Q and Gamma_post(q) from K's
+    # factor, then the online prediction q = Q d (HBM-bound: Q streamed once)
+    Nq = 21
+    planq = make_plan(P, S, torch, "fp64", Nq, Nm, Nt, env, seed + S.QOI_SEED_OFFSET, stream)
+    plan.qoi_precompute(planq, K, 0.25)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Q, Gq = plan.qoi_precompute(planq, K, 0.25)
+    torch.cuda.synchronize()
+    t_q = time.perf_counter() - t0
+    q = P.qoi_predict(Q, d_obs)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    reps = 20
+    ev[0].record()
+    for _ in range(reps):
+        P.qoi_predict(Q, d_obs)
+    ev[1].record()
+    torch.cuda.synchronize()
+    t_p = ev[0].elapsed_time(ev[1]) / reps * 1e-3
+    q_map = planq.F(m).reshape(-1)
+    e_q = (torch.linalg.norm(q - q_map) / torch.linalg.norm(q_map)).item()
+    q_bytes = Q.numel() * 8 + n * 8 + Nq * Nt * 8
+    planq.close()
     plan.close()
-    del K
+    del K, Q, Gq
     torch.cuda.empty_cache()
     units = n
-    return {"workload": f"Nd={Nd} Nm={Nm} Nt={Nt}, K {n}x{n} float64",
+    return {"workload": f"Nd={Nd} Nm={Nm} Nt={Nt}, K {n}x{n} float64; Nq={Nq} QoI locations",
             "hessian_assemble_s": round(t_k, 3), "unit_vectors_per_s": round(units / t_k, 1),
-            "posterior_solve_s": round(t_m, 3), "map_gradient_rel": res}
+            "posterior_solve_s": round(t_m, 3), "map_gradient_rel": res,
+            "qoi_precompute_s": round(t_q, 3),
+            "qoi_predict_ms": round(t_p * 1e3, 4),
+            "qoi_predict_hbm_gbs": round(q_bytes / t_p / 1e9, 1),
+            "qoi_predict_vs_fq_mmap_rel": e_q}
 
 
 def main():

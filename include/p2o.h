@@ -25,8 +25,9 @@
  *     blocks, the scales and its workspaces, and frees them in p2o_destroy.
  *   - `stream` is a hipStream_t (NULL = the null stream).  Every call is
  *     ordered on it and returns without waiting for the device, except the
- *     setup calls, p2o_reserve, p2o_autotune, p2o_hessian_assemble and
- *     p2o_posterior_solve, which may allocate or synchronise the stream.
+ *     setup calls, p2o_reserve, p2o_autotune, p2o_hessian_assemble,
+ *     p2o_posterior_solve and p2o_qoi_precompute, which may allocate or
+ *     synchronise the stream.
  *   - Errors are reported only through the return code; nothing is thrown
  *     across the ABI.  On any code other than P2O_OK the outputs are
  *     unspecified and the handle remains usable.  P2O_EHIP carries the HIP
@@ -226,6 +227,42 @@ p2o_status p2o_posterior_solve(p2o_handle h, double* K, const double* d,
                                double* m_out, int64_t nrhs, double prior_var,
                                int refine_steps, int64_t* failed_pivot,
                                void* stream);
+
+/* ---------------------------------------------- QoI prediction (FP64)
+ * The parameter-to-QoI (p2q) map Fq is another shift-invariant block
+ * Toeplitz operator, Nq forecast locations instead of Nd sensors (section
+ * "Real-time Bayesian inference and prediction framework"): set it up as an
+ * ordinary plan with Nd = Nq; p2o_apply(P2O_F) on it gives q = Fq m. */
+
+/* Phase 3 precomputations of the QoI posterior (zero prior mean,
+ * Gamma_prior = prior_var * I):
+ *   Q  = Fq Gamma_post F* Gamma_noise^{-1} = Fq Gamma_prior F* K^{-1}
+ *        (the data-to-QoI map; the two forms agree by Sherman-Morrison-
+ *        Woodbury), so that Q d = Fq m_map;
+ *   Gq = Fq Gamma_post Fq* = Fq Gamma_prior Fq* - Q (F Gamma_prior Fq*)
+ *        (the QoI posterior covariance), symmetrised.
+ * Formed from the N_t Nq unit vectors of QoI space with the F / F* machinery
+ * of p2o_hessian_assemble and one blocked solve with K's factor for all of
+ * them at once.
+ *   hF    the p2o plan (Nd, Nm, Nt), hq the p2q plan (Nq, Nm, Nt); both
+ *         P2O_FP64 and ready, with the same Nm and Nt (else P2O_EINVAL).
+ *   Kfac  device [(Nt*Nd)^2]: K after p2o_posterior_solve (its Cholesky
+ *         factor in the lower triangle; the upper triangle is not read).
+ *   Q     device [(Nt*Nq)][(Nt*Nd)] row-major, caller-allocated; row
+ *         t*Nq + q, column i*Nd + s.
+ *   Gq    device [(Nt*Nq)^2] row-major, caller-allocated.
+ * Allocates temporaries (the (Nt*Nq) x (Nt*Nd) matrix F Gamma_prior Fq*,
+ * plus up to ~8 GB of transform workspace) and synchronises `stream`. */
+p2o_status p2o_qoi_precompute(p2o_handle hF, p2o_handle hq, const double* Kfac,
+                              double prior_var, double* Q, double* Gq, void* stream);
+
+/* Phase 4 QoI prediction from data: q[r] = Q d[r] for r < nrhs.
+ *   Q  device [nq][n] row-major (from p2o_qoi_precompute: nq = Nt*Nq,
+ *      n = Nt*Nd); d device [nrhs][n]; q device [nrhs][nq].
+ * Stream-ordered, allocates nothing; P2O_EINVAL on null pointers or sizes
+ * below 1. */
+p2o_status p2o_qoi_predict(const double* Q, int64_t nq, int64_t n, const double* d, double* q,
+                           int64_t nrhs, void* stream);
 
 /* ------------------------------------------------------------ housekeeping */
 

@@ -1,5 +1,6 @@
-"""FP64 CPU oracle: the p2o map F, its adjoint F*, the data-space Hessian K
-and the posterior mean, each written as the plain definition from the paper.
+"""FP64 CPU oracle: the p2o map F, its adjoint F*, the data-space Hessian K,
+the posterior mean and the QoI posterior (data-to-QoI map Q and covariance
+Gamma_post(q)), each written as the plain definition from the paper.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).  No FFT, no blocking,
 no reordering beyond what the definitions state: the FFT method the product
@@ -27,7 +28,8 @@ __all__ = [
     "apply_F", "apply_Fadj", "apply_F_loops", "apply_Fadj_loops", "dense_F",
     "F_entry", "Fadj_entry", "hessian_dense", "hessian_gram",
     "hessian_column", "posterior_mean", "posterior_mean_normal_eq",
-    "misfit_gradient", "map_objective_gradient",
+    "misfit_gradient", "map_objective_gradient", "cross_gram", "qoi_maps",
+    "qoi_maps_parameter_space",
 ]
 
 
@@ -173,6 +175,52 @@ def hessian_column(blocks: np.ndarray, prior_var: float, noise_var, col: int) ->
     out = apply_F(blocks, prior_var * apply_Fadj(blocks, e)).reshape(-1)
     out[col] += _noise_diag(noise_var, Nt * Nd)[col]
     return out
+
+
+def cross_gram(blocks_a: np.ndarray, blocks_b: np.ndarray, prior_var: float) -> np.ndarray:
+    """prior_var Fa Fb^T for two block-Toeplitz maps on the same parameter
+    grid (same Nm, Nt), e.g. F Gamma_prior Fq^* of Phase 3: block (i, j) is
+    sum_{l<=min(i,j)} Fa_{i-l} Fb_{j-l}^T, by the recurrence of hessian_gram
+    applied to the Gram product of the two stacked block sets."""
+    Nt, Nda, Nm = _dims(blocks_a)
+    Ntb, Ndb, Nmb = _dims(blocks_b)
+    assert (Nt, Nm) == (Ntb, Nmb)
+    G = blocks_a.reshape(Nt * Nda, Nm) @ blocks_b.reshape(Nt * Ndb, Nm).T
+    for i in range(1, Nt):
+        G[i * Nda:(i + 1) * Nda, Ndb:] += G[(i - 1) * Nda:i * Nda, :-Ndb]
+    return prior_var * G
+
+
+def qoi_maps(blocks: np.ndarray, blocks_q: np.ndarray, prior_var: float,
+             noise_var) -> tuple[np.ndarray, np.ndarray]:
+    """Phase 3 of section "Real-time Bayesian inference and prediction
+    framework" (zero prior mean, Gamma_prior = prior_var I): the data-to-QoI
+    map Q = Fq Gamma_post F^* Gamma_noise^{-1} and the QoI posterior
+    covariance Gamma_post(q) = Fq Gamma_post Fq^*, both written through the
+    Sherman-Morrison-Woodbury form Gamma_post = Gamma_prior -
+    G^* K^{-1} G (G^* = Gamma_prior F^*): Q = Fq G^* K^{-1},
+    Gamma_post(q) = Fq Gamma_prior Fq^* - Q F Gamma_prior Fq^*.
+    Q: [(Nt Nq)][(Nt Nd)], Gamma_post(q): [(Nt Nq)]^2 (index t*N + s)."""
+    K = hessian_gram(blocks, prior_var, noise_var)
+    B = cross_gram(blocks, blocks_q, prior_var)        # F Gp Fq^*, (Nt Nd) x (Nt Nq)
+    KinvB = scipy.linalg.cho_solve(scipy.linalg.cho_factor(K, lower=True), B)
+    Q = KinvB.T                                        # K symmetric
+    Gq = cross_gram(blocks_q, blocks_q, prior_var) - B.T @ KinvB
+    return Q, Gq
+
+
+def qoi_maps_parameter_space(blocks: np.ndarray, blocks_q: np.ndarray, prior_var: float,
+                             noise_var) -> tuple[np.ndarray, np.ndarray]:
+    """The same two matrices from the parameter-space posterior covariance,
+    eq. Hessian: Gamma_post = (F^* Gn^{-1} F + Gp^{-1})^{-1}, then
+    Q = Fq Gamma_post F^* Gn^{-1} and Gamma_post(q) = Fq Gamma_post Fq^*
+    (dense F and Fq; tiny only)."""
+    Nt, Nd, Nm = _dims(blocks)
+    A, Aq = dense_F(blocks), dense_F(blocks_q)
+    ninv = 1.0 / _noise_diag(noise_var, Nt * Nd)
+    H = A.T @ (ninv[:, None] * A) + np.eye(Nt * Nm) / prior_var
+    post = np.linalg.inv(H)
+    return Aq @ post @ A.T * ninv[None, :], Aq @ post @ Aq.T
 
 
 def posterior_mean(blocks: np.ndarray, prior_var: float, noise_var,

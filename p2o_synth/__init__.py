@@ -48,6 +48,9 @@ ARRAY_D = 3
 ARRAY_NOISE = 4
 ARRAY_DIRECTION = 5
 ARRAY_SHAPES = 6
+# The p2q map's blocks are drawn like the p2o map's (array id ARRAY_BLOCKS)
+# under the workload seed plus this offset.
+QOI_SEED_OFFSET = 7919
 
 
 _CHUNK = 1 << 20

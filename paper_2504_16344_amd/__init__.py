@@ -16,7 +16,7 @@ import torch
 __all__ = [
     "Plan", "Batch", "Graph", "P2OError", "P2OApply", "P2OAdjoint", "load_library", "LIB_PATH",
     "FP64", "MIXED_FP16", "MIXED_BF16", "FAST_BF16", "OP_F", "OP_FADJ",
-    "smooth_length", "EXPORTED_SYMBOLS",
+    "smooth_length", "EXPORTED_SYMBOLS", "qoi_predict",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libp2o.so")
@@ -43,6 +43,8 @@ _SIGNATURES = {
     "p2o_hessian_assemble": (_int, [_vp, _dbl, _vp, _vp, _vp]),
     "p2o_posterior_solve": (_int, [_vp, _vp, _vp, _vp, _i64, _dbl, _int,
                                    _c.POINTER(_i64), _vp]),
+    "p2o_qoi_precompute": (_int, [_vp, _vp, _vp, _dbl, _vp, _vp, _vp]),
+    "p2o_qoi_predict": (_int, [_vp, _i64, _i64, _vp, _vp, _i64, _vp]),
     "p2o_destroy": (None, [_vp]),
     "p2o_status_string": (_c.c_char_p, [_int]),
     "p2o_last_hip_error": (_int, [_c.POINTER(_int)]),
@@ -255,6 +257,22 @@ class Plan:
         _check("p2o_posterior_solve", st)
         return out
 
+    def qoi_precompute(self, qoi_plan: "Plan", K: torch.Tensor, prior_var: float,
+                       stream=None):
+        """Phase 3 with this plan as the p2o map and `qoi_plan` as the p2q map:
+        (Q, Gq) with Q = Fq Gp F* K^{-1} ([(Nt Nq)][(Nt Nd)]) and
+        Gq = Fq Gamma_post Fq* ([(Nt Nq)]^2).  K: as left by posterior()."""
+        K = _dev_f64(K, "K")
+        n, nq = self.Nt * self.Nd, qoi_plan.Nt * qoi_plan.Nd
+        if tuple(K.shape) != (n, n):
+            raise ValueError(f"K must be ({n}, {n})")
+        Q = torch.empty((nq, n), dtype=torch.float64, device=K.device)
+        G = torch.empty((nq, nq), dtype=torch.float64, device=K.device)
+        _check("p2o_qoi_precompute", self._lib.p2o_qoi_precompute(
+            self._handle(), qoi_plan._handle(), K.data_ptr(), float(prior_var), Q.data_ptr(),
+            G.data_ptr(), _stream_handle(stream)))
+        return Q, G
+
     def autotune(self, op: int, reps: int = 3, stream=None):
         """Time every candidate product kernel for `op`; keep the fastest.
         Returns (chosen index, per-candidate ms list, -1 = not valid)."""
@@ -306,6 +324,22 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def qoi_predict(Q: torch.Tensor, d: torch.Tensor, stream=None) -> torch.Tensor:
+    """Phase 4 QoI prediction q = Q d.  Q: [nq][n]; d: [n] or [nrhs][...]
+    with n entries per right-hand side.  Returns [nq] or [nrhs][nq]."""
+    Q = _dev_f64(Q, "Q")
+    d = _dev_f64(d, "d")
+    nq, n = (int(v) for v in Q.shape)
+    single = d.numel() == n
+    nrhs = 1 if single else int(d.shape[0])
+    if d.numel() != nrhs * n:
+        raise ValueError(f"d must hold {n} entries per right-hand side")
+    q = torch.empty((nrhs, nq), dtype=torch.float64, device=Q.device)
+    _check("p2o_qoi_predict", load_library().p2o_qoi_predict(
+        Q.data_ptr(), nq, n, d.data_ptr(), q.data_ptr(), nrhs, _stream_handle(stream)))
+    return q[0] if single else q
 
 
 class Batch:

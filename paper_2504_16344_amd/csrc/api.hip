@@ -672,6 +672,90 @@ struct DevBufs {
   }
 };
 
+// Solves with K's Cholesky factor: the per-right-hand-side kernels for a
+// few right-hand sides, the blocked matrix-core variant for many.
+constexpr int64_t kSolveManyFrom = 16;
+hipError_t cholesky_solve(const double* K, double* Y, double* part, int64_t n, int64_t nrhs,
+                          hipStream_t s) {
+  if (nrhs >= kSolveManyFrom) return launch_cholesky_solve_many(K, Y, n, nrhs, s);
+  return launch_cholesky_solve(K, Y, part, n, nrhs, s);
+}
+
+bool same_time_grid(const p2o_plan_s* a, const p2o_plan_s* b) {
+  return a->Nt == b->Nt && a->Nm == b->Nm && a->L == b->L;
+}
+
+// Rows of hf's F applied after prior_var times ha's F*: for every unit
+// vector e_j of ha's data space (j = t N_d(ha) + s, all N_t N_d(ha) of them),
+// out[j * ldo + :] = F_hf (prior_var I) F_ha^* e_j, a vector of hf's data
+// space ([N_t][N_d(hf)]).  With ha = hf this is row j of K minus the noise
+// (Phase 2); with ha the p2q plan and hf the p2o plan it is column j of
+// F Gp Fq^*, with ha = hf = the p2q plan row j of Fq Gp Fq^* (Phase 3).
+// F* of a unit vector is a conjugated, phase-shifted row of ha's frequency
+// blocks (no product needed); then inverse transform (truncation to N_t
+// steps, times prior_var), forward transform, hf's F product over a batch
+// of unit vectors, inverse transform written straight into the rows.
+p2o_status assemble_rows(p2o_plan_s* ha, p2o_plan_s* hf, double prior_var, double* out,
+                         int64_t ldo, hipStream_t s) {
+  const int64_t n = ha->Nt * ha->Nd;
+  const int64_t Nm = hf->Nm;
+  // per unit vector: adjoint spectrum (reused for the refiltered parameter
+  // spectrum), time-domain parameter vector, partial data spectra
+  const size_t per = (size_t)hf->nf * Nm * 16 + (size_t)hf->Nt * Nm * 8 +
+                     (size_t)hf->n_pc * hf->nf * hf->Nd * 16;
+  const size_t budget = (size_t)8 << 30;
+  const int64_t B = std::max<int64_t>(1, std::min<int64_t>({n, 65535, (int64_t)(budget / per)}));
+  DevBufs bufs;
+  void *xh, *m, *parts;
+  TRY_HIP(bufs.alloc(&xh, (size_t)B * hf->nf * Nm * 16));
+  TRY_HIP(bufs.alloc(&m, (size_t)B * hf->Nt * Nm * 8));
+  TRY_HIP(bufs.alloc(&parts, (size_t)B * hf->n_pc * hf->nf * hf->Nd * 16));
+  for (int64_t j0 = 0; j0 < n; j0 += B) {
+    const int64_t nb = std::min(B, n - j0);
+    TRY_HIP(launch_unit_adjoint_spectra(static_cast<const cpx<double>*>(ha->fhat), ha->tw64,
+                                        static_cast<cpx<double>*>(xh), ha->nf, ha->Nd, Nm,
+                                        ha->L, j0, nb, s));
+    FftIo inv{};
+    inv.in = xh;
+    inv.out = m;
+    inv.ncols = Nm;
+    inv.in_row = Nm;
+    inv.in_batch = hf->nf * Nm;
+    inv.out_row = Nm;
+    inv.out_batch = hf->Nt * Nm;
+    inv.nparts = 1;
+    inv.scale = prior_var / (double)hf->L;
+    TRY_HIP(launch_rfft_inv_f64(hf->fft, hf->tw64, hf->perm, inv, nb, s));
+    FftIo fwd{};
+    fwd.in = m;
+    fwd.out = xh;
+    fwd.ncols = Nm;
+    fwd.in_row = Nm;
+    fwd.in_batch = hf->Nt * Nm;
+    fwd.out_row = Nm;
+    fwd.out_batch = hf->nf * Nm;
+    fwd.nparts = 1;
+    fwd.scale = 1.0;
+    TRY_HIP(launch_rfft_fwd_f64(hf->fft, hf->tw64, hf->perm, fwd, nb, s));
+    TRY_HIP(launch_product(hf, P2O_F, xh, parts, nullptr, nb, hf->cfg[P2O_F], s));
+    FftIo o{};
+    o.in = parts;
+    o.out = out + j0 * ldo;
+    o.ncols = hf->Nd;
+    o.in_row = hf->Nd;
+    o.nparts = (int)hf->n_pc;
+    o.part_stride = hf->nf * hf->Nd;
+    o.in_batch = hf->n_pc * hf->nf * hf->Nd;
+    o.out_row = hf->Nd;
+    o.out_batch = ldo;
+    o.scale = 1.0 / (double)hf->L;
+    TRY_HIP(launch_rfft_inv_f64(hf->fft, hf->tw64, hf->perm, o, nb, s));
+  }
+  // the scratch buffers are freed on return: finish their users first
+  TRY_HIP(hipStreamSynchronize(s));
+  return P2O_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -685,64 +769,43 @@ p2o_status p2o_hessian_assemble(p2o_handle h, double prior_var,
   (void)hipGetLastError();
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = h->Nt * h->Nd;
-  // per unit vector: adjoint spectrum (reused for the refiltered parameter
-  // spectrum), time-domain parameter vector, partial data spectra
-  const size_t per = (size_t)h->nf * h->Nm * 16 + (size_t)h->Nt * h->Nm * 8 +
-                     (size_t)h->n_pc * h->nf * h->Nd * 16;
-  const size_t budget = (size_t)8 << 30;
-  const int64_t B = std::max<int64_t>(1, std::min<int64_t>({n, 65535, (int64_t)(budget / per)}));
-  DevBufs bufs;
-  void *xh, *m, *parts;
-  TRY_HIP(bufs.alloc(&xh, (size_t)B * h->nf * h->Nm * 16));
-  TRY_HIP(bufs.alloc(&m, (size_t)B * h->Nt * h->Nm * 8));
-  TRY_HIP(bufs.alloc(&parts, (size_t)B * h->n_pc * h->nf * h->Nd * 16));
-  for (int64_t j0 = 0; j0 < n; j0 += B) {
-    const int64_t nb = std::min(B, n - j0);
-    // F* e_j for the unit vectors j0 .. j0+nb-1: spectra, then time domain
-    // (truncated to Nt steps) times prior_var
-    TRY_HIP(launch_unit_adjoint_spectra(static_cast<const cpx<double>*>(h->fhat), h->tw64,
-                                        static_cast<cpx<double>*>(xh), h->nf, h->Nd, h->Nm,
-                                        h->L, j0, nb, s));
-    FftIo inv{};
-    inv.in = xh;
-    inv.out = m;
-    inv.ncols = h->Nm;
-    inv.in_row = h->Nm;
-    inv.in_batch = h->nf * h->Nm;
-    inv.out_row = h->Nm;
-    inv.out_batch = h->Nt * h->Nm;
-    inv.nparts = 1;
-    inv.scale = prior_var / (double)h->L;
-    TRY_HIP(launch_rfft_inv_f64(h->fft, h->tw64, h->perm, inv, nb, s));
-    // F applied to those parameter vectors; row j of the result is K e_j
-    FftIo fwd{};
-    fwd.in = m;
-    fwd.out = xh;
-    fwd.ncols = h->Nm;
-    fwd.in_row = h->Nm;
-    fwd.in_batch = h->Nt * h->Nm;
-    fwd.out_row = h->Nm;
-    fwd.out_batch = h->nf * h->Nm;
-    fwd.nparts = 1;
-    fwd.scale = 1.0;
-    TRY_HIP(launch_rfft_fwd_f64(h->fft, h->tw64, h->perm, fwd, nb, s));
-    TRY_HIP(launch_product(h, P2O_F, xh, parts, nullptr, nb, h->cfg[P2O_F], s));
-    FftIo out{};
-    out.in = parts;
-    out.out = K + j0 * n;
-    out.ncols = h->Nd;
-    out.in_row = h->Nd;
-    out.nparts = (int)h->n_pc;
-    out.part_stride = h->nf * h->Nd;
-    out.in_batch = h->n_pc * h->nf * h->Nd;
-    out.out_row = h->Nd;
-    out.out_batch = n;
-    out.scale = 1.0 / (double)h->L;
-    TRY_HIP(launch_rfft_inv_f64(h->fft, h->tw64, h->perm, out, nb, s));
-  }
+  TRY_ST(assemble_rows(h, h, prior_var, K, n, s));
   TRY_HIP(launch_add_diagonal(K, noise_var, n, s));
   TRY_HIP(launch_symmetrize(K, n, s));
   TRY_HIP(hipStreamSynchronize(s));
+  return P2O_OK;
+}
+
+p2o_status p2o_qoi_precompute(p2o_handle hF, p2o_handle hq, const double* Kfac,
+                              double prior_var, double* Q, double* Gq, void* stream) {
+  if (!hF || !hq || !Kfac || !Q || !Gq) return P2O_EINVAL;
+  if (!hF->ready || !hq->ready) return P2O_ESTATE;
+  if (hF->prec != P2O_FP64 || hq->prec != P2O_FP64) return P2O_EUNSUPPORTED;
+  if (!same_time_grid(hF, hq)) return P2O_EINVAL;
+  (void)hipGetLastError();
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = hF->Nt * hF->Nd, nq = hq->Nt * hq->Nd;
+  DevBufs bufs;
+  void* bt;  // rows j: F Gp Fq^* e_j (columns of B = F Gp Fq^*)
+  TRY_HIP(bufs.alloc(&bt, (size_t)nq * n * 8));
+  double* Bt = static_cast<double*>(bt);
+  TRY_ST(assemble_rows(hq, hF, prior_var, Bt, n, s));
+  TRY_ST(assemble_rows(hq, hq, prior_var, Gq, nq, s));  // Fq Gp Fq^*
+  // Q = Fq Gp F^* K^{-1} = (K^{-1} B)^T: row j of Q is K^{-1} (column j of B)
+  TRY_HIP(hipMemcpyAsync(Q, Bt, (size_t)nq * n * 8, hipMemcpyDeviceToDevice, s));
+  TRY_HIP(launch_cholesky_solve_many(Kfac, Q, n, nq, s));
+  // Gq = Fq Gp Fq^* - Q B
+  TRY_HIP(launch_dgemm(true, nq, nq, n, -1.0, Q, n, Bt, n, Gq, nq, s));
+  TRY_HIP(launch_symmetrize(Gq, nq, s));
+  TRY_HIP(hipStreamSynchronize(s));
+  return P2O_OK;
+}
+
+p2o_status p2o_qoi_predict(const double* Q, int64_t nq, int64_t n, const double* d, double* q,
+                           int64_t nrhs, void* stream) {
+  if (!Q || !d || !q || nq < 1 || n < 1 || nrhs < 1) return P2O_EINVAL;
+  (void)hipGetLastError();
+  TRY_HIP(launch_qoi_gemv(Q, d, q, nq, n, nrhs, (hipStream_t)stream));
   return P2O_OK;
 }
 
@@ -781,11 +844,11 @@ p2o_status p2o_posterior_solve(p2o_handle h, double* K, const double* d,
   double* X = static_cast<double*>(x);
   double* Rr = static_cast<double*>(r);
   TRY_HIP(hipMemcpyAsync(X, d, (size_t)nrhs * n * 8, hipMemcpyDeviceToDevice, s));
-  TRY_HIP(launch_cholesky_solve(K, X, static_cast<double*>(psolve), n, nrhs, s));
+  TRY_HIP(cholesky_solve(K, X, static_cast<double*>(psolve), n, nrhs, s));
   for (int it = 0; it < refine_steps; ++it) {
     TRY_HIP(launch_residual(K, static_cast<const double*>(diag), d, X, Rr,
                             static_cast<double*>(rows), static_cast<double*>(psymv), n, nrhs, s));
-    TRY_HIP(launch_cholesky_solve(K, Rr, static_cast<double*>(psolve), n, nrhs, s));
+    TRY_HIP(cholesky_solve(K, Rr, static_cast<double*>(psolve), n, nrhs, s));
     TRY_HIP(launch_axpy(X, Rr, 1.0, nrhs * n, s));
   }
   TRY_ST(ensure_ws(h, nrhs));

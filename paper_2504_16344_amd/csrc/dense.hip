@@ -1,0 +1,237 @@
+// Dense float64 linear algebra on the data and QoI spaces (section "Real-time
+// Bayesian inference and prediction framework", Phases 2-4): a matrix-core
+// GEMM, triangular solves with the Cholesky factor of K for many
+// right-hand sides at once (the N_q N_t unit vectors of the QoI
+// precomputation), and the online QoI prediction q = Q d.
+#include "matrix_units.h"
+
+namespace p2o {
+namespace {
+
+constexpr int kGemmTile = 64;  // C tile per workgroup (rows and columns)
+constexpr int kGemmK = 16;     // contraction chunk staged in LDS
+constexpr int kTriNb = 64;     // triangular-solve block (the Cholesky block size)
+
+// C[i][j] += alpha sum_k A[i][k] op(B)[k][j] for i < M, j < N, row-major,
+// op(B)[k][j] = B[j][k] (TRANSB) or B[k][j].  A workgroup owns a 64 x 64
+// tile of C, each of its 4 wavefronts a 32 x 32 quarter (2 x 2
+// v_mfma_f64_16x16x4 tiles); 16-entry chunks of the contraction are staged
+// in LDS as [k][row] for both operands.
+template <bool TRANSB>
+__global__ void __launch_bounds__(256)
+dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A,
+             int64_t lda, const double* __restrict__ B, int64_t ldb, double* __restrict__ C,
+             int64_t ldc) {
+  __shared__ double sa[kGemmK][kGemmTile + 1];
+  __shared__ double sb[kGemmK][kGemmTile + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  const int64_t i0 = (int64_t)blockIdx.y * kGemmTile, j0 = (int64_t)blockIdx.x * kGemmTile;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  d4v acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (d4v){0, 0, 0, 0};
+  for (int64_t k0 = 0; k0 < K; k0 += kGemmK) {
+    {  // A: 64 rows x 16 contraction entries, 4 consecutive entries a thread
+      const int r = tid >> 2, kk = (tid & 3) * 4;
+      const int64_t gi = i0 + r;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t gk = k0 + kk + e;
+        sa[kk + e][r] = (gi < M && gk < K) ? A[gi * lda + gk] : 0.0;
+      }
+    }
+    if constexpr (TRANSB) {
+      const int r = tid >> 2, kk = (tid & 3) * 4;
+      const int64_t gj = j0 + r;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t gk = k0 + kk + e;
+        sb[kk + e][r] = (gj < N && gk < K) ? B[gj * ldb + gk] : 0.0;
+      }
+    } else {
+      const int kk = tid >> 4, c = (tid & 15) * 4;
+      const int64_t gk = k0 + kk;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t gj = j0 + c + e;
+        sb[kk][c + e] = (gk < K && gj < N) ? B[gk * ldb + gj] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kGemmK; ks += 4) {
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti) {
+        const double a = sa[ks + kq][wr + 16 * ti + col];
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+          acc[ti][tj] = mfma64(a, sb[ks + kq][wc + 16 * tj + col], acc[ti][tj]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gi = i0 + wr + 16 * ti + kq + 4 * r;  // accumulator rows interleave
+        const int64_t gj = j0 + wc + 16 * tj + col;
+        if (gi < M && gj < N) C[gi * ldc + gj] += alpha * acc[ti][tj][r];
+      }
+}
+
+// Diagonal blocks of the triangular solves for many right-hand sides.  Y is
+// [nrhs][n]; a wavefront owns one right-hand side at a time (lane = row of
+// the block), the block of the factor sits in LDS for the workgroup.
+// Forward: y[j0 : j0 + bs] = L11^{-1} y[j0 : j0 + bs].
+__global__ void __launch_bounds__(256)
+trsm_lower_diag_many(const double* __restrict__ K, double* __restrict__ Y, int64_t n,
+                     int64_t nrhs, int64_t j0, int bs) {
+  __shared__ double l[kTriNb][kTriNb + 1];
+  for (int e = threadIdx.x; e < kTriNb * kTriNb; e += 256) {
+    const int i = e / kTriNb, j = e % kTriNb;
+    l[i][j] = (i < bs && j <= i) ? K[(j0 + i) * n + j0 + j] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < nrhs;
+       r += (int64_t)gridDim.x * 4) {
+    double* y = Y + r * n + j0;
+    double v = (lane < bs) ? y[lane] : 0.0;
+    for (int c = 0; c < bs; ++c) {
+      const double yc = __shfl(v / l[c][c], c, 64);
+      if (lane == c) v = yc;
+      else if (lane > c) v -= l[lane][c] * yc;
+    }
+    if (lane < bs) y[lane] = v;
+  }
+}
+
+// Backward: x[j0 : j0 + bs] = L11^{-T} y[j0 : j0 + bs].
+__global__ void __launch_bounds__(256)
+trsm_upper_diag_many(const double* __restrict__ K, double* __restrict__ Y, int64_t n,
+                     int64_t nrhs, int64_t j0, int bs) {
+  __shared__ double l[kTriNb][kTriNb + 1];
+  for (int e = threadIdx.x; e < kTriNb * kTriNb; e += 256) {
+    const int i = e / kTriNb, j = e % kTriNb;
+    l[i][j] = (i < bs && j <= i) ? K[(j0 + i) * n + j0 + j] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < nrhs;
+       r += (int64_t)gridDim.x * 4) {
+    double* y = Y + r * n + j0;
+    double v = (lane < bs) ? y[lane] : 0.0;
+    for (int t = bs - 1; t >= 0; --t) {
+      const double xt = __shfl(v / l[t][t], t, 64);
+      if (lane == t) v = xt;
+      else if (lane < t) v -= l[t][lane] * xt;
+    }
+    if (lane < bs) y[lane] = v;
+  }
+}
+
+// q[r][i] = sum_j Q[i][j] d[r][j] for RB right-hand sides at a time: one
+// wavefront per row of Q, 2 entries a lane per step, Q streamed once per
+// pass with non-temporal loads.
+template <int RB>
+__global__ void __launch_bounds__(256)
+qoi_gemv(const double* __restrict__ Q, const double* __restrict__ D, double* __restrict__ q,
+         int64_t rows, int64_t cols, int64_t r0, int nb) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= rows) return;
+  const double* __restrict__ Qi = Q + i * cols;
+  double acc[RB];
+#pragma unroll
+  for (int b = 0; b < RB; ++b) acc[b] = 0.0;
+  for (int64_t j = 2 * lane; j < cols; j += 128) {
+    const bool two = j + 1 < cols;
+    const double q0 = __builtin_nontemporal_load(Qi + j);
+    const double q1 = two ? __builtin_nontemporal_load(Qi + j + 1) : 0.0;
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      if (b >= nb) break;
+      const double* __restrict__ d = D + (r0 + b) * cols;
+      acc[b] += q0 * d[j] + (two ? q1 * d[j + 1] : 0.0);
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    if (b >= nb) break;
+    const double s = wave_sum(acc[b]);
+    if (lane == 0) q[(r0 + b) * rows + i] = s;
+  }
+}
+
+unsigned grid_rhs(int64_t nrhs) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((nrhs + 3) / 4, 2048));
+}
+
+}  // namespace
+
+hipError_t launch_dgemm(bool transb, int64_t M, int64_t N, int64_t K, double alpha,
+                        const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
+                        int64_t ldc, hipStream_t s) {
+  if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+  const int64_t gx = (N + kGemmTile - 1) / kGemmTile, gy = (M + kGemmTile - 1) / kGemmTile;
+  if (gx > 0x7fffffff || gy > 65535) return hipErrorInvalidConfiguration;
+  const dim3 grid((unsigned)gx, (unsigned)gy);
+  if (transb)
+    hipLaunchKernelGGL(dgemm_kernel<true>, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb,
+                       C, ldc);
+  else
+    hipLaunchKernelGGL(dgemm_kernel<false>, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B,
+                       ldb, C, ldc);
+  return hipGetLastError();
+}
+
+// K holds the Cholesky factor L in its lower triangle.  Y ([nrhs][n]) is
+// overwritten by K^{-1} Y = L^{-T} L^{-1} Y: block by block, the diagonal
+// solve of every right-hand side, then the trailing update of all of them
+// as one matrix-core GEMM (forward: Y[:, rest] -= Y[:, blk] L[rest, blk]^T;
+// backward: Y[:, 0 : j0] -= Y[:, blk] L[blk, 0 : j0]).
+hipError_t launch_cholesky_solve_many(const double* K, double* Y, int64_t n, int64_t nrhs,
+                                      hipStream_t s) {
+  const unsigned g = grid_rhs(nrhs);
+  for (int64_t j0 = 0; j0 < n; j0 += kTriNb) {
+    const int bs = (int)std::min<int64_t>(kTriNb, n - j0);
+    hipLaunchKernelGGL(trsm_lower_diag_many, dim3(g), dim3(256), 0, s, K, Y, n, nrhs, j0, bs);
+    const int64_t j1 = j0 + bs;
+    if (j1 < n) {
+      const hipError_t e = launch_dgemm(true, nrhs, n - j1, bs, -1.0, Y + j0, n, K + j1 * n + j0,
+                                        n, Y + j1, n, s);
+      if (e != hipSuccess) return e;
+    }
+  }
+  const int64_t last = ((n - 1) / kTriNb) * kTriNb;
+  for (int64_t j0 = last; j0 >= 0; j0 -= kTriNb) {
+    const int bs = (int)std::min<int64_t>(kTriNb, n - j0);
+    hipLaunchKernelGGL(trsm_upper_diag_many, dim3(g), dim3(256), 0, s, K, Y, n, nrhs, j0, bs);
+    if (j0 > 0) {
+      const hipError_t e = launch_dgemm(false, nrhs, j0, bs, -1.0, Y + j0, n, K + j0 * n, n, Y,
+                                        n, s);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_qoi_gemv(const double* Q, const double* D, double* q, int64_t rows,
+                           int64_t cols, int64_t nrhs, hipStream_t s) {
+  const unsigned g = (unsigned)((rows + 3) / 4);
+  for (int64_t r0 = 0; r0 < nrhs; r0 += 4) {
+    const int nb = (int)std::min<int64_t>(4, nrhs - r0);
+    hipLaunchKernelGGL(qoi_gemv<4>, dim3(g), dim3(256), 0, s, Q, D, q, rows, cols, r0, nb);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace p2o

@@ -191,6 +191,20 @@ hipError_t launch_residual(const double* K, const double* diag, const double* D,
                            int64_t nrhs, hipStream_t s);
 hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t s);
 
+// ------------------------------------------------- dense float64 (dense.hip)
+// C[M x N] += alpha A[M x K] op(B), row-major; op(B) = B^T ([N x K]) when
+// transb, else B ([K x N]); float64 matrix cores.
+hipError_t launch_dgemm(bool transb, int64_t M, int64_t N, int64_t K, double alpha,
+                        const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
+                        int64_t ldc, hipStream_t s);
+// Y[nrhs][n] <- K^{-1} Y with K's Cholesky factor in the lower triangle of K
+// (no scratch; any nrhs, efficient from a few tens of right-hand sides on).
+hipError_t launch_cholesky_solve_many(const double* K, double* Y, int64_t n, int64_t nrhs,
+                                      hipStream_t s);
+// q[r][rows] = Q[rows][cols] d[r][cols] for r < nrhs.
+hipError_t launch_qoi_gemv(const double* Q, const double* D, double* q, int64_t rows,
+                           int64_t cols, int64_t nrhs, hipStream_t s);
+
 }  // namespace p2o
 
 // ------------------------------------------------------------------ plan
