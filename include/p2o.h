@@ -200,7 +200,8 @@ void p2o_batch_destroy(p2o_batch b);
 /* ------------------------------------------------------ inversion (FP64) */
 
 /* K = Gamma_noise + F Gamma_prior F* (Phase 2), Gamma_prior =
- * prior_var * I, Gamma_noise = diag(noise_var), formed as the paper does:
+ * prior_var * (I (x) C) (C = I unless p2o_set_prior selected a spatial
+ * covariance), Gamma_noise = diag(noise_var), formed as the paper does:
  * one F Gamma_prior F* product per unit vector of data space, in batches.
  *   noise_var  device [Nt*Nd] float64 (> 0 expected, not checked)
  *   K          device [(Nt*Nd)^2] float64 row-major, caller-allocated;
@@ -212,7 +213,8 @@ p2o_status p2o_hessian_assemble(p2o_handle h, double prior_var,
                                 const double* noise_var, double* K,
                                 void* stream);
 
-/* Posterior mean m = Gamma_prior F* K^{-1} d (Phase 4, zero prior mean).
+/* Posterior mean m = Gamma_prior F* K^{-1} d (Phase 4, zero prior mean;
+ * Gamma_prior as for p2o_hessian_assemble).
  *   K      device [(Nt*Nd)^2] float64; on return its lower triangle holds
  *          the Cholesky factor L (K = L L^T) and its strict upper triangle
  *          is unchanged.
@@ -228,6 +230,33 @@ p2o_status p2o_posterior_solve(p2o_handle h, double* K, const double* d,
                                int refine_steps, int64_t* failed_pivot,
                                void* stream);
 
+/* --------------------------------------------- spatial prior covariance
+ * The inversion calls below take Gamma_prior = prior_var * (I_Nt (x) C):
+ * the same spatial covariance C on every time step (time-invariant, which
+ * keeps G* = Gamma_prior F* block Toeplitz, section "Real-time Bayesian
+ * inference and prediction framework", Phase 2).  By default C = I.
+ * p2o_set_prior selects a synthetic smooth SPD stand-in for the paper's
+ * Matern-type prior (whose elliptic solves need a mesh): with the Nm
+ * parameters on an nx x ny grid (p = ix*ny + iy),
+ *   C x = delta x + B (B x),
+ *   (B x)[ix, iy] = sum_{|a|,|b| <= radius} w_a w_b x[ix + a, iy + b],
+ *   w_a = exp(-a^2 / (2 length^2)), zero outside the grid,
+ * so B is symmetric and C symmetric positive definite. */
+typedef struct {
+  int64_t nx, ny;  /* grid, nx * ny == Nm */
+  int radius;      /* window half-width, 0 .. 32 */
+  double length;   /* Gaussian length scale in grid points, > 0 */
+  double delta;    /* nugget, > 0 */
+} p2o_prior_grid;
+
+/* Sets the plan's spatial prior (copied; prior may be freed on return), or
+ * restores C = I when prior is NULL.  P2O_EINVAL on a grid that does not
+ * match Nm or parameters out of range (the plan keeps its previous prior).
+ * Used by p2o_hessian_assemble, p2o_posterior_solve and
+ * p2o_qoi_precompute (there the p2o plan's prior governs).  May
+ * synchronise `stream` (replacing an earlier prior). */
+p2o_status p2o_set_prior(p2o_handle h, const p2o_prior_grid* prior, void* stream);
+
 /* ---------------------------------------------- QoI prediction (FP64)
  * The parameter-to-QoI (p2q) map Fq is another shift-invariant block
  * Toeplitz operator, Nq forecast locations instead of Nd sensors (section
@@ -235,7 +264,7 @@ p2o_status p2o_posterior_solve(p2o_handle h, double* K, const double* d,
  * ordinary plan with Nd = Nq; p2o_apply(P2O_F) on it gives q = Fq m. */
 
 /* Phase 3 precomputations of the QoI posterior (zero prior mean,
- * Gamma_prior = prior_var * I):
+ * Gamma_prior = prior_var * (I (x) C) with hF's spatial prior C):
  *   Q  = Fq Gamma_post F* Gamma_noise^{-1} = Fq Gamma_prior F* K^{-1}
  *        (the data-to-QoI map; the two forms agree by Sherman-Morrison-
  *        Woodbury), so that Q d = Fq m_map;

@@ -17,7 +17,9 @@ Readings where the paper is silent (all listed in the design notes):
 * F* is the Euclidean transpose F^T (the blocks are given matrices; no mass
   or quadrature weights are named).
 * The prior mean is zero, as the paper takes it in its online phase.
-* Gamma_prior = prior_var * I and Gamma_noise = diag(noise_var).
+* Gamma_prior = prior_var * (I_Nt (x) C), the same spatial covariance C on
+  every time step (C = I unless given; prior_grid_matrix builds the
+  synthetic smooth one), and Gamma_noise = diag(noise_var).
 """
 from __future__ import annotations
 
@@ -29,7 +31,7 @@ __all__ = [
     "F_entry", "Fadj_entry", "hessian_dense", "hessian_gram",
     "hessian_column", "posterior_mean", "posterior_mean_normal_eq",
     "misfit_gradient", "map_objective_gradient", "cross_gram", "qoi_maps",
-    "qoi_maps_parameter_space",
+    "qoi_maps_parameter_space", "prior_grid_matrix",
 ]
 
 
@@ -139,26 +141,32 @@ def _noise_diag(noise_var, n: int) -> np.ndarray:
     return np.array(v)
 
 
-def hessian_dense(blocks: np.ndarray, prior_var: float, noise_var) -> np.ndarray:
+def hessian_dense(blocks: np.ndarray, prior_var: float, noise_var,
+                  prior_C: np.ndarray | None = None) -> np.ndarray:
     """K = Gamma_noise + F Gamma_prior F^*  (section "Real-time Bayesian
     inference and prediction framework", Phase 2, with G^* = Gamma_prior F^*),
-    from the explicit dense F.  Row/column index (i, s) -> i*Nd + s."""
+    from the explicit dense F; Gamma_prior = prior_var (I_Nt (x) C), C = I
+    unless prior_C is given.  Row/column index (i, s) -> i*Nd + s."""
     Nt, Nd, _ = _dims(blocks)
     A = dense_F(blocks)
-    K = prior_var * (A @ A.T)
+    if prior_C is None:
+        K = prior_var * (A @ A.T)
+    else:
+        K = prior_var * (A @ np.kron(np.eye(Nt), prior_C) @ A.T)
     K[np.diag_indices_from(K)] += _noise_diag(noise_var, Nt * Nd)
     return K
 
 
-def hessian_gram(blocks: np.ndarray, prior_var: float, noise_var) -> np.ndarray:
-    """The same K without forming F: block (i, j) of F F^T is
-    sum_{l<=min(i,j)} F_{i-l} F_{j-l}^T, which satisfies
-    (F F^T)_{ij} = F_i F_j^T + (F F^T)_{i-1, j-1} (terms with a negative
-    index are zero).  One Gram product of the stacked blocks plus that
-    recurrence; independent of the matvec route the product path uses."""
+def hessian_gram(blocks: np.ndarray, prior_var: float, noise_var,
+                 prior_C: np.ndarray | None = None) -> np.ndarray:
+    """The same K without forming F: block (i, j) of F (I (x) C) F^T is
+    sum_{l<=min(i,j)} F_{i-l} C F_{j-l}^T, which satisfies
+    (F (I (x) C) F^T)_{ij} = F_i C F_j^T + (...)_{i-1, j-1} (terms with a
+    negative index are zero).  One Gram product of the stacked blocks plus
+    that recurrence; independent of the matvec route the product path uses."""
     Nt, Nd, Nm = _dims(blocks)
     S = blocks.reshape(Nt * Nd, Nm)
-    G = S @ S.T                      # block (a, b) = F_a F_b^T
+    G = S @ (S.T if prior_C is None else prior_C @ S.T)  # block (a, b) = F_a C F_b^T
     for i in range(1, Nt):           # row block i uses the finished row block i-1
         G[i * Nd:(i + 1) * Nd, Nd:] += G[(i - 1) * Nd:i * Nd, :-Nd]
     G *= prior_var
@@ -177,22 +185,24 @@ def hessian_column(blocks: np.ndarray, prior_var: float, noise_var, col: int) ->
     return out
 
 
-def cross_gram(blocks_a: np.ndarray, blocks_b: np.ndarray, prior_var: float) -> np.ndarray:
-    """prior_var Fa Fb^T for two block-Toeplitz maps on the same parameter
+def cross_gram(blocks_a: np.ndarray, blocks_b: np.ndarray, prior_var: float,
+               prior_C: np.ndarray | None = None) -> np.ndarray:
+    """Fa Gamma_prior Fb^T for two block-Toeplitz maps on the same parameter
     grid (same Nm, Nt), e.g. F Gamma_prior Fq^* of Phase 3: block (i, j) is
-    sum_{l<=min(i,j)} Fa_{i-l} Fb_{j-l}^T, by the recurrence of hessian_gram
-    applied to the Gram product of the two stacked block sets."""
+    prior_var sum_{l<=min(i,j)} Fa_{i-l} C Fb_{j-l}^T, by the recurrence of
+    hessian_gram applied to the Gram product of the two stacked block sets."""
     Nt, Nda, Nm = _dims(blocks_a)
     Ntb, Ndb, Nmb = _dims(blocks_b)
     assert (Nt, Nm) == (Ntb, Nmb)
-    G = blocks_a.reshape(Nt * Nda, Nm) @ blocks_b.reshape(Nt * Ndb, Nm).T
+    Sb = blocks_b.reshape(Nt * Ndb, Nm).T
+    G = blocks_a.reshape(Nt * Nda, Nm) @ (Sb if prior_C is None else prior_C @ Sb)
     for i in range(1, Nt):
         G[i * Nda:(i + 1) * Nda, Ndb:] += G[(i - 1) * Nda:i * Nda, :-Ndb]
     return prior_var * G
 
 
 def qoi_maps(blocks: np.ndarray, blocks_q: np.ndarray, prior_var: float,
-             noise_var) -> tuple[np.ndarray, np.ndarray]:
+             noise_var, prior_C: np.ndarray | None = None) -> tuple[np.ndarray, np.ndarray]:
     """Phase 3 of section "Real-time Bayesian inference and prediction
     framework" (zero prior mean, Gamma_prior = prior_var I): the data-to-QoI
     map Q = Fq Gamma_post F^* Gamma_noise^{-1} and the QoI posterior
@@ -201,16 +211,17 @@ def qoi_maps(blocks: np.ndarray, blocks_q: np.ndarray, prior_var: float,
     G^* K^{-1} G (G^* = Gamma_prior F^*): Q = Fq G^* K^{-1},
     Gamma_post(q) = Fq Gamma_prior Fq^* - Q F Gamma_prior Fq^*.
     Q: [(Nt Nq)][(Nt Nd)], Gamma_post(q): [(Nt Nq)]^2 (index t*N + s)."""
-    K = hessian_gram(blocks, prior_var, noise_var)
-    B = cross_gram(blocks, blocks_q, prior_var)        # F Gp Fq^*, (Nt Nd) x (Nt Nq)
+    K = hessian_gram(blocks, prior_var, noise_var, prior_C)
+    B = cross_gram(blocks, blocks_q, prior_var, prior_C)   # F Gp Fq^*, (Nt Nd) x (Nt Nq)
     KinvB = scipy.linalg.cho_solve(scipy.linalg.cho_factor(K, lower=True), B)
-    Q = KinvB.T                                        # K symmetric
-    Gq = cross_gram(blocks_q, blocks_q, prior_var) - B.T @ KinvB
+    Q = KinvB.T                                            # K symmetric
+    Gq = cross_gram(blocks_q, blocks_q, prior_var, prior_C) - B.T @ KinvB
     return Q, Gq
 
 
 def qoi_maps_parameter_space(blocks: np.ndarray, blocks_q: np.ndarray, prior_var: float,
-                             noise_var) -> tuple[np.ndarray, np.ndarray]:
+                             noise_var, prior_C: np.ndarray | None = None
+                             ) -> tuple[np.ndarray, np.ndarray]:
     """The same two matrices from the parameter-space posterior covariance,
     eq. Hessian: Gamma_post = (F^* Gn^{-1} F + Gp^{-1})^{-1}, then
     Q = Fq Gamma_post F^* Gn^{-1} and Gamma_post(q) = Fq Gamma_post Fq^*
@@ -218,33 +229,61 @@ def qoi_maps_parameter_space(blocks: np.ndarray, blocks_q: np.ndarray, prior_var
     Nt, Nd, Nm = _dims(blocks)
     A, Aq = dense_F(blocks), dense_F(blocks_q)
     ninv = 1.0 / _noise_diag(noise_var, Nt * Nd)
-    H = A.T @ (ninv[:, None] * A) + np.eye(Nt * Nm) / prior_var
+    H = A.T @ (ninv[:, None] * A) + _prior_inverse(Nt, Nm, prior_var, prior_C)
     post = np.linalg.inv(H)
     return Aq @ post @ A.T * ninv[None, :], Aq @ post @ Aq.T
 
 
 def posterior_mean(blocks: np.ndarray, prior_var: float, noise_var,
-                   d: np.ndarray, K: np.ndarray | None = None) -> np.ndarray:
+                   d: np.ndarray, K: np.ndarray | None = None,
+                   prior_C: np.ndarray | None = None) -> np.ndarray:
     """m_map = Gamma_prior F^* K^{-1} d (zero prior mean; Phases 2 and 4),
-    with K^{-1} d from a Cholesky factorisation (LAPACK potrf/potrs)."""
+    with K^{-1} d from a Cholesky factorisation (LAPACK potrf/potrs) and
+    Gamma_prior = prior_var (I (x) C): C on every time slice."""
     Nt, Nd, _ = _dims(blocks)
     if K is None:
-        K = hessian_gram(blocks, prior_var, noise_var)
+        K = hessian_gram(blocks, prior_var, noise_var, prior_C)
     d = np.asarray(d, dtype=np.float64)
     rhs = d.reshape(-1, Nt * Nd).T
     x = scipy.linalg.cho_solve(scipy.linalg.cho_factor(K, lower=True), rhs)
     x = x.T.reshape(d.shape)
-    return prior_var * apply_Fadj(blocks, x)
+    m = prior_var * apply_Fadj(blocks, x)
+    return m if prior_C is None else m @ prior_C.T
+
+
+def _prior_inverse(Nt: int, Nm: int, prior_var: float, prior_C) -> np.ndarray:
+    """Gamma_prior^{-1} = (I_Nt (x) C^{-1}) / prior_var, dense."""
+    Ci = np.eye(Nm) if prior_C is None else np.linalg.inv(prior_C)
+    return np.kron(np.eye(Nt), Ci) / prior_var
+
+
+def prior_grid_matrix(nx: int, ny: int, radius: int, length: float,
+                      delta: float) -> np.ndarray:
+    """The spatial prior covariance C on an nx x ny parameter grid
+    (p = ix ny + iy): C = delta I + B B with B x[ix, iy] =
+    sum_{|a|,|b|<=radius} w_a w_b x[ix+a, iy+b], w_a = exp(-a^2/(2 length^2)),
+    zero outside the grid (a synthetic smooth SPD stand-in for the paper's
+    Matern-type prior, which needs a mesh)."""
+    w = np.exp(-np.arange(radius + 1) ** 2 / (2.0 * length ** 2))
+
+    def window(n):
+        Wn = np.zeros((n, n))
+        for i in range(n):
+            for j in range(max(0, i - radius), min(n, i + radius + 1)):
+                Wn[i, j] = w[abs(i - j)]
+        return Wn
+    B = np.kron(window(nx), window(ny))
+    return delta * np.eye(nx * ny) + B @ B
 
 
 def posterior_mean_normal_eq(blocks: np.ndarray, prior_var: float, noise_var,
-                             d: np.ndarray) -> np.ndarray:
+                             d: np.ndarray, prior_C: np.ndarray | None = None) -> np.ndarray:
     """m_map from the parameter-space normal equations, eq. mmap-problem:
     (F^* Gn^{-1} F + Gp^{-1}) m = F^* Gn^{-1} d (zero prior mean).  Tiny only."""
     Nt, Nd, Nm = _dims(blocks)
     A = dense_F(blocks)
     ninv = 1.0 / _noise_diag(noise_var, Nt * Nd)
-    H = A.T @ (ninv[:, None] * A) + np.eye(Nt * Nm) / prior_var
+    H = A.T @ (ninv[:, None] * A) + _prior_inverse(Nt, Nm, prior_var, prior_C)
     rhs = A.T @ (ninv * np.asarray(d, dtype=np.float64).reshape(-1))
     return np.linalg.solve(H, rhs).reshape(Nt, Nm)
 

@@ -31,6 +31,14 @@ STATUS = {0: "P2O_OK", 1: "P2O_EINVAL", 2: "P2O_ENOMEM", 3: "P2O_EHIP",
 
 _c = ctypes
 _vp, _i64, _int, _dbl = _c.c_void_p, _c.c_int64, _c.c_int, _c.c_double
+
+
+class _PriorGrid(_c.Structure):
+    """p2o_prior_grid of include/p2o.h."""
+    _fields_ = [("nx", _i64), ("ny", _i64), ("radius", _int), ("length", _dbl),
+                ("delta", _dbl)]
+
+
 _SIGNATURES = {
     "p2o_setup": (_int, [_vp, _i64, _i64, _i64, _int, _vp, _c.POINTER(_vp)]),
     "p2o_setup_begin": (_int, [_i64, _i64, _i64, _int, _vp, _c.POINTER(_vp)]),
@@ -44,6 +52,7 @@ _SIGNATURES = {
     "p2o_posterior_solve": (_int, [_vp, _vp, _vp, _vp, _i64, _dbl, _int,
                                    _c.POINTER(_i64), _vp]),
     "p2o_qoi_precompute": (_int, [_vp, _vp, _vp, _dbl, _vp, _vp, _vp]),
+    "p2o_set_prior": (_int, [_vp, _c.POINTER(_PriorGrid), _vp]),
     "p2o_qoi_predict": (_int, [_vp, _i64, _i64, _vp, _vp, _i64, _vp]),
     "p2o_destroy": (None, [_vp]),
     "p2o_status_string": (_c.c_char_p, [_int]),
@@ -256,6 +265,20 @@ class Plan:
             raise err
         _check("p2o_posterior_solve", st)
         return out
+
+    def set_prior(self, grid=None, radius: int = 2, length: float = 1.0, delta: float = 0.1,
+                  stream=None) -> None:
+        """Spatial prior covariance C for the inversion calls
+        (Gamma_prior = prior_var (I (x) C)): grid = (nx, ny) with nx * ny = Nm,
+        C x = delta x + B B x with B the Gaussian window of half-width
+        `radius` and length scale `length`; grid=None restores C = I."""
+        if grid is None:
+            _check("p2o_set_prior", self._lib.p2o_set_prior(self._handle(), None,
+                                                          _stream_handle(stream)))
+            return
+        pg = _PriorGrid(int(grid[0]), int(grid[1]), int(radius), float(length), float(delta))
+        _check("p2o_set_prior", self._lib.p2o_set_prior(self._handle(), _c.byref(pg),
+                                                      _stream_handle(stream)))
 
     def qoi_precompute(self, qoi_plan: "Plan", K: torch.Tensor, prior_var: float,
                        stream=None):

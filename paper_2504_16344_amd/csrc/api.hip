@@ -138,6 +138,7 @@ void free_plan(p2o_plan_s* h) {
   (void)hipFree(h->scales);
   (void)hipFree(h->scratch);
   (void)hipFree(h->ws);
+  (void)hipFree(h->prior_w);
   for (int op = 0; op < 2; ++op) {
     for (auto& pr : h->pending[op]) {
       (void)hipEventDestroy(pr.first);
@@ -557,6 +558,42 @@ p2o_status p2o_last_hip_error(int* code) {
   return P2O_OK;
 }
 
+p2o_status p2o_set_prior(p2o_handle h, const p2o_prior_grid* prior, void* stream) {
+  if (!h) return P2O_EINVAL;
+  (void)hipGetLastError();
+  if (!prior) {
+    if (h->prior_w) {
+      TRY_HIP(hipStreamSynchronize((hipStream_t)stream));
+      TRY_HIP(hipFree(h->prior_w));
+    }
+    h->prior_w = nullptr;
+    return P2O_OK;
+  }
+  if (prior->nx < 1 || prior->ny < 1 || prior->nx * prior->ny != h->Nm || prior->radius < 0 ||
+      prior->radius > kMaxPriorRadius || !(prior->length > 0) || !(prior->delta > 0))
+    return P2O_EINVAL;
+  std::vector<double> w(prior->radius + 1);
+  for (int a = 0; a <= prior->radius; ++a)
+    w[a] = std::exp(-(double)a * a / (2.0 * prior->length * prior->length));
+  double* dw = nullptr;
+  TRY_HIP(hipMalloc(&dw, w.size() * sizeof(double)));
+  hipError_t e = hipMemcpy(dw, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(dw);
+    return hip_fail(e);
+  }
+  if (h->prior_w) {
+    TRY_HIP(hipStreamSynchronize((hipStream_t)stream));
+    TRY_HIP(hipFree(h->prior_w));
+  }
+  h->prior_w = dw;
+  h->prior_nx = prior->nx;
+  h->prior_ny = prior->ny;
+  h->prior_r = prior->radius;
+  h->prior_delta = prior->delta;
+  return P2O_OK;
+}
+
 p2o_status p2o_set_kernel_timing(p2o_handle h, int enable) {
   if (!h) return P2O_EINVAL;
   h->timing = enable != 0;
@@ -685,31 +722,38 @@ bool same_time_grid(const p2o_plan_s* a, const p2o_plan_s* b) {
   return a->Nt == b->Nt && a->Nm == b->Nm && a->L == b->L;
 }
 
-// Rows of hf's F applied after prior_var times ha's F*: for every unit
+// Rows of hf's F applied after Gamma_prior times ha's F*: for every unit
 // vector e_j of ha's data space (j = t N_d(ha) + s, all N_t N_d(ha) of them),
-// out[j * ldo + :] = F_hf (prior_var I) F_ha^* e_j, a vector of hf's data
-// space ([N_t][N_d(hf)]).  With ha = hf this is row j of K minus the noise
+// out[j * ldo + :] = F_hf Gamma_prior F_ha^* e_j, a vector of hf's data
+// space ([N_t][N_d(hf)]), with Gamma_prior = prior_var (I (x) C) and C the
+// spatial prior of plan hp (identity unless set).  With ha = hf this is row j of K minus the noise
 // (Phase 2); with ha the p2q plan and hf the p2o plan it is column j of
 // F Gp Fq^*, with ha = hf = the p2q plan row j of Fq Gp Fq^* (Phase 3).
 // F* of a unit vector is a conjugated, phase-shifted row of ha's frequency
 // blocks (no product needed); then inverse transform (truncation to N_t
 // steps, times prior_var), forward transform, hf's F product over a batch
 // of unit vectors, inverse transform written straight into the rows.
-p2o_status assemble_rows(p2o_plan_s* ha, p2o_plan_s* hf, double prior_var, double* out,
-                         int64_t ldo, hipStream_t s) {
+p2o_status assemble_rows(p2o_plan_s* ha, p2o_plan_s* hf, const p2o_plan_s* hp,
+                         double prior_var, double* out, int64_t ldo, hipStream_t s) {
   const int64_t n = ha->Nt * ha->Nd;
   const int64_t Nm = hf->Nm;
+  const bool prior = hp->prior_w != nullptr;
   // per unit vector: adjoint spectrum (reused for the refiltered parameter
-  // spectrum), time-domain parameter vector, partial data spectra
-  const size_t per = (size_t)hf->nf * Nm * 16 + (size_t)hf->Nt * Nm * 8 +
+  // spectrum), time-domain parameter vector (and two prior scratch copies),
+  // partial data spectra
+  const size_t per = (size_t)hf->nf * Nm * 16 + (size_t)hf->Nt * Nm * 8 * (prior ? 3 : 1) +
                      (size_t)hf->n_pc * hf->nf * hf->Nd * 16;
   const size_t budget = (size_t)8 << 30;
   const int64_t B = std::max<int64_t>(1, std::min<int64_t>({n, 65535, (int64_t)(budget / per)}));
   DevBufs bufs;
-  void *xh, *m, *parts;
+  void *xh, *m, *parts, *t1 = nullptr, *t2 = nullptr;
   TRY_HIP(bufs.alloc(&xh, (size_t)B * hf->nf * Nm * 16));
   TRY_HIP(bufs.alloc(&m, (size_t)B * hf->Nt * Nm * 8));
   TRY_HIP(bufs.alloc(&parts, (size_t)B * hf->n_pc * hf->nf * hf->Nd * 16));
+  if (prior) {
+    TRY_HIP(bufs.alloc(&t1, (size_t)B * hf->Nt * Nm * 8));
+    TRY_HIP(bufs.alloc(&t2, (size_t)B * hf->Nt * Nm * 8));
+  }
   for (int64_t j0 = 0; j0 < n; j0 += B) {
     const int64_t nb = std::min(B, n - j0);
     TRY_HIP(launch_unit_adjoint_spectra(static_cast<const cpx<double>*>(ha->fhat), ha->tw64,
@@ -726,6 +770,10 @@ p2o_status assemble_rows(p2o_plan_s* ha, p2o_plan_s* hf, double prior_var, doubl
     inv.nparts = 1;
     inv.scale = prior_var / (double)hf->L;
     TRY_HIP(launch_rfft_inv_f64(hf->fft, hf->tw64, hf->perm, inv, nb, s));
+    if (prior)  // Gamma_prior = prior_var (I (x) C): C on every time slice
+      TRY_HIP(launch_apply_prior(static_cast<double*>(m), static_cast<double*>(t1),
+                                 static_cast<double*>(t2), nb * hf->Nt, hp->prior_nx,
+                                 hp->prior_ny, hp->prior_w, hp->prior_r, hp->prior_delta, s));
     FftIo fwd{};
     fwd.in = m;
     fwd.out = xh;
@@ -769,7 +817,7 @@ p2o_status p2o_hessian_assemble(p2o_handle h, double prior_var,
   (void)hipGetLastError();
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = h->Nt * h->Nd;
-  TRY_ST(assemble_rows(h, h, prior_var, K, n, s));
+  TRY_ST(assemble_rows(h, h, h, prior_var, K, n, s));
   TRY_HIP(launch_add_diagonal(K, noise_var, n, s));
   TRY_HIP(launch_symmetrize(K, n, s));
   TRY_HIP(hipStreamSynchronize(s));
@@ -789,8 +837,8 @@ p2o_status p2o_qoi_precompute(p2o_handle hF, p2o_handle hq, const double* Kfac,
   void* bt;  // rows j: F Gp Fq^* e_j (columns of B = F Gp Fq^*)
   TRY_HIP(bufs.alloc(&bt, (size_t)nq * n * 8));
   double* Bt = static_cast<double*>(bt);
-  TRY_ST(assemble_rows(hq, hF, prior_var, Bt, n, s));
-  TRY_ST(assemble_rows(hq, hq, prior_var, Gq, nq, s));  // Fq Gp Fq^*
+  TRY_ST(assemble_rows(hq, hF, hF, prior_var, Bt, n, s));
+  TRY_ST(assemble_rows(hq, hq, hF, prior_var, Gq, nq, s));  // Fq Gp Fq^*
   // Q = Fq Gp F^* K^{-1} = (K^{-1} B)^T: row j of Q is K^{-1} (column j of B)
   TRY_HIP(hipMemcpyAsync(Q, Bt, (size_t)nq * n * 8, hipMemcpyDeviceToDevice, s));
   TRY_HIP(launch_cholesky_solve_many(Kfac, Q, n, nq, s));
@@ -853,6 +901,14 @@ p2o_status p2o_posterior_solve(p2o_handle h, double* K, const double* d,
   }
   TRY_ST(ensure_ws(h, nrhs));
   TRY_ST(apply_impl(h, P2O_FADJ, X, m_out, nrhs, s, prior_var));
+  if (h->prior_w) {  // Gamma_prior = prior_var (I (x) C)
+    void *t1, *t2;
+    TRY_HIP(bufs.alloc(&t1, (size_t)nrhs * h->Nt * h->Nm * 8));
+    TRY_HIP(bufs.alloc(&t2, (size_t)nrhs * h->Nt * h->Nm * 8));
+    TRY_HIP(launch_apply_prior(m_out, static_cast<double*>(t1), static_cast<double*>(t2),
+                               nrhs * h->Nt, h->prior_nx, h->prior_ny, h->prior_w, h->prior_r,
+                               h->prior_delta, s));
+  }
   TRY_HIP(hipStreamSynchronize(s));
   return P2O_OK;
 }

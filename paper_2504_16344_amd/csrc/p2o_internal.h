@@ -98,6 +98,7 @@ struct GemvShape {
 // Mixed storage: 16-bit terms packed per complex entry, word 0 = hi (real
 // part in the low half), word 1 = lo (absent for the hi-only tier).
 constexpr int kScaleTile = 256;  // columns per scale sub-block
+constexpr int kMaxPriorRadius = 32;  // largest half-width of the prior's window
 enum class Fmt16 { FP16 = 0, BF16 = 1 };
 
 // Candidate configurations of the product kernels (rows per wavefront for
@@ -201,6 +202,11 @@ hipError_t launch_dgemm(bool transb, int64_t M, int64_t N, int64_t K, double alp
 // (no scratch; any nrhs, efficient from a few tens of right-hand sides on).
 hipError_t launch_cholesky_solve_many(const double* K, double* Y, int64_t n, int64_t nrhs,
                                       hipStream_t s);
+// Spatial prior covariance C on an nx x ny parameter grid (prior.hip):
+// x[count][nx ny] <- C x in place; t1, t2 scratch of the same size; w the
+// r + 1 window weights (device).
+hipError_t launch_apply_prior(double* x, double* t1, double* t2, int64_t count, int64_t nx,
+                              int64_t ny, const double* w, int r, double delta, hipStream_t s);
 // q[r][rows] = Q[rows][cols] d[r][cols] for r < nrhs.
 hipError_t launch_qoi_gemv(const double* Q, const double* D, double* q, int64_t rows,
                            int64_t cols, int64_t nrhs, hipStream_t s);
@@ -224,6 +230,11 @@ struct p2o_plan_s {
   int64_t cols_done = 0;             // setup progress
   int cfg[2] = {0, 0};               // product-kernel candidate per op
   int64_t mfma_min_rhs[2] = {8, 8};  // from this many RHS on, matrix cores (set per precision at setup)
+  // spatial prior covariance C (p2o_set_prior); identity when prior_w is null
+  double* prior_w = nullptr;         // [prior_r + 1] window weights (device)
+  int64_t prior_nx = 0, prior_ny = 0;
+  int prior_r = 0;
+  double prior_delta = 0.0;
   bool ready = false;
   void* scratch = nullptr;           // setup chunk staging (mixed)
   size_t scratch_bytes = 0;
