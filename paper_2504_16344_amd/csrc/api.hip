@@ -730,9 +730,10 @@ bool same_time_grid(const p2o_plan_s* a, const p2o_plan_s* b) {
 // (Phase 2); with ha the p2q plan and hf the p2o plan it is column j of
 // F Gp Fq^*, with ha = hf = the p2q plan row j of Fq Gp Fq^* (Phase 3).
 // F* of a unit vector is a conjugated, phase-shifted row of ha's frequency
-// blocks (no product needed); then inverse transform (truncation to N_t
-// steps, times prior_var), forward transform, hf's F product over a batch
-// of unit vectors, inverse transform written straight into the rows.
+// blocks (no product needed), generated in the load stage of the inverse
+// transform (truncation to N_t steps, times prior_var); then forward
+// transform, hf's F product over a batch of unit vectors, inverse
+// transform written straight into the rows.
 p2o_status assemble_rows(p2o_plan_s* ha, p2o_plan_s* hf, const p2o_plan_s* hp,
                          double prior_var, double* out, int64_t ldo, hipStream_t s) {
   const int64_t n = ha->Nt * ha->Nd;
@@ -756,11 +757,13 @@ p2o_status assemble_rows(p2o_plan_s* ha, p2o_plan_s* hf, const p2o_plan_s* hp,
   }
   for (int64_t j0 = 0; j0 < n; j0 += B) {
     const int64_t nb = std::min(B, n - j0);
-    TRY_HIP(launch_unit_adjoint_spectra(static_cast<const cpx<double>*>(ha->fhat), ha->tw64,
-                                        static_cast<cpx<double>*>(xh), ha->nf, ha->Nd, Nm,
-                                        ha->L, j0, nb, s));
+    // F_ha^* of the unit vectors, generated inside the inverse transform's
+    // load (no spectrum buffer), then truncation to Nt steps, times prior_var
     FftIo inv{};
-    inv.in = xh;
+    inv.in = nullptr;
+    inv.unit_fhat = ha->fhat;
+    inv.unit_nd = ha->Nd;
+    inv.unit_j0 = j0;
     inv.out = m;
     inv.ncols = Nm;
     inv.in_row = Nm;

@@ -17,7 +17,10 @@ constexpr int kTriNb = 64;     // triangular-solve block (the Cholesky block siz
 // tile of C, each of its 4 wavefronts a 32 x 32 quarter (2 x 2
 // v_mfma_f64_16x16x4 tiles); 16-entry chunks of the contraction are staged
 // in LDS as [k][row] for both operands.
-template <bool TRANSB>
+// With LOWER (a symmetric rank-k update of a lower triangle, M == N), the
+// grid enumerates only the tiles I >= J and entries above the diagonal are
+// left untouched.
+template <bool TRANSB, bool LOWER>
 __global__ void __launch_bounds__(256)
 dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A,
              int64_t lda, const double* __restrict__ B, int64_t ldb, double* __restrict__ C,
@@ -26,7 +29,16 @@ dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __rest
   __shared__ double sb[kGemmK][kGemmTile + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, kq = lane >> 4;
-  const int64_t i0 = (int64_t)blockIdx.y * kGemmTile, j0 = (int64_t)blockIdx.x * kGemmTile;
+  int64_t ti_ = blockIdx.y, tj_ = blockIdx.x;
+  if constexpr (LOWER) {  // linear index t -> (I, J), J <= I
+    const int64_t t = blockIdx.x;
+    int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) / 2.0);
+    while (I * (I + 1) / 2 > t) --I;
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    ti_ = I;
+    tj_ = t - I * (I + 1) / 2;
+  }
+  const int64_t i0 = ti_ * kGemmTile, j0 = tj_ * kGemmTile;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
   d4v acc[2][2];
 #pragma unroll
@@ -81,7 +93,7 @@ dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __rest
       for (int r = 0; r < 4; ++r) {
         const int64_t gi = i0 + wr + 16 * ti + kq + 4 * r;  // accumulator rows interleave
         const int64_t gj = j0 + wc + 16 * tj + col;
-        if (gi < M && gj < N) C[gi * ldc + gj] += alpha * acc[ti][tj][r];
+        if (gi < M && gj < N && (!LOWER || gj <= gi)) C[gi * ldc + gj] += alpha * acc[ti][tj][r];
       }
 }
 
@@ -183,11 +195,22 @@ hipError_t launch_dgemm(bool transb, int64_t M, int64_t N, int64_t K, double alp
   if (gx > 0x7fffffff || gy > 65535) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)gx, (unsigned)gy);
   if (transb)
-    hipLaunchKernelGGL(dgemm_kernel<true>, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb,
-                       C, ldc);
+    hipLaunchKernelGGL((dgemm_kernel<true, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
+                       B, ldb, C, ldc);
   else
-    hipLaunchKernelGGL(dgemm_kernel<false>, grid, dim3(256), 0, s, M, N, K, alpha, A, lda, B,
-                       ldb, C, ldc);
+    hipLaunchKernelGGL((dgemm_kernel<false, false>), grid, dim3(256), 0, s, M, N, K, alpha, A,
+                       lda, B, ldb, C, ldc);
+  return hipGetLastError();
+}
+
+hipError_t launch_dsyrk_lower(int64_t n, int64_t K, double alpha, const double* A, int64_t lda,
+                              double* C, int64_t ldc, hipStream_t s) {
+  if (n <= 0 || K <= 0) return hipSuccess;
+  const int64_t T = (n + kGemmTile - 1) / kGemmTile;
+  const int64_t tiles = T * (T + 1) / 2;
+  if (tiles > 0x7fffffff) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((dgemm_kernel<true, true>), dim3((unsigned)tiles), dim3(256), 0, s, n, n, K,
+                     alpha, A, lda, A, lda, C, ldc);
   return hipGetLastError();
 }
 

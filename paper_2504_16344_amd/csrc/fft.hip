@@ -293,6 +293,20 @@ __device__ __forceinline__ cpx<T> load_bins(const cpx<TIN>* __restrict__ in,
   return {(T)acc.x, (T)acc.y};
 }
 
+// Bin k of F* e_j in frequency space, j = unit_j0 + b = i unit_nd + s: F*'s
+// circulant embedding maps the unit vector to conj(Fhat_k[s, :]) shifted by
+// i steps, i.e. times W_L^(i k) (W_L = exp(-2 pi i / L), the table tw).
+template <typename T>
+__device__ __forceinline__ cpx<T> unit_adjoint_bin(const FftIo& io, const cpx<T>* __restrict__ tw,
+                                                   int L, int64_t b, int64_t col, int k) {
+  const int64_t j = io.unit_j0 + b;
+  const int64_t i = j / io.unit_nd, s = j % io.unit_nd;
+  const cpx<double> a =
+      static_cast<const cpx<double>*>(io.unit_fhat)[((int64_t)k * io.unit_nd + s) * io.ncols + col];
+  const cpx<T> w = tw[(i * k) % L];
+  return {(T)(a.x * w.x + a.y * w.y), (T)(a.x * w.y - a.y * w.x)};
+}
+
 // Z[k] = (Xa + conj Xb) + i conj(W_L^k) (Xa - conj Xb) with Xa = X[k],
 // Xb = X[N-k]; the 1/2 of the split and the 1/N of the inverse DFT are
 // folded into io.scale (= 1/L).
@@ -323,13 +337,19 @@ rfft_inv_kernel(FftDesc d, const cpx<T>* __restrict__ tw,
   const int ncol = (int)min((int64_t)C, io.ncols - c0);
   const int N = d.N, Nt = d.Nt;
   const int half = N / 2;
+  const bool unit = std::is_same<T, double>::value && io.unit_fhat != nullptr;
 
   for (int idx = tid; idx < ((half + 1) << logC); idx += nthr) {
     const int k = idx >> logC, c = idx & (C - 1);
     cpx<T> xa = {0, 0}, xb = {0, 0};
     if (c < ncol) {
-      xa = load_bins<TIN, T>(in, io, k, c);
-      xb = load_bins<TIN, T>(in, io, N - k, c);
+      if (unit) {
+        xa = unit_adjoint_bin<T>(io, tw, d.L, b, c0 + c, k);
+        xb = unit_adjoint_bin<T>(io, tw, d.L, b, c0 + c, N - k);
+      } else {
+        xa = load_bins<TIN, T>(in, io, k, c);
+        xb = load_bins<TIN, T>(in, io, N - k, c);
+      }
     }
     if (k == 0) {  // bins 0 and N of a real series are real
       xa.y = 0;

@@ -23,29 +23,6 @@ namespace {
 constexpr int kNb = 64;  // Cholesky / triangular-solve block size
 
 // ------------------------------------------------------------ assembly
-// xhat[b][k][p] = conj(Fhat[k][s_b][p]) * W_L^((i_b k) mod L), column
-// j = j0 + b = i_b * Nd + s_b of data space.
-__global__ void __launch_bounds__(256)
-unit_adjoint_spectra(const cpx<double>* __restrict__ A,
-                     const cpx<double>* __restrict__ tw, cpx<double>* __restrict__ xh,
-                     int64_t nf, int64_t Nd, int64_t Nm, int64_t L, int64_t j0,
-                     int64_t nb) {
-  const int64_t total = nb * nf * Nm;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t p = idx % Nm;
-    const int64_t bk = idx / Nm;
-    const int64_t k = bk % nf;
-    const int64_t b = bk / nf;
-    const int64_t j = j0 + b;
-    const int64_t i = j / Nd, s = j % Nd;
-    const cpx<double> a = A[(k * Nd + s) * Nm + p];
-    const cpx<double> w = tw[(i * k) % L];
-    // conj(a) * w
-    xh[idx] = {a.x * w.x + a.y * w.y, a.x * w.y - a.y * w.x};
-  }
-}
-
 __global__ void add_diagonal(double* __restrict__ K, const double* __restrict__ v,
                              int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -144,62 +121,22 @@ trsm_panel(double* __restrict__ K, int64_t n, int64_t j0, int bs) {
     for (int j = tid; j < bs; j += 64) K[(r0 + i) * n + j0 + j] = x[i][j];
 }
 
-// Trailing update of the lower triangle: C[I, J] -= P_I P_J^T for 64 x 64
-// tiles I >= J of rows/cols [j1, n), P = K[j1:n, j0:j0+bs].
-__global__ void __launch_bounds__(256)
-syrk_update(double* __restrict__ K, int64_t n, int64_t j0, int bs) {
-  __shared__ double pi[kNb][kNb + 1];  // [k][row]
-  __shared__ double pj[kNb][kNb + 1];
-  const int64_t j1 = j0 + bs;
-  const int64_t t = blockIdx.x;
-  int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) / 2.0);
-  while (I * (I + 1) / 2 > t) --I;
-  while ((I + 1) * (I + 2) / 2 <= t) ++I;
-  const int64_t J = t - I * (I + 1) / 2;  // J <= I
-  const int64_t ri = j1 + I * kNb, rj = j1 + J * kNb;
-  const int tid = threadIdx.x;
-  for (int e = tid; e < kNb * kNb; e += 256) {
-    const int r = e / kNb, k = e % kNb;
-    pi[k][r] = (ri + r < n && k < bs) ? K[(ri + r) * n + j0 + k] : 0.0;
-    pj[k][r] = (rj + r < n && k < bs) ? K[(rj + r) * n + j0 + k] : 0.0;
-  }
-  __syncthreads();
-  const int tx = tid & 15, ty = tid >> 4;
-  double acc[4][4] = {};
-  for (int k = 0; k < bs; ++k) {
-    double a[4], b[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a[u] = pi[k][ty + 16 * u];
-      b[u] = pj[k][tx + 16 * u];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t gi = ri + ty + 16 * u, gj = rj + tx + 16 * v;
-      if (gi < n && gj < n && gj <= gi) K[gi * n + gj] -= acc[u][v];
-    }
-}
-
 // ------------------------------------------------------ triangular solves
 // Y is [nrhs][n].  Forward: L y = b block by block.
 // Solve the diagonal block in place, y[j0:j0+bs] = L11^{-1} y[j0:j0+bs]:
 // lane i holds row i; at step c lane c finishes y_c, which is broadcast and
 // removed from the rows below it (column-oriented substitution).
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
 trsv_lower_diag(const double* __restrict__ K, double* __restrict__ Y, int64_t n,
                 int64_t nrhs, int64_t j0, int bs) {
   __shared__ double l[kNb][kNb + 1];
-  const int lane = threadIdx.x;
-  for (int i = 0; i < bs; ++i)
-    for (int j = lane; j < bs; j += 64) l[i][j] = (j <= i) ? K[(j0 + i) * n + j0 + j] : 0.0;
+  for (int e = threadIdx.x; e < kNb * kNb; e += 256) {  // all 4 wavefronts load
+    const int i = e / kNb, j = e % kNb;
+    l[i][j] = (i < bs && j <= i) ? K[(j0 + i) * n + j0 + j] : 0.0;
+  }
   __syncthreads();
+  if (threadIdx.x >= 64) return;  // one wavefront solves
+  const int lane = threadIdx.x;
   for (int64_t r = 0; r < nrhs; ++r) {
     double* y = Y + r * n + j0;
     double v = (lane < bs) ? y[lane] : 0.0;
@@ -255,15 +192,18 @@ trsv_upper_partial(const double* __restrict__ K, const double* __restrict__ Y,
 // Backward diagonal block: x = L11^{-T} (y - sum of the partials); lane c
 // holds unknown c; at step t lane t finishes x_t, which is broadcast and
 // removed from the unknowns above it.
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
 trsv_upper_diag(const double* __restrict__ K, double* __restrict__ Y,
                 const double* __restrict__ part, int nparts, int64_t n, int64_t nrhs,
                 int64_t j0, int bs) {
   __shared__ double l[kNb][kNb + 1];
-  const int lane = threadIdx.x;
-  for (int i = 0; i < bs; ++i)
-    for (int j = lane; j < bs; j += 64) l[i][j] = (j <= i) ? K[(j0 + i) * n + j0 + j] : 0.0;
+  for (int e = threadIdx.x; e < kNb * kNb; e += 256) {  // all 4 wavefronts load
+    const int i = e / kNb, j = e % kNb;
+    l[i][j] = (i < bs && j <= i) ? K[(j0 + i) * n + j0 + j] : 0.0;
+  }
   __syncthreads();
+  if (threadIdx.x >= 64) return;  // one wavefront solves
+  const int lane = threadIdx.x;
   for (int64_t r = 0; r < nrhs; ++r) {
     double* y = Y + r * n + j0;
     double v = 0.0;
@@ -343,17 +283,6 @@ unsigned grid1(int64_t n, int per = 256) {
 
 }  // namespace
 
-hipError_t launch_unit_adjoint_spectra(const cpx<double>* A, const cpx<double>* tw,
-                                       cpx<double>* xh, int64_t nf, int64_t Nd,
-                                       int64_t Nm, int64_t L, int64_t j0, int64_t nb,
-                                       hipStream_t s) {
-  const int64_t total = nb * nf * Nm;
-  const unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20);
-  hipLaunchKernelGGL(unit_adjoint_spectra, dim3(g), dim3(256), 0, s, A, tw, xh, nf, Nd, Nm,
-                     L, j0, nb);
-  return hipGetLastError();
-}
-
 hipError_t launch_add_diagonal(double* K, const double* v, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(add_diagonal, dim3(grid1(n)), dim3(256), 0, s, K, v, n);
   return hipGetLastError();
@@ -375,9 +304,11 @@ hipError_t launch_cholesky(double* K, int64_t n, int64_t* info_dev, hipStream_t 
     const int64_t m = n - j0 - bs;
     if (m > 0) {
       hipLaunchKernelGGL(trsm_panel, dim3(grid1(m, kNb)), dim3(64), 0, s, K, n, j0, bs);
-      const int64_t T = (m + kNb - 1) / kNb;
-      hipLaunchKernelGGL(syrk_update, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, s, K,
-                         n, j0, bs);
+      // trailing update of the lower triangle on the float64 matrix cores
+      const int64_t j1 = j0 + bs;
+      const hipError_t e = launch_dsyrk_lower(m, bs, -1.0, K + j1 * n + j0, n, K + j1 * n + j1,
+                                              n, s);
+      if (e != hipSuccess) return e;
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -390,7 +321,7 @@ hipError_t launch_cholesky_solve(const double* K, double* Y, double* part, int64
                                  int64_t nrhs, hipStream_t s) {
   for (int64_t j0 = 0; j0 < n; j0 += kNb) {
     const int bs = (int)std::min<int64_t>(kNb, n - j0);
-    hipLaunchKernelGGL(trsv_lower_diag, dim3(1), dim3(64), 0, s, K, Y, n, nrhs, j0, bs);
+    hipLaunchKernelGGL(trsv_lower_diag, dim3(1), dim3(256), 0, s, K, Y, n, nrhs, j0, bs);
     const int64_t m = n - j0 - bs;
     if (m > 0)
       hipLaunchKernelGGL(trsv_lower_update, dim3(grid1(m, 4)), dim3(256), 0, s, K, Y, n, nrhs,
@@ -406,7 +337,7 @@ hipError_t launch_cholesky_solve(const double* K, double* Y, double* part, int64
       hipLaunchKernelGGL(trsv_upper_partial, dim3(nparts), dim3(256), 0, s, K, Y, part, n, nrhs,
                          j0, bs);
     }
-    hipLaunchKernelGGL(trsv_upper_diag, dim3(1), dim3(64), 0, s, K, Y, part, nparts, n, nrhs,
+    hipLaunchKernelGGL(trsv_upper_diag, dim3(1), dim3(256), 0, s, K, Y, part, nparts, n, nrhs,
                        j0, bs);
   }
   return hipGetLastError();

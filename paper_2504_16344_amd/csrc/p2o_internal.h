@@ -63,6 +63,13 @@ struct FftIo {
   int64_t n8;            // plane pitch (ncols rounded up to 8)
   int64_t nbins;         // frequency bins per batch (nf)
   const float* col_scales;  // [nbins][ceil(ncols / kScaleTile)] or nullptr
+  // Inverse float64 only: when `unit_fhat` is set, batch b reads instead of
+  // `in` the spectrum of F* applied to the unit vector j = unit_j0 + b of
+  // a data space of unit_nd sensors (j = i unit_nd + s): bin k, column c is
+  // conj(unit_fhat[k][s][c]) W_L^(i k) (unit_fhat: [nbins][unit_nd][ncols]).
+  const void* unit_fhat;
+  int64_t unit_nd;
+  int64_t unit_j0;
 };
 
 int64_t smooth_length(int64_t Nt);  // L: smallest even 7-smooth >= 2*Nt
@@ -176,10 +183,6 @@ hipError_t launch_batch_product(BatchClass cls, p2o_op op, const BatchInst* inst
                                 int64_t total_units, hipStream_t s);
 
 // ------------------------------------------------------- inversion kernels
-hipError_t launch_unit_adjoint_spectra(const cpx<double>* A, const cpx<double>* tw,
-                                       cpx<double>* xh, int64_t nf, int64_t Nd,
-                                       int64_t Nm, int64_t L, int64_t j0, int64_t nb,
-                                       hipStream_t s);
 hipError_t launch_add_diagonal(double* K, const double* v, int64_t n, hipStream_t s);
 hipError_t launch_symmetrize(double* K, int64_t n, hipStream_t s);
 hipError_t launch_cholesky(double* K, int64_t n, int64_t* info_dev, hipStream_t s);
@@ -198,6 +201,10 @@ hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStrea
 hipError_t launch_dgemm(bool transb, int64_t M, int64_t N, int64_t K, double alpha,
                         const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
                         int64_t ldc, hipStream_t s);
+// Lower triangle of C[n x n] += alpha A A^T (A [n x K]); entries above the
+// diagonal untouched.
+hipError_t launch_dsyrk_lower(int64_t n, int64_t K, double alpha, const double* A, int64_t lda,
+                              double* C, int64_t ldc, hipStream_t s);
 // Y[nrhs][n] <- K^{-1} Y with K's Cholesky factor in the lower triangle of K
 // (no scratch; any nrhs, efficient from a few tens of right-hand sides on).
 hipError_t launch_cholesky_solve_many(const double* K, double* Y, int64_t n, int64_t nrhs,
