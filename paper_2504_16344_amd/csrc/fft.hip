@@ -143,10 +143,13 @@ __device__ __forceinline__ void dif_stage(cpx<T>* buf, int N, int M, int L,
     wr[m] = tw[(L / R) * m];
     if (inv) wr[m].y = -wr[m].y;
   }
+  const float rMr = 1.0f / (float)Mr;
   for (int idx = tid; idx < (nbf << logC); idx += nthr) {
     const int bf = idx >> logC;
     const int c = idx & (C - 1);
-    const int g = bf / Mr;
+    int g = (int)((float)bf * rMr);  // bf / Mr: float estimate, one correction step
+    if (g * Mr > bf) --g;
+    else if ((g + 1) * Mr <= bf) ++g;
     const int np = bf - g * Mr;
     const int base = g * M + np;
     cpx<T> x[R], y[R];
@@ -184,6 +187,19 @@ __device__ void dif_all_stages(cpx<T>* buf, const FftDesc& d,
 }
 
 // Forward: x (float64 rows 0..Nt-1 of each column) -> X[k], k = 0..N.
+// Twiddle table (L entries) and digit-reversal table (N entries) copied to
+// LDS after the N x C transform tile; visible after the next barrier.
+template <typename T>
+__device__ __forceinline__ void tables_to_lds(cpx<T>* buf, const FftDesc& d,
+                                              const cpx<T>* __restrict__ tw,
+                                              const int* __restrict__ perm, int logC, int tid,
+                                              int nthr) {
+  cpx<T>* stw = buf + (d.N << logC);
+  int* sperm = reinterpret_cast<int*>(stw + d.L);
+  for (int i = tid; i < d.L; i += nthr) stw[i] = tw[i];
+  for (int i = tid; i < d.N; i += nthr) sperm[i] = perm[i];
+}
+
 // Bin k of the real transform from the half-length complex transform in
 // `buf`: X = a/2 - i w e / 2 with a = Zk + conj Zn, e = Zk - conj Zn.
 template <typename T>
@@ -241,8 +257,8 @@ __device__ __forceinline__ void write_planes(const cpx<float>* buf, const cpx<fl
 
 template <typename T>
 __global__ void __launch_bounds__(512)
-rfft_fwd_kernel(FftDesc d, const cpx<T>* __restrict__ tw,
-                const int* __restrict__ perm, FftIo io, int logC) {
+rfft_fwd_kernel(FftDesc d, const cpx<T>* __restrict__ tw_g,
+                const int* __restrict__ perm_g, FftIo io, int logC) {
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   const int C = 1 << logC;
@@ -254,6 +270,9 @@ rfft_fwd_kernel(FftDesc d, const cpx<T>* __restrict__ tw,
   cpx<T>* __restrict__ out = static_cast<cpx<T>*>(io.out) + b * io.out_batch + c0;
   const int ncol = (int)min((int64_t)C, io.ncols - c0);
   const int N = d.N, Nt = d.Nt;
+  tables_to_lds(buf, d, tw_g, perm_g, logC, tid, nthr);
+  const cpx<T>* tw = buf + (N << logC);
+  const int* perm = reinterpret_cast<const int*>(tw + d.L);
 
   for (int idx = tid; idx < (N << logC); idx += nthr) {
     const int n = idx >> logC, c = idx & (C - 1);
@@ -323,8 +342,8 @@ __device__ __forceinline__ cpx<T> unsplit(cpx<T> xa, cpx<T> xb, cpx<T> w) {
 // real samples of the length-L inverse DFT, times io.scale, as float64.
 template <typename TIN, typename T>
 __global__ void __launch_bounds__(512)
-rfft_inv_kernel(FftDesc d, const cpx<T>* __restrict__ tw,
-                const int* __restrict__ perm, FftIo io, int logC) {
+rfft_inv_kernel(FftDesc d, const cpx<T>* __restrict__ tw_g,
+                const int* __restrict__ perm_g, FftIo io, int logC) {
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* buf = reinterpret_cast<cpx<T>*>(smem_raw);
   const int C = 1 << logC;
@@ -337,6 +356,10 @@ rfft_inv_kernel(FftDesc d, const cpx<T>* __restrict__ tw,
   const int ncol = (int)min((int64_t)C, io.ncols - c0);
   const int N = d.N, Nt = d.Nt;
   const int half = N / 2;
+  tables_to_lds(buf, d, tw_g, perm_g, logC, tid, nthr);
+  const cpx<T>* tw = buf + (N << logC);
+  const int* perm = reinterpret_cast<const int*>(tw + d.L);
+  __syncthreads();  // the load stage below reads the twiddles
   const bool unit = std::is_same<T, double>::value && io.unit_fhat != nullptr;
 
   for (int idx = tid; idx < ((half + 1) << logC); idx += nthr) {
@@ -370,12 +393,21 @@ rfft_inv_kernel(FftDesc d, const cpx<T>* __restrict__ tw,
   }
 }
 
-// Columns per work-group: the largest power of two <= 64 whose LDS tile
-// (N complex values per column) fits in 64 KB.
+// LDS bytes of one work-group: the N x C transform tile, then the twiddle
+// and digit-reversal tables.
 template <typename T>
-int pick_logC(int N) {
+size_t fft_lds_bytes(const FftDesc& d, int logC) {
+  return ((size_t)d.N << logC) * sizeof(cpx<T>) + (size_t)d.L * sizeof(cpx<T>) +
+         (size_t)d.N * sizeof(int);
+}
+
+// Columns per work-group: the largest power of two <= 64 whose LDS fits the
+// budget (two work-groups per compute unit at 80 KB).
+constexpr size_t kFftLdsBudget = 81920;
+template <typename T>
+int pick_logC(const FftDesc& d) {
   int logC = 0;
-  while (logC < 6 && ((size_t)N << (logC + 1)) * sizeof(cpx<T>) <= 65536) ++logC;
+  while (logC < 6 && fft_lds_bytes<T>(d, logC + 1) <= kFftLdsBudget) ++logC;
   return logC;
 }
 
@@ -385,9 +417,9 @@ hipError_t launch_common(K kernel, const FftDesc& d, const cpx<T>* tw,
                          hipStream_t s) {
   if (nbatch < 1 || io.ncols < 1) return hipSuccess;
   if (nbatch > 65535) return hipErrorInvalidConfiguration;
-  const int logC = pick_logC<T>(d.N);
-  const size_t lds = ((size_t)d.N << logC) * sizeof(cpx<T>);
-  if (lds > 65536) return hipErrorInvalidConfiguration;
+  const int logC = pick_logC<T>(d);
+  const size_t lds = fft_lds_bytes<T>(d, logC);
+  if (lds > 163840) return hipErrorInvalidConfiguration;
   const int64_t gx = (io.ncols + (1 << logC) - 1) >> logC;
   if (gx > 0x7fffffff) return hipErrorInvalidConfiguration;
   const int threads = 512;
