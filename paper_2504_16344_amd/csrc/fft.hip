@@ -74,6 +74,8 @@ std::vector<int> make_perm(const FftDesc& d) {
 
 namespace {
 
+constexpr int kLoadGroup = 8;  // loads in flight per thread in the load stages
+
 template <typename T>
 __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
   return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
@@ -274,15 +276,28 @@ rfft_fwd_kernel(FftDesc d, const cpx<T>* __restrict__ tw_g,
   const cpx<T>* tw = buf + (N << logC);
   const int* perm = reinterpret_cast<const int*>(tw + d.L);
 
-  for (int idx = tid; idx < (N << logC); idx += nthr) {
-    const int n = idx >> logC, c = idx & (C - 1);
-    T re = 0, im = 0;
-    if (c < ncol) {
+  // groups of kLoadGroup elements a thread: all their loads are issued
+  // before the first LDS store, so their latencies overlap
+  const int total = N << logC;
+  for (int base = tid; base < total; base += kLoadGroup * nthr) {
+    double re[kLoadGroup], im[kLoadGroup];
+#pragma unroll
+    for (int g = 0; g < kLoadGroup; ++g) {  // unconditional: clamped addresses
+      const int idx = base + g * nthr;
+      const int n = idx >> logC, c = idx & (C - 1);
       const int t0 = 2 * n;
-      if (t0 < Nt) re = (T)in[(int64_t)t0 * io.in_row + c];
-      if (t0 + 1 < Nt) im = (T)in[(int64_t)(t0 + 1) * io.in_row + c];
+      const bool ok = idx < total && c < ncol;
+      re[g] = in[(ok && t0 < Nt) ? (int64_t)t0 * io.in_row + c : 0];
+      im[g] = in[(ok && t0 + 1 < Nt) ? (int64_t)(t0 + 1) * io.in_row + c : 0];
     }
-    buf[idx] = {re, im};
+#pragma unroll
+    for (int g = 0; g < kLoadGroup; ++g) {
+      const int idx = base + g * nthr;
+      const int n = idx >> logC, c = idx & (C - 1);
+      const bool ok = idx < total && c < ncol;
+      if (idx < total)
+        buf[idx] = {(ok && 2 * n < Nt) ? (T)re[g] : (T)0, (ok && 2 * n + 1 < Nt) ? (T)im[g] : (T)0};
+    }
   }
   dif_all_stages<T>(buf, d, tw, false, logC, tid, nthr);
 
@@ -300,16 +315,34 @@ rfft_fwd_kernel(FftDesc d, const cpx<T>* __restrict__ tw_g,
   }
 }
 
-template <typename TIN, typename T>
-__device__ __forceinline__ cpx<T> load_bins(const cpx<TIN>* __restrict__ in,
-                                            const FftIo& io, int k, int c) {
-  cpx<TIN> acc = in[(int64_t)k * io.in_row + c];
+// Partial spectra 1 .. nparts-1 (F's column chunks) added, in a fixed
+// order, to the first ones sa (bins k) and sb (bins N - k) of the
+// G elements of a load group; one part at a time for all elements,
+// so the loads of a part are in flight together.  Sums stay in TIN
+// (float64 for F's partials) until the caller narrows them.
+template <int G, typename TIN>
+__device__ __forceinline__ void add_partials(const cpx<TIN>* __restrict__ in, const FftIo& io,
+                                             int base, int total, int nthr, int logC, int ncol,
+                                             int N, cpx<TIN> (&sa)[G], cpx<TIN> (&sb)[G]) {
+  const int C = 1 << logC;
   for (int q = 1; q < io.nparts; ++q) {
-    const cpx<TIN> v = in[q * io.part_stride + (int64_t)k * io.in_row + c];
-    acc.x += v.x;
-    acc.y += v.y;
+    cpx<TIN> va[G], vb[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int idx = base + g * nthr;
+      const bool ok = idx < total && (idx & (C - 1)) < ncol;
+      const int k = ok ? idx >> logC : 0, c = ok ? idx & (C - 1) : 0;
+      va[g] = in[q * io.part_stride + (int64_t)k * io.in_row + c];
+      vb[g] = in[q * io.part_stride + (int64_t)(N - k) * io.in_row + c];
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      sa[g].x += va[g].x;
+      sa[g].y += va[g].y;
+      sb[g].x += vb[g].x;
+      sb[g].y += vb[g].y;
+    }
   }
-  return {(T)acc.x, (T)acc.y};
 }
 
 // Bin k of F* e_j in frequency space, j = unit_j0 + b = i unit_nd + s: F*'s
@@ -362,25 +395,55 @@ rfft_inv_kernel(FftDesc d, const cpx<T>* __restrict__ tw_g,
   __syncthreads();  // the load stage below reads the twiddles
   const bool unit = std::is_same<T, double>::value && io.unit_fhat != nullptr;
 
-  for (int idx = tid; idx < ((half + 1) << logC); idx += nthr) {
-    const int k = idx >> logC, c = idx & (C - 1);
-    cpx<T> xa = {0, 0}, xb = {0, 0};
-    if (c < ncol) {
-      if (unit) {
-        xa = unit_adjoint_bin<T>(io, tw, d.L, b, c0 + c, k);
-        xb = unit_adjoint_bin<T>(io, tw, d.L, b, c0 + c, N - k);
-      } else {
-        xa = load_bins<TIN, T>(in, io, k, c);
-        xb = load_bins<TIN, T>(in, io, N - k, c);
+  // groups of G bin pairs a thread, loads first (see the forward); half the
+  // group when any side is float64 keeps the kernel within 128 VGPRs (two
+  // work-groups a CU)
+  constexpr int G = (std::is_same<T, double>::value || std::is_same<TIN, double>::value)
+                        ? kLoadGroup / 2
+                        : kLoadGroup;
+  const int total = (half + 1) << logC;
+  for (int base = tid; base < total; base += G * nthr) {
+    cpx<T> xa[G], xb[G];
+    if (unit) {
+#pragma unroll
+      for (int g = 0; g < G; ++g) {  // unconditional: clamped addresses
+        const int idx = base + g * nthr;
+        const bool ok = idx < total && (idx & (C - 1)) < ncol;
+        const int k = ok ? idx >> logC : 0, c = ok ? idx & (C - 1) : 0;
+        xa[g] = unit_adjoint_bin<T>(io, tw, d.L, b, c0 + c, k);
+        xb[g] = unit_adjoint_bin<T>(io, tw, d.L, b, c0 + c, N - k);
+      }
+    } else {
+      cpx<TIN> sa[G], sb[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {  // first partial spectrum
+        const int idx = base + g * nthr;
+        const bool ok = idx < total && (idx & (C - 1)) < ncol;
+        const int k = ok ? idx >> logC : 0, c = ok ? idx & (C - 1) : 0;
+        sa[g] = in[(int64_t)k * io.in_row + c];
+        sb[g] = in[(int64_t)(N - k) * io.in_row + c];
+      }
+      if (io.nparts > 1) add_partials<G>(in, io, base, total, nthr, logC, ncol, N, sa, sb);
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        xa[g] = {(T)sa[g].x, (T)sa[g].y};
+        xb[g] = {(T)sb[g].x, (T)sb[g].y};
       }
     }
-    if (k == 0) {  // bins 0 and N of a real series are real
-      xa.y = 0;
-      xb.y = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int idx = base + g * nthr;
+      if (idx >= total) continue;
+      const int k = idx >> logC, c = idx & (C - 1);
+      if (c >= ncol) xa[g] = xb[g] = cpx<T>{0, 0};
+      if (k == 0) {  // bins 0 and N of a real series are real
+        xa[g].y = 0;
+        xb[g].y = 0;
+      }
+      buf[(k << logC) + c] = unsplit(xa[g], xb[g], tw[k]);
+      const int k2 = N - k;
+      if (k2 != k && k2 < N) buf[(k2 << logC) + c] = unsplit(xb[g], xa[g], tw[k2]);
     }
-    buf[(k << logC) + c] = unsplit(xa, xb, tw[k]);
-    const int k2 = N - k;
-    if (k2 != k && k2 < N) buf[(k2 << logC) + c] = unsplit(xb, xa, tw[k2]);
   }
   dif_all_stages<T>(buf, d, tw, true, logC, tid, nthr);
 
