@@ -500,10 +500,11 @@ def bench_mrhs(args):
 
 
 def bench_inversion(torch, S, P):
-    """K = Gn + F Gp F* (20000 x 20000), the posterior mean, and the QoI
-    posterior (Q, Gamma_post(q)) with its online prediction q = Q d at the
-    100 x 5000 x 200 inversion workload with 21 QoI locations: wall time of
-    each call (the prediction by events)."""
+    """K = Gn + F Gp F* (20000 x 20000; by the paper's unit-vector matvecs
+    and in Gram form), the posterior mean, and the QoI posterior
+    (Q, Gamma_post(q); both assembly methods) with its online prediction
+    q = Q d at the 100 x 5000 x 200 inversion workload with 21 QoI
+    locations: wall time of each call (the prediction by events)."""
     Nd, Nm, Nt, seed = 100, 5000, 200, 5
     stream = torch.cuda.current_stream()
     env = torch.from_numpy(S.envelope(Nt, 40.0, 1.0 / np.sqrt(Nm))).cuda()
@@ -524,6 +525,17 @@ def bench_inversion(torch, S, P):
     plan.hessian(0.25, nv, out=K)
     torch.cuda.synchronize()
     t_k = time.perf_counter() - t0
+    # the same K in Gram form (time-domain blocks, one GEMM, block-diagonal sums)
+    K2 = torch.empty_like(K)
+    plan.hessian(0.25, nv, out=K2, method="gram")  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.hessian(0.25, nv, out=K2, method="gram")
+    torch.cuda.synchronize()
+    t_kg = time.perf_counter() - t0
+    e_kg = ((K2 - K).abs().max() / K.abs().max()).item()
+    del K2
+    plan.set_assembly("matvec")
     t0 = time.perf_counter()
     m = plan.posterior(K, d_obs, 0.25, refine_steps=1)
     torch.cuda.synchronize()
@@ -541,6 +553,15 @@ def bench_inversion(torch, S, P):
     Q, Gq = plan.qoi_precompute(planq, K, 0.25)
     torch.cuda.synchronize()
     t_q = time.perf_counter() - t0
+    del Gq
+    plan.qoi_precompute(planq, K, 0.25, method="gram")  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Q2, Gq = plan.qoi_precompute(planq, K, 0.25, method="gram")
+    torch.cuda.synchronize()
+    t_qg = time.perf_counter() - t0
+    e_qg = ((Q2 - Q).abs().max() / Q.abs().max()).item()
+    del Q2
     q = P.qoi_predict(Q, d_obs)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     reps = 20
@@ -560,8 +581,10 @@ def bench_inversion(torch, S, P):
     units = n
     return {"workload": f"Nd={Nd} Nm={Nm} Nt={Nt}, K {n}x{n} float64; Nq={Nq} QoI locations",
             "hessian_assemble_s": round(t_k, 3), "unit_vectors_per_s": round(units / t_k, 1),
+            "hessian_gram_s": round(t_kg, 4), "hessian_gram_vs_matvec_rel": e_kg,
             "posterior_solve_s": round(t_m, 3), "map_gradient_rel": res,
-            "qoi_precompute_s": round(t_q, 3),
+            "qoi_precompute_s": round(t_q, 3), "qoi_precompute_gram_s": round(t_qg, 3),
+            "qoi_gram_vs_matvec_rel": e_qg,
             "qoi_predict_ms": round(t_p * 1e3, 4),
             "qoi_predict_hbm_gbs": round(q_bytes / t_p / 1e9, 1),
             "qoi_predict_vs_fq_mmap_rel": e_q}

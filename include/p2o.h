@@ -201,17 +201,45 @@ void p2o_batch_destroy(p2o_batch b);
 
 /* K = Gamma_noise + F Gamma_prior F* (Phase 2), Gamma_prior =
  * prior_var * (I (x) C) (C = I unless p2o_set_prior selected a spatial
- * covariance), Gamma_noise = diag(noise_var), formed as the paper does:
- * one F Gamma_prior F* product per unit vector of data space, in batches.
+ * covariance), Gamma_noise = diag(noise_var), formed as the paper does
+ * (one F Gamma_prior F* product per unit vector of data space, in batches)
+ * or in Gram form, as p2o_set_assembly selects.
  *   noise_var  device [Nt*Nd] float64 (> 0 expected, not checked)
  *   K          device [(Nt*Nd)^2] float64 row-major, caller-allocated;
  *              entry (i*Nd + s, j*Nd + r) couples sensor s at step i with
- *              sensor r at step j.  K is symmetrised, (K + K^T)/2.
+ *              sensor r at step j.  K is symmetrised: (K + K^T)/2 by the
+ *              unit-vector method, the lower triangle mirrored by the Gram
+ *              form.
  * Requires a P2O_FP64 plan (else P2O_EUNSUPPORTED).  Allocates a temporary
- * workspace of up to ~8 GB and synchronises `stream`. */
+ * workspace (up to ~8 GB by the unit-vector method; see p2o_assembly for
+ * the Gram form) and synchronises `stream`. */
 p2o_status p2o_hessian_assemble(p2o_handle h, double prior_var,
                                 const double* noise_var, double* K,
                                 void* stream);
+
+/* How p2o_hessian_assemble and p2o_qoi_precompute (there: the p2o plan's
+ * setting) form their products F Gamma_prior F* (and Fq Gamma_prior F*,
+ * Fq Gamma_prior Fq*); both give the same matrix up to rounding.
+ *   P2O_ASSEMBLE_MATVEC (default): the paper's Phase 2, one FFT-based
+ *     F Gamma_prior F* product per unit vector of data space, in batches
+ *     (about 8 nf Nd^2 Nm Nt flops for K).
+ *   P2O_ASSEMBLE_GRAM: the time-domain blocks F_0 .. F_{Nt-1} are recovered
+ *     from the frequency blocks by one inverse transform and stacked into
+ *     the (Nt Nd) x Nm matrix A (row t*Nd + s = row s of F_t); then
+ *     G = prior_var A C A^T (one float64 matrix-core GEMM, lower triangle,
+ *     about (Nt Nd)^2 Nm flops) and, because F is block lower triangular
+ *     Toeplitz, block (t, u) of F Gamma_prior F* is the sum over
+ *     l <= min(t, u) of block (t - l, u - l) of G: prefix sums along the
+ *     block diagonals.  Needs (Nt Nd) Nm doubles of temporary memory (three
+ *     times that again with a spatial prior). */
+typedef enum {
+  P2O_ASSEMBLE_MATVEC = 0,
+  P2O_ASSEMBLE_GRAM = 1
+} p2o_assembly;
+
+/* Selects the assembly method of the plan's later inversion calls.
+ * P2O_EINVAL on a null handle or an unknown method.  Host-side only. */
+p2o_status p2o_set_assembly(p2o_handle h, p2o_assembly method);
 
 /* Posterior mean m = Gamma_prior F* K^{-1} d (Phase 4, zero prior mean;
  * Gamma_prior as for p2o_hessian_assemble).
@@ -271,8 +299,8 @@ p2o_status p2o_set_prior(p2o_handle h, const p2o_prior_grid* prior, void* stream
  *   Gq = Fq Gamma_post Fq* = Fq Gamma_prior Fq* - Q (F Gamma_prior Fq*)
  *        (the QoI posterior covariance), symmetrised.
  * Formed from the N_t Nq unit vectors of QoI space with the F / F* machinery
- * of p2o_hessian_assemble and one blocked solve with K's factor for all of
- * them at once.
+ * of p2o_hessian_assemble (or in Gram form, as hF's p2o_set_assembly
+ * selects) and one blocked solve with K's factor for all of them at once.
  *   hF    the p2o plan (Nd, Nm, Nt), hq the p2q plan (Nq, Nm, Nt); both
  *         P2O_FP64 and ready, with the same Nm and Nt (else P2O_EINVAL).
  *   Kfac  device [(Nt*Nd)^2]: K after p2o_posterior_solve (its Cholesky

@@ -25,6 +25,7 @@ FP64, MIXED_FP16, MIXED_BF16, FAST_BF16 = 0, 1, 2, 3
 PREC_BY_NAME = {"fp64": FP64, "mixed_fp16": MIXED_FP16, "mixed_bf16": MIXED_BF16,
                 "fast_bf16": FAST_BF16}
 OP_F, OP_FADJ = 0, 1
+ASSEMBLY = {"matvec": 0, "gram": 1}  # p2o_assembly
 
 STATUS = {0: "P2O_OK", 1: "P2O_EINVAL", 2: "P2O_ENOMEM", 3: "P2O_EHIP",
           4: "P2O_ENOTPD", 5: "P2O_ESTATE", 6: "P2O_EUNSUPPORTED"}
@@ -53,6 +54,7 @@ _SIGNATURES = {
                                    _c.POINTER(_i64), _vp]),
     "p2o_qoi_precompute": (_int, [_vp, _vp, _vp, _dbl, _vp, _vp, _vp]),
     "p2o_set_prior": (_int, [_vp, _c.POINTER(_PriorGrid), _vp]),
+    "p2o_set_assembly": (_int, [_vp, _int]),
     "p2o_qoi_predict": (_int, [_vp, _i64, _i64, _vp, _vp, _i64, _vp]),
     "p2o_destroy": (None, [_vp]),
     "p2o_status_string": (_c.c_char_p, [_int]),
@@ -228,9 +230,23 @@ class Plan:
     def FT(self, d: torch.Tensor, out=None, stream=None) -> torch.Tensor:
         return self.apply(OP_FADJ, d, out, stream)
 
+    def set_assembly(self, method: str) -> None:
+        """How hessian() and qoi_precompute() form their F Gamma_prior F*
+        products: "matvec" (one FFT-based product per unit vector, the
+        paper's Phase 2; the default) or "gram" (Gram matrix of the
+        time-domain blocks, then prefix sums along the block diagonals)."""
+        if method not in ASSEMBLY:
+            raise ValueError(f"method must be one of {sorted(ASSEMBLY)}")
+        _check("p2o_set_assembly", self._lib.p2o_set_assembly(self._handle(), ASSEMBLY[method]))
+
     def hessian(self, prior_var: float, noise_var: torch.Tensor,
-                out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-        """K = Gamma_noise + F (prior_var I) F*, [(Nt Nd)][(Nt Nd)] float64."""
+                out: torch.Tensor | None = None, stream=None,
+                method: str | None = None) -> torch.Tensor:
+        """K = Gamma_noise + F Gamma_prior F*, [(Nt Nd)][(Nt Nd)] float64,
+        Gamma_prior = prior_var (I (x) C).  `method`, when given, is set as the
+        plan's assembly method first (see set_assembly)."""
+        if method is not None:
+            self.set_assembly(method)
         n = self.Nt * self.Nd
         noise_var = _dev_f64(noise_var, "noise_var")
         if noise_var.numel() != n:
@@ -281,10 +297,13 @@ class Plan:
                                                       _stream_handle(stream)))
 
     def qoi_precompute(self, qoi_plan: "Plan", K: torch.Tensor, prior_var: float,
-                       stream=None):
+                       stream=None, method: str | None = None):
         """Phase 3 with this plan as the p2o map and `qoi_plan` as the p2q map:
         (Q, Gq) with Q = Fq Gp F* K^{-1} ([(Nt Nq)][(Nt Nd)]) and
-        Gq = Fq Gamma_post Fq* ([(Nt Nq)]^2).  K: as left by posterior()."""
+        Gq = Fq Gamma_post Fq* ([(Nt Nq)]^2).  K: as left by posterior().
+        `method`, when given, is set as this plan's assembly method first."""
+        if method is not None:
+            self.set_assembly(method)
         K = _dev_f64(K, "K")
         n, nq = self.Nt * self.Nd, qoi_plan.Nt * qoi_plan.Nd
         if tuple(K.shape) != (n, n):

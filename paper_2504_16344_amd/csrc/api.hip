@@ -807,6 +807,66 @@ p2o_status assemble_rows(p2o_plan_s* ha, p2o_plan_s* hf, const p2o_plan_s* hp,
   return P2O_OK;
 }
 
+// The time-domain blocks F_0 .. F_{Nt-1} of an FP64 plan, recovered from
+// its frequency blocks by one inverse transform over all Nd Nm series
+// (exact up to rounding: the spectra are those of the zero-padded series):
+// out [Nt][Nd][Nm], i.e. the (Nt Nd) x Nm matrix whose row t Nd + s is row s
+// of F_t.
+hipError_t time_blocks(const p2o_plan_s* h, double* out, hipStream_t s) {
+  FftIo io{};
+  io.in = h->fhat;
+  io.out = out;
+  io.ncols = h->Nd * h->Nm;
+  io.in_row = h->Nd * h->Nm;
+  io.out_row = h->Nd * h->Nm;
+  io.nparts = 1;
+  io.scale = 1.0 / (double)h->L;
+  return launch_rfft_inv_f64(h->fft, h->tw64, h->perm, io, 1, s);
+}
+
+// The same rows as assemble_rows, from the Gram form of the product.  With
+// the stacked time-domain blocks of ha (rows (a, j)) and of hf (rows (b, i)),
+//   G = prior_var Fa C Ff^T,
+// the entry of F_hf Gamma_prior F_ha^* coupling output (t, i) with unit
+// vector (u, j) is the sum over l <= min(t, u) of G[(u - l, j)][(t - l, i)]
+// (the block Toeplitz F_hf and F_ha share their time steps): one matrix-core
+// GEMM and one pass of prefix sums along the block diagonals.  With `lower`
+// (ha == hf: the product is symmetric) only the lower triangle of `out` is
+// written.
+p2o_status assemble_gram(const p2o_plan_s* ha, const p2o_plan_s* hf, const p2o_plan_s* hp,
+                         double prior_var, double* out, int64_t ldo, bool lower,
+                         hipStream_t s) {
+  const int64_t na = ha->Nt * ha->Nd, nb = hf->Nt * hf->Nd, Nm = hf->Nm;
+  const bool prior = hp->prior_w != nullptr;
+  DevBufs bufs;
+  void *fa, *ff = nullptr;
+  TRY_HIP(bufs.alloc(&fa, (size_t)na * Nm * 8));
+  TRY_HIP(time_blocks(ha, static_cast<double*>(fa), s));
+  if (hf == ha && !prior) {
+    ff = fa;
+  } else {
+    TRY_HIP(bufs.alloc(&ff, (size_t)nb * Nm * 8));
+    if (hf == ha)
+      TRY_HIP(hipMemcpyAsync(ff, fa, (size_t)nb * Nm * 8, hipMemcpyDeviceToDevice, s));
+    else
+      TRY_HIP(time_blocks(hf, static_cast<double*>(ff), s));
+  }
+  if (prior) {  // Ff <- Ff C (C symmetric): C on every row
+    void *t1, *t2;
+    TRY_HIP(bufs.alloc(&t1, (size_t)nb * Nm * 8));
+    TRY_HIP(bufs.alloc(&t2, (size_t)nb * Nm * 8));
+    TRY_HIP(launch_apply_prior(static_cast<double*>(ff), static_cast<double*>(t1),
+                               static_cast<double*>(t2), nb, hp->prior_nx, hp->prior_ny,
+                               hp->prior_w, hp->prior_r, hp->prior_delta, s));
+  }
+  TRY_HIP(launch_dgemm_nt_set(lower, na, nb, Nm, prior_var, static_cast<const double*>(fa), Nm,
+                              static_cast<const double*>(ff), Nm, out, ldo, s));
+  TRY_HIP(launch_block_diag_scan(out, ldo, ha->Nt, ha->Nd, hf->Nd, lower, s));
+  // the scratch buffers are freed on return: finish their users first
+  TRY_HIP(hipStreamSynchronize(s));
+  return P2O_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -820,10 +880,22 @@ p2o_status p2o_hessian_assemble(p2o_handle h, double prior_var,
   (void)hipGetLastError();
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = h->Nt * h->Nd;
-  TRY_ST(assemble_rows(h, h, h, prior_var, K, n, s));
-  TRY_HIP(launch_add_diagonal(K, noise_var, n, s));
-  TRY_HIP(launch_symmetrize(K, n, s));
+  if (h->assembly == P2O_ASSEMBLE_GRAM) {
+    TRY_ST(assemble_gram(h, h, h, prior_var, K, n, true, s));
+    TRY_HIP(launch_add_diagonal(K, noise_var, n, s));
+    TRY_HIP(launch_mirror_lower(K, n, s));
+  } else {
+    TRY_ST(assemble_rows(h, h, h, prior_var, K, n, s));
+    TRY_HIP(launch_add_diagonal(K, noise_var, n, s));
+    TRY_HIP(launch_symmetrize(K, n, s));
+  }
   TRY_HIP(hipStreamSynchronize(s));
+  return P2O_OK;
+}
+
+p2o_status p2o_set_assembly(p2o_handle h, p2o_assembly method) {
+  if (!h || (method != P2O_ASSEMBLE_MATVEC && method != P2O_ASSEMBLE_GRAM)) return P2O_EINVAL;
+  h->assembly = method;
   return P2O_OK;
 }
 
@@ -840,14 +912,23 @@ p2o_status p2o_qoi_precompute(p2o_handle hF, p2o_handle hq, const double* Kfac,
   void* bt;  // rows j: F Gp Fq^* e_j (columns of B = F Gp Fq^*)
   TRY_HIP(bufs.alloc(&bt, (size_t)nq * n * 8));
   double* Bt = static_cast<double*>(bt);
-  TRY_ST(assemble_rows(hq, hF, hF, prior_var, Bt, n, s));
-  TRY_ST(assemble_rows(hq, hq, hF, prior_var, Gq, nq, s));  // Fq Gp Fq^*
+  const bool gram = hF->assembly == P2O_ASSEMBLE_GRAM;
+  if (gram) {
+    TRY_ST(assemble_gram(hq, hF, hF, prior_var, Bt, n, false, s));
+    TRY_ST(assemble_gram(hq, hq, hF, prior_var, Gq, nq, true, s));  // lower triangle
+  } else {
+    TRY_ST(assemble_rows(hq, hF, hF, prior_var, Bt, n, s));
+    TRY_ST(assemble_rows(hq, hq, hF, prior_var, Gq, nq, s));  // Fq Gp Fq^*
+  }
   // Q = Fq Gp F^* K^{-1} = (K^{-1} B)^T: row j of Q is K^{-1} (column j of B)
   TRY_HIP(hipMemcpyAsync(Q, Bt, (size_t)nq * n * 8, hipMemcpyDeviceToDevice, s));
   TRY_HIP(launch_cholesky_solve_many(Kfac, Q, n, nq, s));
   // Gq = Fq Gp Fq^* - Q B
   TRY_HIP(launch_dgemm(true, nq, nq, n, -1.0, Q, n, Bt, n, Gq, nq, s));
-  TRY_HIP(launch_symmetrize(Gq, nq, s));
+  if (gram)
+    TRY_HIP(launch_mirror_lower(Gq, nq, s));
+  else
+    TRY_HIP(launch_symmetrize(Gq, nq, s));
   TRY_HIP(hipStreamSynchronize(s));
   return P2O_OK;
 }

@@ -19,8 +19,9 @@ constexpr int kTriNb = 64;     // triangular-solve block (the Cholesky block siz
 // in LDS as [k][row] for both operands.
 // With LOWER (a symmetric rank-k update of a lower triangle, M == N), the
 // grid enumerates only the tiles I >= J and entries above the diagonal are
-// left untouched.
-template <bool TRANSB, bool LOWER>
+// left untouched.  Without ACC, C is overwritten (C = alpha A op(B)) and
+// never read.
+template <bool TRANSB, bool LOWER, bool ACC = true>
 __global__ void __launch_bounds__(256)
 dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A,
              int64_t lda, const double* __restrict__ B, int64_t ldb, double* __restrict__ C,
@@ -93,8 +94,60 @@ dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __rest
       for (int r = 0; r < 4; ++r) {
         const int64_t gi = i0 + wr + 16 * ti + kq + 4 * r;  // accumulator rows interleave
         const int64_t gj = j0 + wc + 16 * tj + col;
-        if (gi < M && gj < N && (!LOWER || gj <= gi)) C[gi * ldc + gj] += alpha * acc[ti][tj][r];
+        if (gi < M && gj < N && (!LOWER || gj <= gi)) {
+          if constexpr (ACC)
+            C[gi * ldc + gj] += alpha * acc[ti][tj][r];
+          else
+            C[gi * ldc + gj] = alpha * acc[ti][tj][r];
+        }
       }
+}
+
+// Prefix sums along the block diagonals of X (rows (a, i) = a P + i, columns
+// (b, j) = b Q + j, a, b < T):
+//   X[(a, i)][(b, j)] <- sum_{l = 0 .. min(a, b)} X[(a - l, i)][(b - l, j)].
+// One thread walks one chain (r, c), (r + P, c + Q), ... from its first
+// entry (a = 0 or b = 0); chains are disjoint, so the sums are formed in
+// place.  Lanes take consecutive columns of a chain start row, so every step
+// of a wavefront reads a contiguous run.  With LOWER (P == Q, a symmetric
+// matrix of which only the lower triangle is kept) chains that start above
+// the diagonal are skipped and every other chain stays on or below it.
+constexpr int kScanGroup = 8;  // chain entries loaded ahead of their sums
+__global__ void __launch_bounds__(256)
+block_diag_scan(double* __restrict__ X, int64_t ld, int64_t T, int64_t P, int64_t Q, int lower) {
+  const int64_t R = T * P, Cn = T * Q;
+  const int64_t nA = lower ? 0 : P * Cn;               // chains from block row 0
+  const int64_t nB = lower ? R * Q : (R - P) * Q;      // chains from block column 0
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nA + nB;
+       e += (int64_t)gridDim.x * 256) {
+    int64_t r0, c0;
+    if (e < nA) {
+      r0 = e / Cn;
+      c0 = e - r0 * Cn;
+    } else {
+      const int64_t f = e - nA;
+      r0 = (lower ? 0 : P) + f / Q;
+      c0 = f % Q;
+    }
+    if (lower && c0 > r0) continue;
+    const int64_t steps = std::min((R - 1 - r0) / P, (Cn - 1 - c0) / Q) + 1;
+    const int64_t stride = P * ld + Q;
+    double* __restrict__ p = X + r0 * ld + c0;
+    double acc = 0.0;
+    for (int64_t l = 0; l < steps; l += kScanGroup) {
+      double v[kScanGroup];
+#pragma unroll
+      for (int g = 0; g < kScanGroup; ++g)  // clamped: every load in bounds
+        v[g] = p[std::min(l + g, steps - 1) * stride];
+#pragma unroll
+      for (int g = 0; g < kScanGroup; ++g) {
+        if (l + g < steps) {
+          acc += v[g];
+          p[(l + g) * stride] = acc;
+        }
+      }
+    }
+  }
 }
 
 // Diagonal blocks of the triangular solves for many right-hand sides.  Y is
@@ -200,6 +253,35 @@ hipError_t launch_dgemm(bool transb, int64_t M, int64_t N, int64_t K, double alp
   else
     hipLaunchKernelGGL((dgemm_kernel<false, false>), grid, dim3(256), 0, s, M, N, K, alpha, A,
                        lda, B, ldb, C, ldc);
+  return hipGetLastError();
+}
+
+hipError_t launch_dgemm_nt_set(bool lower, int64_t M, int64_t N, int64_t K, double alpha,
+                               const double* A, int64_t lda, const double* B, int64_t ldb,
+                               double* C, int64_t ldc, hipStream_t s) {
+  if (M <= 0 || N <= 0 || (lower && M != N)) return hipErrorInvalidValue;
+  if (K <= 0) return hipErrorInvalidValue;
+  if (lower) {
+    const int64_t T = (N + kGemmTile - 1) / kGemmTile;
+    const int64_t tiles = T * (T + 1) / 2;
+    if (tiles > 0x7fffffff) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((dgemm_kernel<true, true, false>), dim3((unsigned)tiles), dim3(256), 0, s,
+                       M, N, K, alpha, A, lda, B, ldb, C, ldc);
+  } else {
+    const int64_t gx = (N + kGemmTile - 1) / kGemmTile, gy = (M + kGemmTile - 1) / kGemmTile;
+    if (gx > 0x7fffffff || gy > 65535) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((dgemm_kernel<true, false, false>), dim3((unsigned)gx, (unsigned)gy),
+                       dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, C, ldc);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_block_diag_scan(double* X, int64_t ld, int64_t T, int64_t P, int64_t Q,
+                                  bool lower, hipStream_t s) {
+  if (T <= 0 || P <= 0 || Q <= 0 || (lower && P != Q)) return hipErrorInvalidValue;
+  const int64_t chains = lower ? T * P * Q : P * T * Q + (T - 1) * P * Q;
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((chains + 255) / 256, 1 << 20));
+  hipLaunchKernelGGL(block_diag_scan, dim3(g), dim3(256), 0, s, X, ld, T, P, Q, lower ? 1 : 0);
   return hipGetLastError();
 }
 

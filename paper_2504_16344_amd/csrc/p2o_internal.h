@@ -184,7 +184,8 @@ hipError_t launch_batch_product(BatchClass cls, p2o_op op, const BatchInst* inst
 
 // ------------------------------------------------------- inversion kernels
 hipError_t launch_add_diagonal(double* K, const double* v, int64_t n, hipStream_t s);
-hipError_t launch_symmetrize(double* K, int64_t n, hipStream_t s);
+hipError_t launch_symmetrize(double* K, int64_t n, hipStream_t s);    // (K + K^T) / 2
+hipError_t launch_mirror_lower(double* K, int64_t n, hipStream_t s);  // upper <- lower
 hipError_t launch_cholesky(double* K, int64_t n, int64_t* info_dev, hipStream_t s);
 hipError_t launch_cholesky_solve(const double* K, double* Y, double* part, int64_t n,
                                  int64_t nrhs, hipStream_t s);
@@ -205,6 +206,16 @@ hipError_t launch_dgemm(bool transb, int64_t M, int64_t N, int64_t K, double alp
 // diagonal untouched.
 hipError_t launch_dsyrk_lower(int64_t n, int64_t K, double alpha, const double* A, int64_t lda,
                               double* C, int64_t ldc, hipStream_t s);
+// C[M x N] = alpha A[M x K] B[N x K]^T, row-major, C overwritten (not read);
+// with lower (M == N) only the lower triangle of C is written.
+hipError_t launch_dgemm_nt_set(bool lower, int64_t M, int64_t N, int64_t K, double alpha,
+                               const double* A, int64_t lda, const double* B, int64_t ldb,
+                               double* C, int64_t ldc, hipStream_t s);
+// In place prefix sums along the block diagonals of X [T P][T Q] (leading
+// dimension ld): X[(a, i)][(b, j)] <- sum_{l <= min(a, b)} X[(a - l, i)][(b - l, j)];
+// with lower (P == Q) only the lower triangle is read and written.
+hipError_t launch_block_diag_scan(double* X, int64_t ld, int64_t T, int64_t P, int64_t Q,
+                                  bool lower, hipStream_t s);
 // Y[nrhs][n] <- K^{-1} Y with K's Cholesky factor in the lower triangle of K
 // (no scratch; any nrhs, efficient from a few tens of right-hand sides on).
 hipError_t launch_cholesky_solve_many(const double* K, double* Y, int64_t n, int64_t nrhs,
@@ -242,6 +253,7 @@ struct p2o_plan_s {
   int64_t prior_nx = 0, prior_ny = 0;
   int prior_r = 0;
   double prior_delta = 0.0;
+  int assembly = 0;                  // p2o_assembly of the inversion calls
   bool ready = false;
   void* scratch = nullptr;           // setup chunk staging (mixed)
   size_t scratch_bytes = 0;
