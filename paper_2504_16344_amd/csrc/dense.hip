@@ -11,17 +11,20 @@ namespace {
 constexpr int kGemmTile = 64;  // C tile per workgroup (rows and columns)
 constexpr int kGemmK = 16;     // contraction chunk staged in LDS
 constexpr int kTriNb = 64;     // triangular-solve block (the Cholesky block size)
+constexpr int64_t kSolvePanel = 256;  // columns per rank-k update of the solves
 
 // C[i][j] += alpha sum_k A[i][k] op(B)[k][j] for i < M, j < N, row-major,
 // op(B)[k][j] = B[j][k] (TRANSB) or B[k][j].  A workgroup owns a 64 x 64
 // tile of C, each of its 4 wavefronts a 32 x 32 quarter (2 x 2
 // v_mfma_f64_16x16x4 tiles); 16-entry chunks of the contraction are staged
 // in LDS as [k][row] for both operands.
-// With LOWER (a symmetric rank-k update of a lower triangle, M == N), the
-// grid enumerates only the tiles I >= J and entries above the diagonal are
-// left untouched.  Without ACC, C is overwritten (C = alpha A op(B)) and
-// never read.
-template <bool TRANSB, bool LOWER, bool ACC = true>
+// Triangle modes: kTriGrid (a symmetric rank-k update of a lower triangle,
+// M == N) enumerates only the tiles I >= J and leaves the entries above the
+// diagonal untouched; kTriMask keeps the rectangular grid and only masks
+// the entries above the diagonal (a panel whose top square straddles it).
+// Without ACC, C is overwritten (C = alpha A op(B)) and never read.
+enum { kFull = 0, kTriGrid = 1, kTriMask = 2 };
+template <bool TRANSB, int TRI, bool ACC = true>
 __global__ void __launch_bounds__(256)
 dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A,
              int64_t lda, const double* __restrict__ B, int64_t ldb, double* __restrict__ C,
@@ -31,7 +34,7 @@ dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __rest
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, kq = lane >> 4;
   int64_t ti_ = blockIdx.y, tj_ = blockIdx.x;
-  if constexpr (LOWER) {  // linear index t -> (I, J), J <= I
+  if constexpr (TRI == kTriGrid) {  // linear index t -> (I, J), J <= I
     const int64_t t = blockIdx.x;
     int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) / 2.0);
     while (I * (I + 1) / 2 > t) --I;
@@ -94,7 +97,7 @@ dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __rest
       for (int r = 0; r < 4; ++r) {
         const int64_t gi = i0 + wr + 16 * ti + kq + 4 * r;  // accumulator rows interleave
         const int64_t gj = j0 + wc + 16 * tj + col;
-        if (gi < M && gj < N && (!LOWER || gj <= gi)) {
+        if (gi < M && gj < N && (TRI == kFull || gj <= gi)) {
           if constexpr (ACC)
             C[gi * ldc + gj] += alpha * acc[ti][tj][r];
           else
@@ -248,10 +251,10 @@ hipError_t launch_dgemm(bool transb, int64_t M, int64_t N, int64_t K, double alp
   if (gx > 0x7fffffff || gy > 65535) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)gx, (unsigned)gy);
   if (transb)
-    hipLaunchKernelGGL((dgemm_kernel<true, false>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
+    hipLaunchKernelGGL((dgemm_kernel<true, kFull>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
                        B, ldb, C, ldc);
   else
-    hipLaunchKernelGGL((dgemm_kernel<false, false>), grid, dim3(256), 0, s, M, N, K, alpha, A,
+    hipLaunchKernelGGL((dgemm_kernel<false, kFull>), grid, dim3(256), 0, s, M, N, K, alpha, A,
                        lda, B, ldb, C, ldc);
   return hipGetLastError();
 }
@@ -265,14 +268,25 @@ hipError_t launch_dgemm_nt_set(bool lower, int64_t M, int64_t N, int64_t K, doub
     const int64_t T = (N + kGemmTile - 1) / kGemmTile;
     const int64_t tiles = T * (T + 1) / 2;
     if (tiles > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((dgemm_kernel<true, true, false>), dim3((unsigned)tiles), dim3(256), 0, s,
+    hipLaunchKernelGGL((dgemm_kernel<true, kTriGrid, false>), dim3((unsigned)tiles), dim3(256), 0, s,
                        M, N, K, alpha, A, lda, B, ldb, C, ldc);
   } else {
     const int64_t gx = (N + kGemmTile - 1) / kGemmTile, gy = (M + kGemmTile - 1) / kGemmTile;
     if (gx > 0x7fffffff || gy > 65535) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((dgemm_kernel<true, false, false>), dim3((unsigned)gx, (unsigned)gy),
+    hipLaunchKernelGGL((dgemm_kernel<true, kFull, false>), dim3((unsigned)gx, (unsigned)gy),
                        dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, C, ldc);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_dgemm_nt_lower_mask(int64_t M, int64_t N, int64_t K, double alpha,
+                                      const double* A, int64_t lda, const double* B,
+                                      int64_t ldb, double* C, int64_t ldc, hipStream_t s) {
+  if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+  const int64_t gx = (N + kGemmTile - 1) / kGemmTile, gy = (M + kGemmTile - 1) / kGemmTile;
+  if (gx > 0x7fffffff || gy > 65535) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((dgemm_kernel<true, kTriMask>), dim3((unsigned)gx, (unsigned)gy), dim3(256),
+                     0, s, M, N, K, alpha, A, lda, B, ldb, C, ldc);
   return hipGetLastError();
 }
 
@@ -291,38 +305,51 @@ hipError_t launch_dsyrk_lower(int64_t n, int64_t K, double alpha, const double* 
   const int64_t T = (n + kGemmTile - 1) / kGemmTile;
   const int64_t tiles = T * (T + 1) / 2;
   if (tiles > 0x7fffffff) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((dgemm_kernel<true, true>), dim3((unsigned)tiles), dim3(256), 0, s, n, n, K,
+  hipLaunchKernelGGL((dgemm_kernel<true, kTriGrid>), dim3((unsigned)tiles), dim3(256), 0, s, n, n, K,
                      alpha, A, lda, A, lda, C, ldc);
   return hipGetLastError();
 }
 
 // K holds the Cholesky factor L in its lower triangle.  Y ([nrhs][n]) is
 // overwritten by K^{-1} Y = L^{-T} L^{-1} Y: block by block, the diagonal
-// solve of every right-hand side, then the trailing update of all of them
-// as one matrix-core GEMM (forward: Y[:, rest] -= Y[:, blk] L[rest, blk]^T;
-// backward: Y[:, 0 : j0] -= Y[:, blk] L[blk, 0 : j0]).
+// solve of every right-hand side, then the update of the others as
+// matrix-core GEMMs (forward: Y[:, rest] -= Y[:, blk] L[rest, blk]^T;
+// backward: Y[:, 0 : j0] -= Y[:, blk] L[blk, 0 : j0]), the updates beyond
+// the current panel of kSolvePanel columns deferred and done as one.
 hipError_t launch_cholesky_solve_many(const double* K, double* Y, int64_t n, int64_t nrhs,
                                       hipStream_t s) {
   const unsigned g = grid_rhs(nrhs);
-  for (int64_t j0 = 0; j0 < n; j0 += kTriNb) {
-    const int bs = (int)std::min<int64_t>(kTriNb, n - j0);
-    hipLaunchKernelGGL(trsm_lower_diag_many, dim3(g), dim3(256), 0, s, K, Y, n, nrhs, j0, bs);
-    const int64_t j1 = j0 + bs;
-    if (j1 < n) {
-      const hipError_t e = launch_dgemm(true, nrhs, n - j1, bs, -1.0, Y + j0, n, K + j1 * n + j0,
-                                        n, Y + j1, n, s);
-      if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  // forward, L Z = Y: panels of kSolvePanel columns; inside a panel block by
+  // block (diagonal solve, update of the panel's later columns), then one
+  // rank-kSolvePanel update of all later columns
+  for (int64_t p0 = 0; p0 < n; p0 += kSolvePanel) {
+    const int64_t p1 = std::min(n, p0 + kSolvePanel);
+    for (int64_t j0 = p0; j0 < p1; j0 += kTriNb) {
+      const int bs = (int)std::min<int64_t>(kTriNb, p1 - j0);
+      hipLaunchKernelGGL(trsm_lower_diag_many, dim3(g), dim3(256), 0, s, K, Y, n, nrhs, j0, bs);
+      const int64_t j1 = j0 + bs;
+      if (j1 < p1 && (e = launch_dgemm(true, nrhs, p1 - j1, bs, -1.0, Y + j0, n,
+                                       K + j1 * n + j0, n, Y + j1, n, s)) != hipSuccess)
+        return e;
     }
+    if (p1 < n && (e = launch_dgemm(true, nrhs, n - p1, p1 - p0, -1.0, Y + p0, n,
+                                    K + p1 * n + p0, n, Y + p1, n, s)) != hipSuccess)
+      return e;
   }
-  const int64_t last = ((n - 1) / kTriNb) * kTriNb;
-  for (int64_t j0 = last; j0 >= 0; j0 -= kTriNb) {
-    const int bs = (int)std::min<int64_t>(kTriNb, n - j0);
-    hipLaunchKernelGGL(trsm_upper_diag_many, dim3(g), dim3(256), 0, s, K, Y, n, nrhs, j0, bs);
-    if (j0 > 0) {
-      const hipError_t e = launch_dgemm(false, nrhs, j0, bs, -1.0, Y + j0, n, K + j0 * n, n, Y,
-                                        n, s);
-      if (e != hipSuccess) return e;
+  // backward, L^T X = Z: the same from the last panel down
+  for (int64_t p0 = ((n - 1) / kSolvePanel) * kSolvePanel; p0 >= 0; p0 -= kSolvePanel) {
+    const int64_t p1 = std::min(n, p0 + kSolvePanel);
+    for (int64_t j0 = p0 + ((p1 - 1 - p0) / kTriNb) * kTriNb; j0 >= p0; j0 -= kTriNb) {
+      const int bs = (int)std::min<int64_t>(kTriNb, p1 - j0);
+      hipLaunchKernelGGL(trsm_upper_diag_many, dim3(g), dim3(256), 0, s, K, Y, n, nrhs, j0, bs);
+      if (j0 > p0 && (e = launch_dgemm(false, nrhs, j0 - p0, bs, -1.0, Y + j0, n,
+                                       K + j0 * n + p0, n, Y + p0, n, s)) != hipSuccess)
+        return e;
     }
+    if (p0 > 0 && (e = launch_dgemm(false, nrhs, p0, p1 - p0, -1.0, Y + p0, n, K + p0 * n, n, Y,
+                                    n, s)) != hipSuccess)
+      return e;
   }
   return hipGetLastError();
 }

@@ -60,66 +60,68 @@ symmetrize(double* __restrict__ K, int64_t n, int64_t T, int mirror) {
 }
 
 // ------------------------------------------------------------ Cholesky
-// Factor the bs x bs diagonal block at (j0, j0) in LDS; lower triangle
-// only (the strict upper triangle of K is left untouched).  The first
-// non-positive (or NaN) pivot index is recorded in *info.
-__global__ void __launch_bounds__(256)
-potrf_diag(double* __restrict__ K, int64_t n, int64_t j0, int bs,
-           int64_t* __restrict__ info) {
-  __shared__ double a[kNb][kNb + 1];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < bs * bs; e += blockDim.x) {
-    const int i = e / bs, j = e % bs;
-    a[i][j] = (j <= i) ? K[(j0 + i) * n + j0 + j] : 0.0;
-  }
-  for (int k = 0; k < bs; ++k) {
-    __syncthreads();
-    if (tid == 0) {
-      const double d = a[k][k];
-      if (!(d > 0.0) && *info < 0) *info = j0 + k;
-      a[k][k] = sqrt(d);
-    }
-    __syncthreads();
-    const double piv = a[k][k];
-    for (int i = k + 1 + tid; i < bs; i += blockDim.x) a[i][k] /= piv;
-    __syncthreads();
-    const int m = bs - k - 1;  // trailing size
-    for (int e = tid; e < m * m; e += blockDim.x) {
-      const int i = k + 1 + e / m, j = k + 1 + e % m;
-      if (j <= i) a[i][j] -= a[i][k] * a[j][k];
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < bs * bs; e += blockDim.x) {
-    const int i = e / bs, j = e % bs;
-    if (j <= i) K[(j0 + i) * n + j0 + j] = a[i][j];
-  }
-}
-
-// Panel rows r in [j1, n): X = B L11^{-T}; one wavefront per 64 rows.
+// One Cholesky step on the bs x bs diagonal block at (j0, j0) and the kNb
+// rows of the column below it that this work-group owns (one wavefront,
+// lane i owning row i of each LDS tile).  Every work-group factors the
+// diagonal block itself (the redundant work is a few microseconds and saves
+// a launch and a serialised step per block); work-group 0 writes it back
+// and records the first non-positive (or NaN) pivot in *info.
+//   factor: at step k every lane reads the pivot, lane k stores its square
+//           root, lanes i > k divide their entry k by it (column k of L),
+//           then subtract L_ik L_jk from their entries k < j <= i;
+//   solve:  each owned row b of the column panel becomes b L11^{-T},
+//           column by column.
+// Tiles are loaded coalesced (row u, column = lane), all loads unconditional
+// with clamped addresses.
 __global__ void __launch_bounds__(64)
-trsm_panel(double* __restrict__ K, int64_t n, int64_t j0, int bs) {
-  __shared__ double l[kNb][kNb + 1];
+potrf_trsm(double* __restrict__ K, int64_t n, int64_t j0, int bs, int64_t* __restrict__ info) {
+  __shared__ double a[kNb][kNb + 1];
   __shared__ double x[kNb][kNb + 1];
-  const int tid = threadIdx.x;
-  const int64_t j1 = j0 + bs;
-  const int64_t r0 = j1 + (int64_t)blockIdx.x * kNb;
-  const int rows = (int)min((int64_t)kNb, n - r0);
-  for (int i = 0; i < bs; ++i)
-    for (int j = tid; j < bs; j += 64) l[i][j] = (j <= i) ? K[(j0 + i) * n + j0 + j] : 0.0;
-  for (int i = 0; i < rows; ++i)
-    for (int j = tid; j < bs; j += 64) x[i][j] = K[(r0 + i) * n + j0 + j];
+  const int lane = threadIdx.x;
+  const int cl = min(lane, bs - 1);
+#pragma unroll 16
+  for (int u = 0; u < kNb; ++u) {
+    const double v = K[(j0 + min(u, bs - 1)) * n + j0 + cl];
+    a[u][lane] = (lane <= u) ? v : 0.0;
+  }
+  const int64_t r0 = j0 + bs + (int64_t)blockIdx.x * kNb;
+  const int rows = (int)max<int64_t>(0, min<int64_t>(kNb, n - r0));
+  if (rows > 0) {  // uniform across the work-group
+#pragma unroll 16
+    for (int u = 0; u < kNb; ++u) x[u][lane] = K[(r0 + min(u, rows - 1)) * n + j0 + cl];
+  }
   __syncthreads();
-  if (tid < rows) {
+  for (int k = 0; k < bs; ++k) {
+    const double d = a[k][k];
+    if (lane == 0 && blockIdx.x == 0 && !(d > 0.0) && *info < 0) *info = j0 + k;
+    const double piv = sqrt(d);
+    __syncthreads();  // every lane has read a[k][k]
+    if (lane == k) a[k][k] = piv;
+    if (lane > k && lane < bs) a[lane][k] /= piv;
+    __syncthreads();  // column k of L complete
+    if (lane > k && lane < bs) {
+      const double lik = a[lane][k];
+      for (int j = k + 1; j <= lane; ++j) a[lane][j] -= lik * a[j][k];
+    }
+    __syncthreads();
+  }
+  if (blockIdx.x == 0) {
+#pragma unroll 16
+    for (int u = 0; u < kNb; ++u)
+      if (u < bs && lane <= u) K[(j0 + u) * n + j0 + lane] = a[u][lane];
+  }
+  if (rows == 0) return;
+  if (lane < rows) {
     for (int c = 0; c < bs; ++c) {
-      double s = x[tid][c];
-      for (int t = 0; t < c; ++t) s -= x[tid][t] * l[c][t];
-      x[tid][c] = s / l[c][c];
+      const double xc = x[lane][c] / a[c][c];
+      x[lane][c] = xc;
+      for (int t = c + 1; t < bs; ++t) x[lane][t] -= xc * a[t][c];
     }
   }
   __syncthreads();
-  for (int i = 0; i < rows; ++i)
-    for (int j = tid; j < bs; j += 64) K[(r0 + i) * n + j0 + j] = x[i][j];
+#pragma unroll 16
+  for (int u = 0; u < kNb; ++u)
+    if (u < rows && lane < bs) K[(r0 + u) * n + j0 + lane] = x[u][lane];
 }
 
 // ------------------------------------------------------ triangular solves
@@ -305,22 +307,37 @@ hipError_t launch_mirror_lower(double* K, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Blocked right-looking Cholesky of the lower triangle.
+// Blocked right-looking Cholesky of the lower triangle, two levels: panels
+// of kPanel columns, each factored as kNb-wide blocks (diagonal block,
+// triangular solve of the column below it, update of the panel's remaining
+// columns), then one rank-kPanel update of the trailing lower triangle on
+// the float64 matrix cores.  The wide trailing update reads and writes the
+// trailing matrix kPanel / kNb times less often than block-by-block updates.
+constexpr int64_t kPanel = 256;
 hipError_t launch_cholesky(double* K, int64_t n, int64_t* info_dev, hipStream_t s) {
-  for (int64_t j0 = 0; j0 < n; j0 += kNb) {
-    const int bs = (int)std::min<int64_t>(kNb, n - j0);
-    hipLaunchKernelGGL(potrf_diag, dim3(1), dim3(256), 0, s, K, n, j0, bs, info_dev);
-    const int64_t m = n - j0 - bs;
-    if (m > 0) {
-      hipLaunchKernelGGL(trsm_panel, dim3(grid1(m, kNb)), dim3(64), 0, s, K, n, j0, bs);
-      // trailing update of the lower triangle on the float64 matrix cores
-      const int64_t j1 = j0 + bs;
-      const hipError_t e = launch_dsyrk_lower(m, bs, -1.0, K + j1 * n + j0, n, K + j1 * n + j1,
-                                              n, s);
+  for (int64_t p0 = 0; p0 < n; p0 += kPanel) {
+    const int64_t p1 = std::min(n, p0 + kPanel);
+    for (int64_t j0 = p0; j0 < p1; j0 += kNb) {
+      const int bs = (int)std::min<int64_t>(kNb, p1 - j0);
+      const int64_t j1 = j0 + bs, m = n - j1;
+      hipLaunchKernelGGL(potrf_trsm, dim3(m > 0 ? grid1(m, kNb) : 1), dim3(64), 0, s, K, n, j0,
+                         bs, info_dev);
+      if (m > 0) {
+        // the panel's columns j1 .. p1 - 1, rows j1 .. n - 1 (lower part only)
+        const hipError_t e =
+            launch_dgemm_nt_lower_mask(m, p1 - j1, bs, -1.0, K + j1 * n + j0, n,
+                                       K + j1 * n + j0, n, K + j1 * n + j1, n, s);
+        if (e != hipSuccess) return e;
+      }
+      const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    const int64_t mt = n - p1;
+    if (mt > 0) {  // trailing lower triangle -= panel panel^T
+      const hipError_t e = launch_dsyrk_lower(mt, p1 - p0, -1.0, K + p1 * n + p0, n,
+                                              K + p1 * n + p1, n, s);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }
