@@ -205,35 +205,67 @@ trsm_upper_diag_many(const double* __restrict__ K, double* __restrict__ Y, int64
 }
 
 // q[r][i] = sum_j Q[i][j] d[r][j] for RB right-hand sides at a time: one
-// wavefront per row of Q, 2 entries a lane per step, Q streamed once per
-// pass with non-temporal loads.
-template <int RB>
-__global__ void __launch_bounds__(256)
+// work-group of W wavefronts per RQ rows of Q, wavefront w summing the w-th
+// of W contiguous column ranges of all RQ rows (each d entry loaded once
+// serves RQ rows); each lane takes 2 consecutive entries per 128-entry step
+// and U steps per loop turn, all loads issued before any product
+// (unconditional, clamped addresses; entries past the range are zeroed at
+// the consumer).  The W partial sums are added in LDS in a fixed order.  Q
+// is streamed once per pass with non-temporal loads.
+template <int RB, int U, int W, int RQ>
+__global__ void __launch_bounds__(64 * W)
 qoi_gemv(const double* __restrict__ Q, const double* __restrict__ D, double* __restrict__ q,
          int64_t rows, int64_t cols, int64_t r0, int nb) {
-  const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= rows) return;
-  const double* __restrict__ Qi = Q + i * cols;
-  double acc[RB];
+  __shared__ double red[W][RQ][RB];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * RQ;
+  const double* __restrict__ Qr[RQ];
 #pragma unroll
-  for (int b = 0; b < RB; ++b) acc[b] = 0.0;
-  for (int64_t j = 2 * lane; j < cols; j += 128) {
-    const bool two = j + 1 < cols;
-    const double q0 = __builtin_nontemporal_load(Qi + j);
-    const double q1 = two ? __builtin_nontemporal_load(Qi + j + 1) : 0.0;
+  for (int w = 0; w < RQ; ++w) Qr[w] = Q + min(i0 + w, rows - 1) * cols;
+  const int64_t span = (cols + 128 * W - 1) / (128 * W) * 128;
+  const int64_t c0 = wave * span, c1 = min(cols, c0 + span);
+  double acc[RQ][RB];
 #pragma unroll
-    for (int b = 0; b < RB; ++b) {
-      if (b >= nb) break;
-      const double* __restrict__ d = D + (r0 + b) * cols;
-      acc[b] += q0 * d[j] + (two ? q1 * d[j + 1] : 0.0);
+  for (int w = 0; w < RQ; ++w)
+#pragma unroll
+    for (int b = 0; b < RB; ++b) acc[w][b] = 0.0;
+  for (int64_t j0 = c0 + 2 * lane; j0 < c1; j0 += 128 * U) {
+    double qv[RQ][2 * U], dv[RB][2 * U];
+#pragma unroll
+    for (int u = 0; u < 2 * U; ++u) {
+      const int64_t j = min(j0 + 128 * (u >> 1) + (u & 1), cols - 1);
+#pragma unroll
+      for (int w = 0; w < RQ; ++w) qv[w][u] = __builtin_nontemporal_load(Qr[w] + j);
+#pragma unroll
+      for (int b = 0; b < RB; ++b) dv[b][u] = D[(r0 + min(b, nb - 1)) * cols + j];
+    }
+#pragma unroll
+    for (int u = 0; u < 2 * U; ++u) {
+      const bool in = j0 + 128 * (u >> 1) + (u & 1) < c1;
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        const double du = in ? dv[b][u] : 0.0;
+#pragma unroll
+        for (int w = 0; w < RQ; ++w) acc[w][b] += qv[w][u] * du;
+      }
     }
   }
 #pragma unroll
-  for (int b = 0; b < RB; ++b) {
-    if (b >= nb) break;
-    const double s = wave_sum(acc[b]);
-    if (lane == 0) q[(r0 + b) * rows + i] = s;
+  for (int w = 0; w < RQ; ++w)
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const double s = wave_sum(acc[w][b]);
+      if (lane == 0) red[wave][w][b] = s;
+    }
+  __syncthreads();
+  if (threadIdx.x < RQ * RB) {
+    const int w = threadIdx.x / RB, b = threadIdx.x % RB;
+    if (b < nb && i0 + w < rows) {
+      double s = 0.0;
+#pragma unroll
+      for (int v = 0; v < W; ++v) s += red[v][w][b];
+      q[(r0 + b) * rows + i0 + w] = s;
+    }
   }
 }
 
@@ -356,10 +388,21 @@ hipError_t launch_cholesky_solve_many(const double* K, double* Y, int64_t n, int
 
 hipError_t launch_qoi_gemv(const double* Q, const double* D, double* q, int64_t rows,
                            int64_t cols, int64_t nrhs, hipStream_t s) {
-  const unsigned g = (unsigned)((rows + 3) / 4);
+  // wavefronts per work-group, 128-entry steps per turn, rows of Q per work-group
+  constexpr int W = 8, U = 1, RQ = 4;
+  const int64_t g = (rows + RQ - 1) / RQ;
+  if (g > 0x7fffffff) return hipErrorInvalidConfiguration;
   for (int64_t r0 = 0; r0 < nrhs; r0 += 4) {
     const int nb = (int)std::min<int64_t>(4, nrhs - r0);
-    hipLaunchKernelGGL(qoi_gemv<4>, dim3(g), dim3(256), 0, s, Q, D, q, rows, cols, r0, nb);
+    if (nb == 1)
+      hipLaunchKernelGGL((qoi_gemv<1, U, W, RQ>), dim3((unsigned)g), dim3(64 * W), 0, s, Q, D, q,
+                         rows, cols, r0, nb);
+    else if (nb == 2)
+      hipLaunchKernelGGL((qoi_gemv<2, U, W, RQ>), dim3((unsigned)g), dim3(64 * W), 0, s, Q, D, q,
+                         rows, cols, r0, nb);
+    else
+      hipLaunchKernelGGL((qoi_gemv<4, U, W, RQ>), dim3((unsigned)g), dim3(64 * W), 0, s, Q, D, q,
+                         rows, cols, r0, nb);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -91,32 +91,54 @@ potrf_trsm(double* __restrict__ K, int64_t n, int64_t j0, int bs, int64_t* __res
     for (int u = 0; u < kNb; ++u) x[u][lane] = K[(r0 + min(u, rows - 1)) * n + j0 + cl];
   }
   __syncthreads();
-  for (int k = 0; k < bs; ++k) {
-    const double d = a[k][k];
-    if (lane == 0 && blockIdx.x == 0 && !(d > 0.0) && *info < 0) *info = j0 + k;
-    const double piv = sqrt(d);
-    __syncthreads();  // every lane has read a[k][k]
-    if (lane == k) a[k][k] = piv;
-    if (lane > k && lane < bs) a[lane][k] /= piv;
-    __syncthreads();  // column k of L complete
-    if (lane > k && lane < bs) {
-      const double lik = a[lane][k];
-      for (int j = k + 1; j <= lane; ++j) a[lane][j] -= lik * a[j][k];
+  {  // factor with lane's row in registers; column k of L goes through LDS
+    __shared__ double colk[kNb + 1];
+    double r[kNb];
+#pragma unroll
+    for (int j = 0; j < kNb; ++j) r[j] = a[lane][j];
+#pragma unroll
+    for (int k = 0; k < kNb; ++k) {
+      if (k < bs) {  // uniform
+        if (lane == k) colk[kNb] = r[k];
+        __syncthreads();
+        const double d = colk[kNb];
+        if (lane == 0 && blockIdx.x == 0 && !(d > 0.0) && *info < 0) *info = j0 + k;
+        const double piv = sqrt(d);
+        r[k] = (lane == k) ? piv : (lane > k ? r[k] / piv : r[k]);
+        colk[lane] = r[k];
+        __syncthreads();
+        const double lik = (lane > k) ? r[k] : 0.0;
+#pragma unroll
+        for (int t = k + 1; t < kNb; ++t) r[t] -= lik * colk[t];
+        __syncthreads();
+      }
     }
-    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kNb; ++j) a[lane][j] = (j <= lane) ? r[j] : 0.0;
   }
+  __syncthreads();
   if (blockIdx.x == 0) {
 #pragma unroll 16
     for (int u = 0; u < kNb; ++u)
       if (u < bs && lane <= u) K[(j0 + u) * n + j0 + lane] = a[u][lane];
   }
   if (rows == 0) return;
-  if (lane < rows) {
-    for (int c = 0; c < bs; ++c) {
-      const double xc = x[lane][c] / a[c][c];
-      x[lane][c] = xc;
-      for (int t = c + 1; t < bs; ++t) x[lane][t] -= xc * a[t][c];
+  {  // lane's row in registers (static indices: the loops are unrolled);
+     // columns at or past bs and rows at or past `rows` carry junk and are
+     // never stored
+    double xr[kNb];
+#pragma unroll
+    for (int j = 0; j < kNb; ++j) xr[j] = x[lane][j];
+#pragma unroll
+    for (int c = 0; c < kNb; ++c) {
+      if (c < bs) {  // uniform
+        xr[c] = xr[c] / a[c][c];
+#pragma unroll
+        for (int t = c + 1; t < kNb; ++t) xr[t] -= xr[c] * a[t][c];
+      }
     }
+#pragma unroll
+    for (int j = 0; j < kNb; ++j) x[lane][j] = xr[j];
   }
   __syncthreads();
 #pragma unroll 16
