@@ -147,101 +147,116 @@ potrf_trsm(double* __restrict__ K, int64_t n, int64_t j0, int bs, int64_t* __res
 }
 
 // ------------------------------------------------------ triangular solves
-// Y is [nrhs][n].  Forward: L y = b block by block.
-// Solve the diagonal block in place, y[j0:j0+bs] = L11^{-1} y[j0:j0+bs]:
-// lane i holds row i; at step c lane c finishes y_c, which is broadcast and
-// removed from the rows below it (column-oriented substitution).
+// Y is [nrhs][n].  One kernel per 64-block and direction: every work-group
+// solves the diagonal block itself (L11 is 32 KB, an L2 hit after the first
+// work-group) and then applies that block's update to its own share of the
+// rest; work-group 0 stores the block's solution.  The block's right-hand
+// side is read from one buffer and its solution written to another, so no
+// work-group can see a block already solved by another:
+//   forward  (L z = y): reads Y[:, blk], writes Z[:, blk], updates Y rows
+//            i >= j1 (y_i -= L[i, blk] z_blk);
+//   backward (L^T x = z): reads Z[:, blk], writes Y[:, blk], updates Z
+//            entries c < j0 (z_c -= L[blk, c]^T x_blk).
+constexpr int kFwdRows = 64;    // forward: rows updated per work-group
+constexpr int kBwdCols = 256;   // backward: entries updated per work-group
+
+__device__ __forceinline__ double wave_total(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// L11 (lower, zero above the diagonal and outside bs) into LDS; 256
+// threads, coalesced rows, all loads issued first at clamped addresses.
+__device__ __forceinline__ void load_diag_block(const double* __restrict__ K, int64_t n,
+                                                int64_t j0, int bs, double (*l)[kNb + 1]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cl = min(lane, bs - 1);
+  double v[kNb / 4];
+#pragma unroll
+  for (int u = 0; u < kNb / 4; ++u) v[u] = K[(j0 + min(4 * u + wave, bs - 1)) * n + j0 + cl];
+#pragma unroll
+  for (int u = 0; u < kNb / 4; ++u) {
+    const int row = 4 * u + wave;
+    l[row][lane] = (row < bs && lane <= row) ? v[u] : 0.0;
+  }
+}
+
 __global__ void __launch_bounds__(256)
-trsv_lower_diag(const double* __restrict__ K, double* __restrict__ Y, int64_t n,
-                int64_t nrhs, int64_t j0, int bs) {
+trsv_fwd_step(const double* __restrict__ K, double* __restrict__ Y, double* __restrict__ Z,
+              int64_t n, int64_t nrhs, int64_t j0, int bs) {
   __shared__ double l[kNb][kNb + 1];
-  for (int e = threadIdx.x; e < kNb * kNb; e += 256) {  // all 4 wavefronts load
-    const int i = e / kNb, j = e % kNb;
-    l[i][j] = (i < bs && j <= i) ? K[(j0 + i) * n + j0 + j] : 0.0;
-  }
-  __syncthreads();
-  if (threadIdx.x >= 64) return;  // one wavefront solves
-  const int lane = threadIdx.x;
-  for (int64_t r = 0; r < nrhs; ++r) {
-    double* y = Y + r * n + j0;
-    double v = (lane < bs) ? y[lane] : 0.0;
-    for (int c = 0; c < bs; ++c) {
-      const double yc = __shfl(v / l[c][c], c, 64);
-      if (lane == c) v = yc;
-      else if (lane > c) v -= l[lane][c] * yc;
-    }
-    if (lane < bs) y[lane] = v;
-  }
-}
-
-// Rows i >= j1: y[i] -= L[i, j0:j1] y[j0:j1]; one wavefront per row, lanes
-// over the block's columns.
-__global__ void __launch_bounds__(256)
-trsv_lower_update(const double* __restrict__ K, double* __restrict__ Y, int64_t n,
-                  int64_t nrhs, int64_t j0, int bs) {
-  const int lane = threadIdx.x & 63;
-  const int64_t i = j0 + bs + (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= n) return;
-  const double l = (lane < bs) ? K[i * n + j0 + lane] : 0.0;
-  for (int64_t r = 0; r < nrhs; ++r) {
-    double v = (lane < bs) ? l * Y[r * n + j0 + lane] : 0.0;
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane == 0) Y[r * n + i] -= v;
-  }
-}
-
-// Backward: L^T x = y.  Partial sums of L[i, j0:j1]^T x[i] over row ranges
-// of 256 rows i >= j1: part[w][r][c].
-__global__ void __launch_bounds__(256)
-trsv_upper_partial(const double* __restrict__ K, const double* __restrict__ Y,
-                   double* __restrict__ part, int64_t n, int64_t nrhs, int64_t j0,
-                   int bs) {
-  __shared__ double red[4][kNb];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __shared__ double zb[kNb];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  load_diag_block(K, n, j0, bs, l);
   const int64_t j1 = j0 + bs;
-  const int64_t rbeg = j1 + (int64_t)blockIdx.x * 256;
-  const int64_t rend = min(rbeg + 256, n);
+  const int64_t rbeg = j1 + (int64_t)blockIdx.x * kFwdRows;
+  // this work-group's rows of the column panel, 16 a wavefront
+  constexpr int kPer = kFwdRows / 4;
+  double lr[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int64_t i = min(rbeg + wave * kPer + u, n - 1);
+    lr[u] = K[i * n + j0 + min(lane, bs - 1)];
+  }
+  __syncthreads();
   for (int64_t r = 0; r < nrhs; ++r) {
-    double acc = 0.0;
-    if (lane < bs)
-      for (int64_t i = rbeg + wv; i < rend; i += 4) acc += K[i * n + j0 + lane] * Y[r * n + i];
-    red[wv][lane] = acc;
+    if (wave == 0) {  // lane c holds unknown c; at step c lane c finishes it
+      double v = Y[r * n + j0 + min(lane, bs - 1)];
+      if (lane >= bs) v = 0.0;
+      for (int c = 0; c < bs; ++c) {
+        const double zc = __shfl(v / l[c][c], c, 64);
+        if (lane == c) v = zc;
+        else if (lane > c) v -= l[lane][c] * zc;
+      }
+      zb[lane] = v;
+      if (blockIdx.x == 0 && lane < bs) Z[r * n + j0 + lane] = v;
+    }
     __syncthreads();
-    if (wv == 0)
-      part[((int64_t)blockIdx.x * nrhs + r) * kNb + lane] =
-          red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
-    __syncthreads();
+    const double zl = (lane < bs) ? zb[lane] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int64_t i = rbeg + wave * kPer + u;
+      const double s = wave_total(lr[u] * zl);
+      if (lane == 0 && i < n) Y[r * n + i] -= s;
+    }
+    __syncthreads();  // zb is rewritten for the next right-hand side
   }
 }
 
-// Backward diagonal block: x = L11^{-T} (y - sum of the partials); lane c
-// holds unknown c; at step t lane t finishes x_t, which is broadcast and
-// removed from the unknowns above it.
 __global__ void __launch_bounds__(256)
-trsv_upper_diag(const double* __restrict__ K, double* __restrict__ Y,
-                const double* __restrict__ part, int nparts, int64_t n, int64_t nrhs,
-                int64_t j0, int bs) {
+trsv_bwd_step(const double* __restrict__ K, double* __restrict__ Y, double* __restrict__ Z,
+              int64_t n, int64_t nrhs, int64_t j0, int bs) {
   __shared__ double l[kNb][kNb + 1];
-  for (int e = threadIdx.x; e < kNb * kNb; e += 256) {  // all 4 wavefronts load
-    const int i = e / kNb, j = e % kNb;
-    l[i][j] = (i < bs && j <= i) ? K[(j0 + i) * n + j0 + j] : 0.0;
-  }
+  __shared__ double xb[kNb];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  load_diag_block(K, n, j0, bs, l);
+  // this work-group's entries c < j0: column c of the block's row panel
+  const int64_t c = (int64_t)blockIdx.x * kBwdCols + threadIdx.x;
+  const bool own = c < j0;
+  const int64_t cc = own ? c : 0;
+  double lc[kNb];
+#pragma unroll
+  for (int t = 0; t < kNb; ++t) lc[t] = K[(j0 + min(t, bs - 1)) * n + cc];
   __syncthreads();
-  if (threadIdx.x >= 64) return;  // one wavefront solves
-  const int lane = threadIdx.x;
   for (int64_t r = 0; r < nrhs; ++r) {
-    double* y = Y + r * n + j0;
-    double v = 0.0;
-    if (lane < bs) {
-      v = y[lane];
-      for (int w = 0; w < nparts; ++w) v -= part[((int64_t)w * nrhs + r) * kNb + lane];
+    if (wave == 0) {  // lane t holds unknown t; from the last one down
+      double v = Z[r * n + j0 + min(lane, bs - 1)];
+      if (lane >= bs) v = 0.0;
+      for (int t = bs - 1; t >= 0; --t) {
+        const double xt = __shfl(v / l[t][t], t, 64);
+        if (lane == t) v = xt;
+        else if (lane < t) v -= l[t][lane] * xt;
+      }
+      xb[lane] = v;
+      if (blockIdx.x == 0 && lane < bs) Y[r * n + j0 + lane] = v;
     }
-    for (int t = bs - 1; t >= 0; --t) {
-      const double xt = __shfl(v / l[t][t], t, 64);
-      if (lane == t) v = xt;
-      else if (lane < t) v -= l[t][lane] * xt;
-    }
-    if (lane < bs) y[lane] = v;
+    __syncthreads();
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < kNb; ++t) acc += (t < bs ? lc[t] : 0.0) * xb[t];
+    if (own) Z[r * n + c] -= acc;
+    __syncthreads();  // xb is rewritten for the next right-hand side
   }
 }
 
@@ -364,35 +379,26 @@ hipError_t launch_cholesky(double* K, int64_t n, int64_t* info_dev, hipStream_t 
   return hipSuccess;
 }
 
-// In place: Y <- (L L^T)^{-1} Y; part: scratch of ceil(n/256)*nrhs*64 doubles.
-hipError_t launch_cholesky_solve(const double* K, double* Y, double* part, int64_t n,
+// In place: Y <- (L L^T)^{-1} Y; Z: scratch of nrhs * n doubles (the
+// forward solution).
+hipError_t launch_cholesky_solve(const double* K, double* Y, double* Z, int64_t n,
                                  int64_t nrhs, hipStream_t s) {
   for (int64_t j0 = 0; j0 < n; j0 += kNb) {
     const int bs = (int)std::min<int64_t>(kNb, n - j0);
-    hipLaunchKernelGGL(trsv_lower_diag, dim3(1), dim3(256), 0, s, K, Y, n, nrhs, j0, bs);
     const int64_t m = n - j0 - bs;
-    if (m > 0)
-      hipLaunchKernelGGL(trsv_lower_update, dim3(grid1(m, 4)), dim3(256), 0, s, K, Y, n, nrhs,
-                         j0, bs);
+    const unsigned g = (unsigned)std::max<int64_t>(1, (m + kFwdRows - 1) / kFwdRows);
+    hipLaunchKernelGGL(trsv_fwd_step, dim3(g), dim3(256), 0, s, K, Y, Z, n, nrhs, j0, bs);
   }
-  const int64_t last = ((n - 1) / kNb) * kNb;
-  for (int64_t j0 = last; j0 >= 0; j0 -= kNb) {
+  for (int64_t j0 = ((n - 1) / kNb) * kNb; j0 >= 0; j0 -= kNb) {
     const int bs = (int)std::min<int64_t>(kNb, n - j0);
-    const int64_t m = n - j0 - bs;
-    int nparts = 0;
-    if (m > 0) {
-      nparts = (int)((m + 255) / 256);
-      hipLaunchKernelGGL(trsv_upper_partial, dim3(nparts), dim3(256), 0, s, K, Y, part, n, nrhs,
-                         j0, bs);
-    }
-    hipLaunchKernelGGL(trsv_upper_diag, dim3(1), dim3(256), 0, s, K, Y, part, nparts, n, nrhs,
-                       j0, bs);
+    const unsigned g = (unsigned)std::max<int64_t>(1, (j0 + kBwdCols - 1) / kBwdCols);
+    hipLaunchKernelGGL(trsv_bwd_step, dim3(g), dim3(256), 0, s, K, Y, Z, n, nrhs, j0, bs);
   }
   return hipGetLastError();
 }
 
 size_t cholesky_solve_scratch(int64_t n, int64_t nrhs) {
-  return (size_t)((n + 255) / 256 + 1) * nrhs * kNb * sizeof(double);
+  return (size_t)n * nrhs * sizeof(double);
 }
 
 hipError_t launch_copy_diagonal(const double* K, double* d, int64_t n, hipStream_t s) {
