@@ -540,6 +540,17 @@ def bench_inversion(torch, S, P):
     m = plan.posterior(K, d_obs, 0.25, refine_steps=1)
     torch.cuda.synchronize()
     t_m = time.perf_counter() - t0
+    # Phase 4 online: m from the factor alone (two triangular sweeps + F*)
+    m_on = plan.posterior_mean(K, d_obs, 0.25)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(5):
+        plan.posterior_mean(K, d_obs, 0.25, out=m_on)
+    ev[1].record()
+    torch.cuda.synchronize()
+    t_on = ev[0].elapsed_time(ev[1]) / 5 * 1e-3
+    e_on = (torch.linalg.norm(m_on - m) / torch.linalg.norm(m)).item()
     # MAP optimality residual F* Gn^-1 (F m - d) + m / Gp, relative to m / Gp
     g = plan.FT((plan.F(m) - d_obs) / s2) + m / 0.25
     res = (torch.linalg.norm(g) / torch.linalg.norm(m / 0.25)).item()
@@ -583,6 +594,7 @@ def bench_inversion(torch, S, P):
             "hessian_assemble_s": round(t_k, 3), "unit_vectors_per_s": round(units / t_k, 1),
             "hessian_gram_s": round(t_kg, 4), "hessian_gram_vs_matvec_rel": e_kg,
             "posterior_solve_s": round(t_m, 3), "map_gradient_rel": res,
+            "posterior_online_ms": round(t_on * 1e3, 3), "posterior_online_vs_refined_rel": e_on,
             "qoi_precompute_s": round(t_q, 3), "qoi_precompute_gram_s": round(t_qg, 3),
             "qoi_gram_vs_matvec_rel": e_qg,
             "qoi_predict_ms": round(t_p * 1e3, 4),

@@ -258,6 +258,19 @@ p2o_status p2o_posterior_solve(p2o_handle h, double* K, const double* d,
                                int refine_steps, int64_t* failed_pivot,
                                void* stream);
 
+/* Phase 4 online inference with K already factored (offline, by
+ * p2o_posterior_solve): m = Gamma_prior F* K^{-1} d from the Cholesky factor
+ * alone (two triangular sweeps and one F* apply; no refinement, which
+ * would need K itself).
+ *   Kfac   device [(Nt*Nd)^2]: K after p2o_posterior_solve (the factor in
+ *          its lower triangle; the upper triangle is not read).
+ *   d      device [nrhs][Nt][Nd];  m_out device [nrhs][Nt][Nm].
+ * Requires a P2O_FP64 plan (else P2O_EUNSUPPORTED); P2O_EINVAL on null
+ * pointers or nrhs outside 1 .. 65535.  Allocates its temporaries and
+ * synchronises `stream`. */
+p2o_status p2o_posterior_mean(p2o_handle h, const double* Kfac, const double* d, double* m_out,
+                              int64_t nrhs, double prior_var, void* stream);
+
 /* --------------------------------------------- spatial prior covariance
  * The inversion calls below take Gamma_prior = prior_var * (I_Nt (x) C):
  * the same spatial covariance C on every time step (time-invariant, which

@@ -55,6 +55,7 @@ _SIGNATURES = {
     "p2o_qoi_precompute": (_int, [_vp, _vp, _vp, _dbl, _vp, _vp, _vp]),
     "p2o_set_prior": (_int, [_vp, _c.POINTER(_PriorGrid), _vp]),
     "p2o_set_assembly": (_int, [_vp, _int]),
+    "p2o_posterior_mean": (_int, [_vp, _vp, _vp, _vp, _i64, _dbl, _vp]),
     "p2o_qoi_predict": (_int, [_vp, _i64, _i64, _vp, _vp, _i64, _vp]),
     "p2o_destroy": (None, [_vp]),
     "p2o_status_string": (_c.c_char_p, [_int]),
@@ -280,6 +281,25 @@ class Plan:
             err.failed_pivot = piv.value
             raise err
         _check("p2o_posterior_solve", st)
+        return out
+
+    def posterior_mean(self, Kfac: torch.Tensor, d: torch.Tensor, prior_var: float,
+                       out=None, stream=None) -> torch.Tensor:
+        """Phase 4 online: m = Gamma_prior F* K^{-1} d from the factor left in
+        Kfac's lower triangle by posterior() (K is not modified)."""
+        Kfac = _dev_f64(Kfac, "Kfac")
+        d = _dev_f64(d, "d")
+        nrhs = 1 if d.dim() == 2 else int(d.shape[0])
+        if d.shape[-2:] != (self.Nt, self.Nd):
+            raise ValueError("d must end in (Nt, Nd)")
+        n = self.Nt * self.Nd
+        if tuple(Kfac.shape) != (n, n):
+            raise ValueError(f"Kfac must be ({n}, {n})")
+        if out is None:
+            out = torch.empty(d.shape[:-1] + (self.Nm,), dtype=torch.float64, device=d.device)
+        _check("p2o_posterior_mean", self._lib.p2o_posterior_mean(
+            self._handle(), Kfac.data_ptr(), d.data_ptr(), out.data_ptr(), nrhs,
+            float(prior_var), _stream_handle(stream)))
         return out
 
     def set_prior(self, grid=None, radius: int = 2, length: float = 1.0, delta: float = 0.1,

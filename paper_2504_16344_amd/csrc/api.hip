@@ -997,6 +997,35 @@ p2o_status p2o_posterior_solve(p2o_handle h, double* K, const double* d,
   return P2O_OK;
 }
 
+p2o_status p2o_posterior_mean(p2o_handle h, const double* Kfac, const double* d, double* m_out,
+                              int64_t nrhs, double prior_var, void* stream) {
+  if (!h || !Kfac || !d || !m_out || nrhs < 1 || nrhs > 65535) return P2O_EINVAL;
+  if (!h->ready) return P2O_ESTATE;
+  if (h->prec != P2O_FP64) return P2O_EUNSUPPORTED;
+  (void)hipGetLastError();
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = h->Nt * h->Nd;
+  DevBufs bufs;
+  void *x, *psolve;
+  TRY_HIP(bufs.alloc(&x, (size_t)nrhs * n * 8));
+  TRY_HIP(bufs.alloc(&psolve, cholesky_solve_scratch(n, nrhs)));
+  double* X = static_cast<double*>(x);
+  TRY_HIP(hipMemcpyAsync(X, d, (size_t)nrhs * n * 8, hipMemcpyDeviceToDevice, s));
+  TRY_HIP(cholesky_solve(Kfac, X, static_cast<double*>(psolve), n, nrhs, s));
+  TRY_ST(ensure_ws(h, nrhs));
+  TRY_ST(apply_impl(h, P2O_FADJ, X, m_out, nrhs, s, prior_var));
+  if (h->prior_w) {  // Gamma_prior = prior_var (I (x) C)
+    void *t1, *t2;
+    TRY_HIP(bufs.alloc(&t1, (size_t)nrhs * h->Nt * h->Nm * 8));
+    TRY_HIP(bufs.alloc(&t2, (size_t)nrhs * h->Nt * h->Nm * 8));
+    TRY_HIP(launch_apply_prior(m_out, static_cast<double*>(t1), static_cast<double*>(t2),
+                               nrhs * h->Nt, h->prior_nx, h->prior_ny, h->prior_w, h->prior_r,
+                               h->prior_delta, s));
+  }
+  TRY_HIP(hipStreamSynchronize(s));
+  return P2O_OK;
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------ batched instances

@@ -101,3 +101,49 @@ def test_inversion_needs_fp64_plan():
         with pytest.raises(P.P2OError) as e:
             plan.hessian(0.25, dev(np.ones(8)))
         assert e.value.status == 6
+
+
+@pytest.mark.parametrize("shape,nrhs", [((3, 40, 7), 1), ((5, 300, 29), 3), ((5, 300, 29), 20),
+                                        ((20, 300, 55), 2)])
+def test_posterior_mean_from_factor(shape, nrhs):
+    """Phase 4 online: m = Gp F* K^{-1} d from the factor left by posterior()
+    (single- and many-right-hand-side sweeps), against the oracle; K is not
+    modified by the call."""
+    Nd, Nm, Nt = shape
+    print(f"\n[inverse] online shape={shape} nrhs={nrhs}", flush=True)
+    blocks, _, _ = workload(9, Nd, Nm, Nt, tau=Nt / 3)
+    n = Nt * Nd
+    nv = _noise(9, n)
+    d = S.vector(9, S.ARRAY_D, nrhs * n).reshape(nrhs, Nt, Nd)
+    K_ref = oracle.hessian_gram(blocks, 0.25, nv)
+    m_ref = np.stack([oracle.posterior_mean(blocks, 0.25, nv, d[r], K=K_ref) for r in range(nrhs)])
+    with P.Plan(dev(blocks), "fp64") as plan:
+        K = plan.hessian(0.25, dev(nv))
+        plan.posterior(K, dev(np.zeros((Nt, Nd))), 0.25, refine_steps=0)  # factor K
+        K_before = K.clone()
+        m = host(plan.posterior_mean(K, dev(d), 0.25))
+        assert torch.equal(K, K_before)
+    e = rel_err(m, m_ref)
+    print(f"  m err {e:.2e}", flush=True)
+    assert e <= 1e-10
+
+
+def test_posterior_mean_errors():
+    blocks, _, _ = workload(10, 2, 24, 8, tau=3.0)
+    with P.Plan(dev(blocks), "fp64") as plan:
+        K = torch.eye(16, dtype=torch.float64, device="cuda")
+        with pytest.raises(ValueError):
+            plan.posterior_mean(K, dev(np.ones((7, 2))), 0.25)
+        lib = P.load_library()
+        d = dev(np.ones((8, 2)))
+        m = torch.empty((8, 24), dtype=torch.float64, device="cuda")
+        assert lib.p2o_posterior_mean(plan._handle(), None, d.data_ptr(), m.data_ptr(), 1,
+                                      0.25, None) == 1
+        assert lib.p2o_posterior_mean(plan._handle(), K.data_ptr(), d.data_ptr(),
+                                      m.data_ptr(), 0, 0.25, None) == 1
+    b256, _, _ = workload(10, 2, 256, 8, tau=3.0)
+    with P.Plan(dev(b256), "mixed_bf16") as plan:
+        with pytest.raises(P.P2OError) as e:
+            plan.posterior_mean(torch.eye(16, dtype=torch.float64, device="cuda"),
+                                dev(np.ones((8, 2))), 0.25)
+        assert e.value.status == 6
