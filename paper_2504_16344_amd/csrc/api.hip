@@ -722,91 +722,6 @@ bool same_time_grid(const p2o_plan_s* a, const p2o_plan_s* b) {
   return a->Nt == b->Nt && a->Nm == b->Nm && a->L == b->L;
 }
 
-// Rows of hf's F applied after Gamma_prior times ha's F*: for every unit
-// vector e_j of ha's data space (j = t N_d(ha) + s, all N_t N_d(ha) of them),
-// out[j * ldo + :] = F_hf Gamma_prior F_ha^* e_j, a vector of hf's data
-// space ([N_t][N_d(hf)]), with Gamma_prior = prior_var (I (x) C) and C the
-// spatial prior of plan hp (identity unless set).  With ha = hf this is row j of K minus the noise
-// (Phase 2); with ha the p2q plan and hf the p2o plan it is column j of
-// F Gp Fq^*, with ha = hf = the p2q plan row j of Fq Gp Fq^* (Phase 3).
-// F* of a unit vector is a conjugated, phase-shifted row of ha's frequency
-// blocks (no product needed), generated in the load stage of the inverse
-// transform (truncation to N_t steps, times prior_var); then forward
-// transform, hf's F product over a batch of unit vectors, inverse
-// transform written straight into the rows.
-p2o_status assemble_rows(p2o_plan_s* ha, p2o_plan_s* hf, const p2o_plan_s* hp,
-                         double prior_var, double* out, int64_t ldo, hipStream_t s) {
-  const int64_t n = ha->Nt * ha->Nd;
-  const int64_t Nm = hf->Nm;
-  const bool prior = hp->prior_w != nullptr;
-  // per unit vector: adjoint spectrum (reused for the refiltered parameter
-  // spectrum), time-domain parameter vector (and two prior scratch copies),
-  // partial data spectra
-  const size_t per = (size_t)hf->nf * Nm * 16 + (size_t)hf->Nt * Nm * 8 * (prior ? 3 : 1) +
-                     (size_t)hf->n_pc * hf->nf * hf->Nd * 16;
-  const size_t budget = (size_t)8 << 30;
-  const int64_t B = std::max<int64_t>(1, std::min<int64_t>({n, 65535, (int64_t)(budget / per)}));
-  DevBufs bufs;
-  void *xh, *m, *parts, *t1 = nullptr, *t2 = nullptr;
-  TRY_HIP(bufs.alloc(&xh, (size_t)B * hf->nf * Nm * 16));
-  TRY_HIP(bufs.alloc(&m, (size_t)B * hf->Nt * Nm * 8));
-  TRY_HIP(bufs.alloc(&parts, (size_t)B * hf->n_pc * hf->nf * hf->Nd * 16));
-  if (prior) {
-    TRY_HIP(bufs.alloc(&t1, (size_t)B * hf->Nt * Nm * 8));
-    TRY_HIP(bufs.alloc(&t2, (size_t)B * hf->Nt * Nm * 8));
-  }
-  for (int64_t j0 = 0; j0 < n; j0 += B) {
-    const int64_t nb = std::min(B, n - j0);
-    // F_ha^* of the unit vectors, generated inside the inverse transform's
-    // load (no spectrum buffer), then truncation to Nt steps, times prior_var
-    FftIo inv{};
-    inv.in = nullptr;
-    inv.unit_fhat = ha->fhat;
-    inv.unit_nd = ha->Nd;
-    inv.unit_j0 = j0;
-    inv.out = m;
-    inv.ncols = Nm;
-    inv.in_row = Nm;
-    inv.in_batch = hf->nf * Nm;
-    inv.out_row = Nm;
-    inv.out_batch = hf->Nt * Nm;
-    inv.nparts = 1;
-    inv.scale = prior_var / (double)hf->L;
-    TRY_HIP(launch_rfft_inv_f64(hf->fft, hf->tw64, hf->perm, inv, nb, s));
-    if (prior)  // Gamma_prior = prior_var (I (x) C): C on every time slice
-      TRY_HIP(launch_apply_prior(static_cast<double*>(m), static_cast<double*>(t1),
-                                 static_cast<double*>(t2), nb * hf->Nt, hp->prior_nx,
-                                 hp->prior_ny, hp->prior_w, hp->prior_r, hp->prior_delta, s));
-    FftIo fwd{};
-    fwd.in = m;
-    fwd.out = xh;
-    fwd.ncols = Nm;
-    fwd.in_row = Nm;
-    fwd.in_batch = hf->Nt * Nm;
-    fwd.out_row = Nm;
-    fwd.out_batch = hf->nf * Nm;
-    fwd.nparts = 1;
-    fwd.scale = 1.0;
-    TRY_HIP(launch_rfft_fwd_f64(hf->fft, hf->tw64, hf->perm, fwd, nb, s));
-    TRY_HIP(launch_product(hf, P2O_F, xh, parts, nullptr, nb, hf->cfg[P2O_F], s));
-    FftIo o{};
-    o.in = parts;
-    o.out = out + j0 * ldo;
-    o.ncols = hf->Nd;
-    o.in_row = hf->Nd;
-    o.nparts = (int)hf->n_pc;
-    o.part_stride = hf->nf * hf->Nd;
-    o.in_batch = hf->n_pc * hf->nf * hf->Nd;
-    o.out_row = hf->Nd;
-    o.out_batch = ldo;
-    o.scale = 1.0 / (double)hf->L;
-    TRY_HIP(launch_rfft_inv_f64(hf->fft, hf->tw64, hf->perm, o, nb, s));
-  }
-  // the scratch buffers are freed on return: finish their users first
-  TRY_HIP(hipStreamSynchronize(s));
-  return P2O_OK;
-}
-
 // The time-domain blocks F_0 .. F_{Nt-1} of an FP64 plan, recovered from
 // its frequency blocks by one inverse transform over all Nd Nm series
 // (exact up to rounding: the spectra are those of the zero-padded series):
@@ -822,6 +737,67 @@ hipError_t time_blocks(const p2o_plan_s* h, double* out, hipStream_t s) {
   io.nparts = 1;
   io.scale = 1.0 / (double)h->L;
   return launch_rfft_inv_f64(h->fft, h->tw64, h->perm, io, 1, s);
+}
+
+// Rows of hf's F applied after Gamma_prior times ha's F*: for every unit
+// vector e_j of ha's data space (j = i Nd_a + s: sensor s, step i),
+// row j of `out` (leading dimension ldo) receives F_hf Gamma_prior F_ha^* e_j
+// ([Nt][Nd_f]).  The paper's Phase 2 matvecs on unit vectors: the
+// spectrum of Gamma_prior F_ha^* e_j (truncated to Nt steps, zero padded)
+// is generated directly, for all Nt steps of a sensor at once by a running
+// sum over the steps (launch_unit_spectra, from ha's time-domain blocks with
+// the prior's spatial factor applied), then hf's F product and inverse
+// transform, whose output rows are scattered to j = i Nd_a + s.
+p2o_status assemble_rows(p2o_plan_s* ha, p2o_plan_s* hf, const p2o_plan_s* hp,
+                         double prior_var, double* out, int64_t ldo, hipStream_t s) {
+  const int64_t Nt = hf->Nt, Nm = hf->Nm, nda = ha->Nd;
+  const bool prior = hp->prior_w != nullptr;
+  DevBufs bufs;
+  void* a;  // ha's time-domain rows (i Nd_a + s), times C
+  TRY_HIP(bufs.alloc(&a, (size_t)Nt * nda * Nm * 8));
+  TRY_HIP(time_blocks(ha, static_cast<double*>(a), s));
+  if (prior) {
+    void *t1, *t2;
+    TRY_HIP(bufs.alloc(&t1, (size_t)Nt * nda * Nm * 8));
+    TRY_HIP(bufs.alloc(&t2, (size_t)Nt * nda * Nm * 8));
+    TRY_HIP(launch_apply_prior(static_cast<double*>(a), static_cast<double*>(t1),
+                               static_cast<double*>(t2), Nt * nda, hp->prior_nx, hp->prior_ny,
+                               hp->prior_w, hp->prior_r, hp->prior_delta, s));
+  }
+  // whole sensors per pass: every unit vector's parameter spectrum and
+  // partial data spectra
+  const size_t per = (size_t)hf->nf * Nm * 16 + (size_t)hf->n_pc * hf->nf * hf->Nd * 16;
+  const size_t budget = (size_t)8 << 30;
+  const int64_t ns = std::max<int64_t>(
+      1, std::min<int64_t>({nda, 65535 / Nt, (int64_t)(budget / (per * Nt))}));
+  void *xh, *parts;
+  TRY_HIP(bufs.alloc(&xh, (size_t)ns * Nt * hf->nf * Nm * 16));
+  TRY_HIP(bufs.alloc(&parts, (size_t)ns * Nt * hf->n_pc * hf->nf * hf->Nd * 16));
+  const int64_t in_batch = hf->n_pc * hf->nf * hf->Nd;  // complex entries a unit vector
+  for (int64_t s0 = 0; s0 < nda; s0 += ns) {
+    const int nsb = (int)std::min(ns, nda - s0);
+    TRY_HIP(launch_unit_spectra(static_cast<const double*>(a), nda, Nm, Nt, hf->nf, hf->L,
+                                hf->tw64, s0, nsb, prior_var, static_cast<cpx<double>*>(xh),
+                                s));
+    TRY_HIP(launch_product(hf, P2O_F, xh, parts, nullptr, (int64_t)nsb * Nt, hf->cfg[P2O_F], s));
+    for (int j = 0; j < nsb; ++j) {  // sensor s0 + j: steps i to rows i Nd_a + s0 + j
+      FftIo o{};
+      o.in = static_cast<const cpx<double>*>(parts) + (int64_t)j * Nt * in_batch;
+      o.out = out + (s0 + j) * ldo;
+      o.ncols = hf->Nd;
+      o.in_row = hf->Nd;
+      o.nparts = (int)hf->n_pc;
+      o.part_stride = hf->nf * hf->Nd;
+      o.in_batch = in_batch;
+      o.out_row = hf->Nd;
+      o.out_batch = nda * ldo;
+      o.scale = 1.0 / (double)hf->L;
+      TRY_HIP(launch_rfft_inv_f64(hf->fft, hf->tw64, hf->perm, o, Nt, s));
+    }
+  }
+  // the scratch buffers are freed on return: finish their users first
+  TRY_HIP(hipStreamSynchronize(s));
+  return P2O_OK;
 }
 
 // The same rows as assemble_rows, from the Gram form of the product.  With
