@@ -345,20 +345,6 @@ __device__ __forceinline__ void add_partials(const cpx<TIN>* __restrict__ in, co
   }
 }
 
-// Bin k of F* e_j in frequency space, j = unit_j0 + b = i unit_nd + s: F*'s
-// circulant embedding maps the unit vector to conj(Fhat_k[s, :]) shifted by
-// i steps, i.e. times W_L^(i k) (W_L = exp(-2 pi i / L), the table tw).
-template <typename T>
-__device__ __forceinline__ cpx<T> unit_adjoint_bin(const FftIo& io, const cpx<T>* __restrict__ tw,
-                                                   int L, int64_t b, int64_t col, int k) {
-  const int64_t j = io.unit_j0 + b;
-  const int64_t i = j / io.unit_nd, s = j % io.unit_nd;
-  const cpx<double> a =
-      static_cast<const cpx<double>*>(io.unit_fhat)[((int64_t)k * io.unit_nd + s) * io.ncols + col];
-  const cpx<T> w = tw[(i * k) % L];
-  return {(T)(a.x * w.x + a.y * w.y), (T)(a.x * w.y - a.y * w.x)};
-}
-
 // Z[k] = (Xa + conj Xb) + i conj(W_L^k) (Xa - conj Xb) with Xa = X[k],
 // Xb = X[N-k]; the 1/2 of the split and the 1/N of the inverse DFT are
 // folded into io.scale (= 1/L).
@@ -393,7 +379,6 @@ rfft_inv_kernel(FftDesc d, const cpx<T>* __restrict__ tw_g,
   const cpx<T>* tw = buf + (N << logC);
   const int* perm = reinterpret_cast<const int*>(tw + d.L);
   __syncthreads();  // the load stage below reads the twiddles
-  const bool unit = std::is_same<T, double>::value && io.unit_fhat != nullptr;
 
   // groups of G bin pairs a thread, loads first (see the forward); half the
   // group when any side is float64 keeps the kernel within 128 VGPRs (two
@@ -404,16 +389,7 @@ rfft_inv_kernel(FftDesc d, const cpx<T>* __restrict__ tw_g,
   const int total = (half + 1) << logC;
   for (int base = tid; base < total; base += G * nthr) {
     cpx<T> xa[G], xb[G];
-    if (unit) {
-#pragma unroll
-      for (int g = 0; g < G; ++g) {  // unconditional: clamped addresses
-        const int idx = base + g * nthr;
-        const bool ok = idx < total && (idx & (C - 1)) < ncol;
-        const int k = ok ? idx >> logC : 0, c = ok ? idx & (C - 1) : 0;
-        xa[g] = unit_adjoint_bin<T>(io, tw, d.L, b, c0 + c, k);
-        xb[g] = unit_adjoint_bin<T>(io, tw, d.L, b, c0 + c, N - k);
-      }
-    } else {
+    {
       cpx<TIN> sa[G], sb[G];
 #pragma unroll
       for (int g = 0; g < G; ++g) {  // first partial spectrum

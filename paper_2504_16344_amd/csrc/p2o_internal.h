@@ -63,13 +63,6 @@ struct FftIo {
   int64_t n8;            // plane pitch (ncols rounded up to 8)
   int64_t nbins;         // frequency bins per batch (nf)
   const float* col_scales;  // [nbins][ceil(ncols / kScaleTile)] or nullptr
-  // Inverse float64 only: when `unit_fhat` is set, batch b reads instead of
-  // `in` the spectrum of F* applied to the unit vector j = unit_j0 + b of
-  // a data space of unit_nd sensors (j = i unit_nd + s): bin k, column c is
-  // conj(unit_fhat[k][s][c]) W_L^(i k) (unit_fhat: [nbins][unit_nd][ncols]).
-  const void* unit_fhat;
-  int64_t unit_nd;
-  int64_t unit_j0;
 };
 
 int64_t smooth_length(int64_t Nt);  // L: smallest even 7-smooth >= 2*Nt
