@@ -6,13 +6,13 @@
 //   K = L L^T (blocked Cholesky), x = K^{-1} d with iterative refinement,
 //   m = Gamma_prior F* x.
 //
-// F* of the unit vector e_(i,s) needs no block product: the transform of
-// that data vector is dhat_k[s'] = [s' = s] W_L^(i k), W_L = exp(-2 pi i / L),
-// so the product Fhat_k^H dhat_k is the conjugated row s of Fhat_k times a
-// phase:  xhat_k[p] = conj(Fhat_k[s, p]) * W_L^(i k).
-// That spectrum still has to go through the inverse transform and the
-// truncation to Nt steps (the time-domain F* output) before F is applied,
-// exactly as in a full F* apply.
+// F* of the unit vector e_(i,s) (sensor s, step i) is row s of F_(i-t) at
+// step t <= i and zero after it, so the spectrum of its truncated,
+// zero-padded series is W_L^(ik) sum_(u <= i) F_u[s, :] W_L^(-uk): a running
+// sum over the shifts i, which gives the spectra of all Nt unit vectors of
+// a sensor in one pass over the time-domain blocks (no transform per unit
+// vector).  Those spectra then go through the F product and its inverse
+// transform exactly as in an F apply.
 #include <cmath>
 
 #include "p2o_internal.h"
