@@ -9,21 +9,24 @@ namespace p2o {
 namespace {
 
 constexpr int kGemmTile = 64;  // C tile per workgroup (rows and columns)
-constexpr int kGemmK = 16;     // contraction chunk staged in LDS
+constexpr int kGemmK = 32;     // contraction chunk staged in LDS
 constexpr int kTriNb = 64;     // triangular-solve block (the Cholesky block size)
 constexpr int64_t kSolvePanel = 256;  // columns per rank-k update of the solves
 
 // C[i][j] += alpha sum_k A[i][k] op(B)[k][j] for i < M, j < N, row-major,
 // op(B)[k][j] = B[j][k] (TRANSB) or B[k][j].  A workgroup owns a 64 x 64
 // tile of C, each of its 4 wavefronts a 32 x 32 quarter (2 x 2
-// v_mfma_f64_16x16x4 tiles); 16-entry chunks of the contraction are staged
+// v_mfma_f64_16x16x4 tiles); 32-entry chunks of the contraction are staged
 // in LDS as [k][row] for both operands.
 // Triangle modes: kTriGrid (a symmetric rank-k update of a lower triangle,
 // M == N) enumerates only the tiles I >= J and leaves the entries above the
 // diagonal untouched; kTriMask keeps the rectangular grid and only masks
 // the entries above the diagonal (a panel whose top square straddles it).
 // Without ACC, C is overwritten (C = alpha A op(B)) and never read.
-enum { kFull = 0, kTriGrid = 1, kTriMask = 2 };
+// kFullCols is kFull with the grid's x index running over row tiles, so
+// that consecutive work-groups share a column tile of op(B) (for an A small
+// enough to stay in the last-level cache while B streams once).
+enum { kFull = 0, kTriGrid = 1, kTriMask = 2, kFullCols = 3 };
 template <bool TRANSB, int TRI, bool ACC = true>
 __global__ void __launch_bounds__(256)
 dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A,
@@ -34,6 +37,10 @@ dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __rest
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, kq = lane >> 4;
   int64_t ti_ = blockIdx.y, tj_ = blockIdx.x;
+  if constexpr (TRI == kFullCols) {
+    ti_ = blockIdx.x;
+    tj_ = blockIdx.y;
+  }
   if constexpr (TRI == kTriGrid) {  // linear index t -> (I, J), J <= I
     const int64_t t = blockIdx.x;
     int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) / 2.0);
@@ -49,34 +56,48 @@ dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __rest
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = (d4v){0, 0, 0, 0};
-  for (int64_t k0 = 0; k0 < K; k0 += kGemmK) {
-    {  // A: 64 rows x 16 contraction entries, 4 consecutive entries a thread
-      const int r = tid >> 2, kk = (tid & 3) * 4;
-      const int64_t gi = i0 + r;
+  // Each thread stages kPer entries of A and of op(B) per chunk: the next
+  // chunk's loads are issued into registers before the current chunk's
+  // matrix-core work, at clamped addresses (out-of-range entries are zeroed
+  // when stored to LDS).
+  constexpr int kPer = kGemmK * kGemmTile / 256;
+  const int ra = tid / (kGemmK / kPer), ka = (tid % (kGemmK / kPer)) * kPer;  // A, B^T
+  const int kb = tid / (kGemmTile / kPer), cb = (tid % (kGemmTile / kPer)) * kPer;  // B
+  double va[kPer], vb[kPer];
+  auto load = [&](int64_t k0) {
+    const int64_t gi = min(i0 + ra, M - 1);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t gk = k0 + kk + e;
-        sa[kk + e][r] = (gi < M && gk < K) ? A[gi * lda + gk] : 0.0;
-      }
-    }
+    for (int e = 0; e < kPer; ++e) va[e] = A[gi * lda + min(k0 + ka + e, K - 1)];
     if constexpr (TRANSB) {
-      const int r = tid >> 2, kk = (tid & 3) * 4;
-      const int64_t gj = j0 + r;
+      const int64_t gj = min(j0 + ra, N - 1);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t gk = k0 + kk + e;
-        sb[kk + e][r] = (gj < N && gk < K) ? B[gj * ldb + gk] : 0.0;
-      }
+      for (int e = 0; e < kPer; ++e) vb[e] = B[gj * ldb + min(k0 + ka + e, K - 1)];
     } else {
-      const int kk = tid >> 4, c = (tid & 15) * 4;
-      const int64_t gk = k0 + kk;
+      const int64_t gk = min(k0 + kb, K - 1);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t gj = j0 + c + e;
-        sb[kk][c + e] = (gk < K && gj < N) ? B[gk * ldb + gj] : 0.0;
-      }
+      for (int e = 0; e < kPer; ++e) vb[e] = B[gk * ldb + min(j0 + cb + e, N - 1)];
     }
+  };
+  auto store = [&](int64_t k0) {
+    const bool ia = i0 + ra < M;
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) sa[ka + e][ra] = (ia && k0 + ka + e < K) ? va[e] : 0.0;
+    if constexpr (TRANSB) {
+      const bool jb = j0 + ra < N;
+#pragma unroll
+      for (int e = 0; e < kPer; ++e) sb[ka + e][ra] = (jb && k0 + ka + e < K) ? vb[e] : 0.0;
+    } else {
+      const bool kin = k0 + kb < K;
+#pragma unroll
+      for (int e = 0; e < kPer; ++e) sb[kb][cb + e] = (kin && j0 + cb + e < N) ? vb[e] : 0.0;
+    }
+  };
+  load(0);
+  for (int64_t k0 = 0; k0 < K; k0 += kGemmK) {
+    __syncthreads();  // the previous chunk's reads of sa, sb are done
+    store(k0);
     __syncthreads();
+    if (k0 + kGemmK < K) load(k0 + kGemmK);
 #pragma unroll
     for (int ks = 0; ks < kGemmK; ks += 4) {
 #pragma unroll
@@ -87,7 +108,6 @@ dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __rest
           acc[ti][tj] = mfma64(a, sb[ks + kq][wc + 16 * tj + col], acc[ti][tj]);
       }
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int ti = 0; ti < 2; ++ti)
@@ -97,7 +117,7 @@ dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __rest
       for (int r = 0; r < 4; ++r) {
         const int64_t gi = i0 + wr + 16 * ti + kq + 4 * r;  // accumulator rows interleave
         const int64_t gj = j0 + wc + 16 * tj + col;
-        if (gi < M && gj < N && (TRI == kFull || gj <= gi)) {
+        if (gi < M && gj < N && (TRI == kFull || TRI == kFullCols || gj <= gi)) {
           if constexpr (ACC)
             C[gi * ldc + gj] += alpha * acc[ti][tj][r];
           else
@@ -302,10 +322,10 @@ hipError_t launch_dgemm_nt_set(bool lower, int64_t M, int64_t N, int64_t K, doub
     if (tiles > 0x7fffffff) return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL((dgemm_kernel<true, kTriGrid, false>), dim3((unsigned)tiles), dim3(256), 0, s,
                        M, N, K, alpha, A, lda, B, ldb, C, ldc);
-  } else {
-    const int64_t gx = (N + kGemmTile - 1) / kGemmTile, gy = (M + kGemmTile - 1) / kGemmTile;
+  } else {  // row tiles along x: A stays cached while B streams once
+    const int64_t gx = (M + kGemmTile - 1) / kGemmTile, gy = (N + kGemmTile - 1) / kGemmTile;
     if (gx > 0x7fffffff || gy > 65535) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((dgemm_kernel<true, kFull, false>), dim3((unsigned)gx, (unsigned)gy),
+    hipLaunchKernelGGL((dgemm_kernel<true, kFullCols, false>), dim3((unsigned)gx, (unsigned)gy),
                        dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, C, ldc);
   }
   return hipGetLastError();
