@@ -8,14 +8,13 @@
 namespace p2o {
 namespace {
 
-constexpr int kGemmTile = 64;  // C tile per workgroup (rows and columns)
 constexpr int kGemmK = 32;     // contraction chunk staged in LDS
 constexpr int kTriNb = 64;     // triangular-solve block (the Cholesky block size)
 constexpr int64_t kSolvePanel = 256;  // columns per rank-k update of the solves
 
 // C[i][j] += alpha sum_k A[i][k] op(B)[k][j] for i < M, j < N, row-major,
-// op(B)[k][j] = B[j][k] (TRANSB) or B[k][j].  A workgroup owns a 64 x 64
-// tile of C, each of its 4 wavefronts a 32 x 32 quarter (2 x 2
+// op(B)[k][j] = B[j][k] (TRANSB) or B[k][j].  A workgroup owns a TM x TM
+// tile of C, each of its 4 wavefronts a quarter (TM/32 x TM/32
 // v_mfma_f64_16x16x4 tiles); 32-entry chunks of the contraction are staged
 // in LDS as [k][row] for both operands.
 // Triangle modes: kTriGrid (a symmetric rank-k update of a lower triangle,
@@ -27,13 +26,14 @@ constexpr int64_t kSolvePanel = 256;  // columns per rank-k update of the solves
 // that consecutive work-groups share a column tile of op(B) (for an A small
 // enough to stay in the last-level cache while B streams once).
 enum { kFull = 0, kTriGrid = 1, kTriMask = 2, kFullCols = 3 };
-template <bool TRANSB, int TRI, bool ACC = true>
+template <bool TRANSB, int TRI, bool ACC, int TM>
 __global__ void __launch_bounds__(256)
 dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A,
              int64_t lda, const double* __restrict__ B, int64_t ldb, double* __restrict__ C,
              int64_t ldc) {
-  __shared__ double sa[kGemmK][kGemmTile + 1];
-  __shared__ double sb[kGemmK][kGemmTile + 1];
+  constexpr int MT = TM / 32;  // MFMA tiles per wavefront and dimension
+  __shared__ double sa[kGemmK][TM + 1];
+  __shared__ double sb[kGemmK][TM + 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, kq = lane >> 4;
   int64_t ti_ = blockIdx.y, tj_ = blockIdx.x;
@@ -49,20 +49,20 @@ dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __rest
     ti_ = I;
     tj_ = t - I * (I + 1) / 2;
   }
-  const int64_t i0 = ti_ * kGemmTile, j0 = tj_ * kGemmTile;
-  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-  d4v acc[2][2];
+  const int64_t i0 = ti_ * TM, j0 = tj_ * TM;
+  const int wr = (wave >> 1) * (TM / 2), wc = (wave & 1) * (TM / 2);
+  d4v acc[MT][MT];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < MT; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = (d4v){0, 0, 0, 0};
+    for (int b = 0; b < MT; ++b) acc[a][b] = (d4v){0, 0, 0, 0};
   // Each thread stages kPer entries of A and of op(B) per chunk: the next
   // chunk's loads are issued into registers before the current chunk's
   // matrix-core work, at clamped addresses (out-of-range entries are zeroed
   // when stored to LDS).
-  constexpr int kPer = kGemmK * kGemmTile / 256;
+  constexpr int kPer = kGemmK * TM / 256;
   const int ra = tid / (kGemmK / kPer), ka = (tid % (kGemmK / kPer)) * kPer;  // A, B^T
-  const int kb = tid / (kGemmTile / kPer), cb = (tid % (kGemmTile / kPer)) * kPer;  // B
+  const int kb = tid / (TM / kPer), cb = (tid % (TM / kPer)) * kPer;  // B
   double va[kPer], vb[kPer];
   auto load = [&](int64_t k0) {
     const int64_t gi = min(i0 + ra, M - 1);
@@ -100,19 +100,21 @@ dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __rest
     if (k0 + kGemmK < K) load(k0 + kGemmK);
 #pragma unroll
     for (int ks = 0; ks < kGemmK; ks += 4) {
+      double bf[MT];
 #pragma unroll
-      for (int ti = 0; ti < 2; ++ti) {
+      for (int tj = 0; tj < MT; ++tj) bf[tj] = sb[ks + kq][wc + 16 * tj + col];
+#pragma unroll
+      for (int ti = 0; ti < MT; ++ti) {
         const double a = sa[ks + kq][wr + 16 * ti + col];
 #pragma unroll
-        for (int tj = 0; tj < 2; ++tj)
-          acc[ti][tj] = mfma64(a, sb[ks + kq][wc + 16 * tj + col], acc[ti][tj]);
+        for (int tj = 0; tj < MT; ++tj) acc[ti][tj] = mfma64(a, bf[tj], acc[ti][tj]);
       }
     }
   }
 #pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
+  for (int ti = 0; ti < MT; ++ti)
 #pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
+    for (int tj = 0; tj < MT; ++tj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t gi = i0 + wr + 16 * ti + kq + 4 * r;  // accumulator rows interleave
@@ -295,51 +297,52 @@ unsigned grid_rhs(int64_t nrhs) {
 
 }  // namespace
 
+// One GEMM launch on 64 x 64 tiles (128 x 128 tiles need ~224 VGPRs, one
+// wavefront per SIMD, and measured slower).
+template <bool TRANSB, int TRI, bool ACC>
+hipError_t launch_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                       int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
+                       hipStream_t s) {
+  if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+  constexpr int64_t tm = 64;
+  const int64_t tr = (M + tm - 1) / tm, tc = (N + tm - 1) / tm;
+  dim3 grid;
+  if (TRI == kTriGrid) {
+    if (tr * (tr + 1) / 2 > 0x7fffffff) return hipErrorInvalidConfiguration;
+    grid = dim3((unsigned)(tr * (tr + 1) / 2));
+  } else if (TRI == kFullCols) {
+    if (tc > 65535) return hipErrorInvalidConfiguration;
+    grid = dim3((unsigned)tr, (unsigned)tc);
+  } else {
+    if (tr > 65535) return hipErrorInvalidConfiguration;
+    grid = dim3((unsigned)tc, (unsigned)tr);
+  }
+  hipLaunchKernelGGL((dgemm_kernel<TRANSB, TRI, ACC, tm>), grid, dim3(256), 0, s, M, N, K, alpha,
+                     A, lda, B, ldb, C, ldc);
+  return hipGetLastError();
+}
+
 hipError_t launch_dgemm(bool transb, int64_t M, int64_t N, int64_t K, double alpha,
                         const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
                         int64_t ldc, hipStream_t s) {
-  if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
-  const int64_t gx = (N + kGemmTile - 1) / kGemmTile, gy = (M + kGemmTile - 1) / kGemmTile;
-  if (gx > 0x7fffffff || gy > 65535) return hipErrorInvalidConfiguration;
-  const dim3 grid((unsigned)gx, (unsigned)gy);
-  if (transb)
-    hipLaunchKernelGGL((dgemm_kernel<true, kFull>), grid, dim3(256), 0, s, M, N, K, alpha, A, lda,
-                       B, ldb, C, ldc);
-  else
-    hipLaunchKernelGGL((dgemm_kernel<false, kFull>), grid, dim3(256), 0, s, M, N, K, alpha, A,
-                       lda, B, ldb, C, ldc);
-  return hipGetLastError();
+  if (transb) return launch_gemm<true, kFull, true>(M, N, K, alpha, A, lda, B, ldb, C, ldc, s);
+  return launch_gemm<false, kFull, true>(M, N, K, alpha, A, lda, B, ldb, C, ldc, s);
 }
 
 hipError_t launch_dgemm_nt_set(bool lower, int64_t M, int64_t N, int64_t K, double alpha,
                                const double* A, int64_t lda, const double* B, int64_t ldb,
                                double* C, int64_t ldc, hipStream_t s) {
-  if (M <= 0 || N <= 0 || (lower && M != N)) return hipErrorInvalidValue;
-  if (K <= 0) return hipErrorInvalidValue;
-  if (lower) {
-    const int64_t T = (N + kGemmTile - 1) / kGemmTile;
-    const int64_t tiles = T * (T + 1) / 2;
-    if (tiles > 0x7fffffff) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((dgemm_kernel<true, kTriGrid, false>), dim3((unsigned)tiles), dim3(256), 0, s,
-                       M, N, K, alpha, A, lda, B, ldb, C, ldc);
-  } else {  // row tiles along x: A stays cached while B streams once
-    const int64_t gx = (M + kGemmTile - 1) / kGemmTile, gy = (N + kGemmTile - 1) / kGemmTile;
-    if (gx > 0x7fffffff || gy > 65535) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((dgemm_kernel<true, kFullCols, false>), dim3((unsigned)gx, (unsigned)gy),
-                       dim3(256), 0, s, M, N, K, alpha, A, lda, B, ldb, C, ldc);
-  }
-  return hipGetLastError();
+  if (M <= 0 || N <= 0 || K <= 0 || (lower && M != N)) return hipErrorInvalidValue;
+  if (lower)
+    return launch_gemm<true, kTriGrid, false>(M, N, K, alpha, A, lda, B, ldb, C, ldc, s);
+  // row tiles along x: A stays cached while B streams once
+  return launch_gemm<true, kFullCols, false>(M, N, K, alpha, A, lda, B, ldb, C, ldc, s);
 }
 
 hipError_t launch_dgemm_nt_lower_mask(int64_t M, int64_t N, int64_t K, double alpha,
                                       const double* A, int64_t lda, const double* B,
                                       int64_t ldb, double* C, int64_t ldc, hipStream_t s) {
-  if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
-  const int64_t gx = (N + kGemmTile - 1) / kGemmTile, gy = (M + kGemmTile - 1) / kGemmTile;
-  if (gx > 0x7fffffff || gy > 65535) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((dgemm_kernel<true, kTriMask>), dim3((unsigned)gx, (unsigned)gy), dim3(256),
-                     0, s, M, N, K, alpha, A, lda, B, ldb, C, ldc);
-  return hipGetLastError();
+  return launch_gemm<true, kTriMask, true>(M, N, K, alpha, A, lda, B, ldb, C, ldc, s);
 }
 
 hipError_t launch_block_diag_scan(double* X, int64_t ld, int64_t T, int64_t P, int64_t Q,
@@ -353,13 +356,7 @@ hipError_t launch_block_diag_scan(double* X, int64_t ld, int64_t T, int64_t P, i
 
 hipError_t launch_dsyrk_lower(int64_t n, int64_t K, double alpha, const double* A, int64_t lda,
                               double* C, int64_t ldc, hipStream_t s) {
-  if (n <= 0 || K <= 0) return hipSuccess;
-  const int64_t T = (n + kGemmTile - 1) / kGemmTile;
-  const int64_t tiles = T * (T + 1) / 2;
-  if (tiles > 0x7fffffff) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((dgemm_kernel<true, kTriGrid>), dim3((unsigned)tiles), dim3(256), 0, s, n, n, K,
-                     alpha, A, lda, A, lda, C, ldc);
-  return hipGetLastError();
+  return launch_gemm<true, kTriGrid, true>(n, n, K, alpha, A, lda, A, lda, C, ldc, s);
 }
 
 // K holds the Cholesky factor L in its lower triangle.  Y ([nrhs][n]) is
