@@ -214,6 +214,10 @@ __device__ __forceinline__ void load_diag_block(const double* __restrict__ K, in
   }
 }
 
+// Both sweeps issue every global load of a right-hand side (the block's
+// entries, the entries they update) before the first barrier or before the
+// solve, and the diagonal's reciprocals are formed in parallel, so the
+// serial part is one multiply and one cross-lane broadcast per unknown.
 __global__ void __launch_bounds__(256)
 trsv_fwd_step(const double* __restrict__ K, double* __restrict__ Y, double* __restrict__ Z,
               int64_t n, int64_t nrhs, int64_t j0, int bs) {
@@ -231,13 +235,16 @@ trsv_fwd_step(const double* __restrict__ K, double* __restrict__ Y, double* __re
     const int64_t i = min(rbeg + wave * kPer + u, n - 1);
     lr[u] = K[i * n + j0 + min(lane, bs - 1)];
   }
+  const int64_t my_row = min(rbeg + wave * kPer + min(lane, kPer - 1), n - 1);
+  const int bl = min(lane, bs - 1);
+  double yb = Y[j0 + bl], yo = Y[my_row];  // right-hand side 0
   __syncthreads();
+  const double rl = 1.0 / l[bl][bl];
   for (int64_t r = 0; r < nrhs; ++r) {
     if (wave == 0) {  // lane c holds unknown c; at step c lane c finishes it
-      double v = Y[r * n + j0 + min(lane, bs - 1)];
-      if (lane >= bs) v = 0.0;
+      double v = (lane < bs) ? yb : 0.0;
       for (int c = 0; c < bs; ++c) {
-        const double zc = __shfl(v / l[c][c], c, 64);
+        const double zc = __shfl(v * rl, c, 64);
         if (lane == c) v = zc;
         else if (lane > c) v -= l[lane][c] * zc;
       }
@@ -246,11 +253,16 @@ trsv_fwd_step(const double* __restrict__ K, double* __restrict__ Y, double* __re
     }
     __syncthreads();
     const double zl = (lane < bs) ? zb[lane] : 0.0;
+    double mine = 0.0;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
-      const int64_t i = rbeg + wave * kPer + u;
       const double s = wave_total(lr[u] * zl);
-      if (lane == 0 && i < n) Y[r * n + i] -= s;
+      if (lane == u) mine = s;
+    }
+    if (lane < kPer && rbeg + wave * kPer + lane < n) Y[r * n + my_row] = yo - mine;
+    if (r + 1 < nrhs) {
+      yb = Y[(r + 1) * n + j0 + bl];
+      yo = Y[(r + 1) * n + my_row];
     }
     __syncthreads();  // zb is rewritten for the next right-hand side
   }
@@ -270,13 +282,15 @@ trsv_bwd_step(const double* __restrict__ K, double* __restrict__ Y, double* __re
   double lc[kNb];
 #pragma unroll
   for (int t = 0; t < kNb; ++t) lc[t] = K[(j0 + min(t, bs - 1)) * n + cc];
+  const int bl = min(lane, bs - 1);
+  double zv = Z[j0 + bl], zo = Z[cc];  // right-hand side 0
   __syncthreads();
+  const double rl = 1.0 / l[bl][bl];
   for (int64_t r = 0; r < nrhs; ++r) {
     if (wave == 0) {  // lane t holds unknown t; from the last one down
-      double v = Z[r * n + j0 + min(lane, bs - 1)];
-      if (lane >= bs) v = 0.0;
+      double v = (lane < bs) ? zv : 0.0;
       for (int t = bs - 1; t >= 0; --t) {
-        const double xt = __shfl(v / l[t][t], t, 64);
+        const double xt = __shfl(v * rl, t, 64);
         if (lane == t) v = xt;
         else if (lane < t) v -= l[t][lane] * xt;
       }
@@ -287,7 +301,11 @@ trsv_bwd_step(const double* __restrict__ K, double* __restrict__ Y, double* __re
     double acc = 0.0;
 #pragma unroll
     for (int t = 0; t < kNb; ++t) acc += (t < bs ? lc[t] : 0.0) * xb[t];
-    if (own) Z[r * n + c] -= acc;
+    if (own) Z[r * n + c] = zo - acc;
+    if (r + 1 < nrhs) {
+      zv = Z[(r + 1) * n + j0 + bl];
+      zo = Z[(r + 1) * n + cc];
+    }
     __syncthreads();  // xb is rewritten for the next right-hand side
   }
 }
