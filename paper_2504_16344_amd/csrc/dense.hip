@@ -177,24 +177,41 @@ block_diag_scan(double* __restrict__ X, int64_t ld, int64_t T, int64_t P, int64_
 
 // Diagonal blocks of the triangular solves for many right-hand sides.  Y is
 // [nrhs][n]; a wavefront owns one right-hand side at a time (lane = row of
-// the block), the block of the factor sits in LDS for the workgroup.
+// the block), the block of the factor sits in LDS for the workgroup (loaded
+// coalesced, all loads issued first, clamped addresses), and each lane keeps
+// the reciprocal of its diagonal entry, so a step is one multiply and one
+// cross-lane broadcast.
+__device__ __forceinline__ double load_tri_block(const double* __restrict__ K, int64_t n,
+                                                 int64_t j0, int bs, double (*l)[kTriNb + 1]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cl = min(lane, bs - 1);
+  double v[kTriNb / 4];
+#pragma unroll
+  for (int u = 0; u < kTriNb / 4; ++u) v[u] = K[(j0 + min(4 * u + wave, bs - 1)) * n + j0 + cl];
+#pragma unroll
+  for (int u = 0; u < kTriNb / 4; ++u) {
+    const int row = 4 * u + wave;
+    l[row][lane] = (row < bs && lane <= row) ? v[u] : 0.0;
+  }
+  __syncthreads();
+  return 1.0 / l[cl][cl];
+}
+
 // Forward: y[j0 : j0 + bs] = L11^{-1} y[j0 : j0 + bs].
 __global__ void __launch_bounds__(256)
 trsm_lower_diag_many(const double* __restrict__ K, double* __restrict__ Y, int64_t n,
                      int64_t nrhs, int64_t j0, int bs) {
   __shared__ double l[kTriNb][kTriNb + 1];
-  for (int e = threadIdx.x; e < kTriNb * kTriNb; e += 256) {
-    const int i = e / kTriNb, j = e % kTriNb;
-    l[i][j] = (i < bs && j <= i) ? K[(j0 + i) * n + j0 + j] : 0.0;
-  }
-  __syncthreads();
+  const double rl = load_tri_block(K, n, j0, bs, l);
   const int lane = threadIdx.x & 63;
+  const int cl = min(lane, bs - 1);
   for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < nrhs;
        r += (int64_t)gridDim.x * 4) {
     double* y = Y + r * n + j0;
-    double v = (lane < bs) ? y[lane] : 0.0;
+    double v = y[cl];
+    if (lane >= bs) v = 0.0;
     for (int c = 0; c < bs; ++c) {
-      const double yc = __shfl(v / l[c][c], c, 64);
+      const double yc = __shfl(v * rl, c, 64);
       if (lane == c) v = yc;
       else if (lane > c) v -= l[lane][c] * yc;
     }
@@ -207,18 +224,16 @@ __global__ void __launch_bounds__(256)
 trsm_upper_diag_many(const double* __restrict__ K, double* __restrict__ Y, int64_t n,
                      int64_t nrhs, int64_t j0, int bs) {
   __shared__ double l[kTriNb][kTriNb + 1];
-  for (int e = threadIdx.x; e < kTriNb * kTriNb; e += 256) {
-    const int i = e / kTriNb, j = e % kTriNb;
-    l[i][j] = (i < bs && j <= i) ? K[(j0 + i) * n + j0 + j] : 0.0;
-  }
-  __syncthreads();
+  const double rl = load_tri_block(K, n, j0, bs, l);
   const int lane = threadIdx.x & 63;
+  const int cl = min(lane, bs - 1);
   for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < nrhs;
        r += (int64_t)gridDim.x * 4) {
     double* y = Y + r * n + j0;
-    double v = (lane < bs) ? y[lane] : 0.0;
+    double v = y[cl];
+    if (lane >= bs) v = 0.0;
     for (int t = bs - 1; t >= 0; --t) {
-      const double xt = __shfl(v / l[t][t], t, 64);
+      const double xt = __shfl(v * rl, t, 64);
       if (lane == t) v = xt;
       else if (lane < t) v -= l[t][lane] * xt;
     }

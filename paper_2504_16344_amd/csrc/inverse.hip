@@ -123,8 +123,9 @@ potrf_trsm(double* __restrict__ K, int64_t n, int64_t j0, int bs, int64_t* __res
     for (int u = 0; u < kNb; ++u) x[u][lane] = K[(r0 + min(u, rows - 1)) * n + j0 + cl];
   }
   __syncthreads();
+  __shared__ double colk[kNb + 1];  // column k of L, the pivot; then the reciprocals
+  const double* rinv = colk;
   {  // factor with lane's row in registers; column k of L goes through LDS
-    __shared__ double colk[kNb + 1];
     double r[kNb];
 #pragma unroll
     for (int j = 0; j < kNb; ++j) r[j] = a[lane][j];
@@ -135,8 +136,8 @@ potrf_trsm(double* __restrict__ K, int64_t n, int64_t j0, int bs, int64_t* __res
         __syncthreads();
         const double d = colk[kNb];
         if (lane == 0 && blockIdx.x == 0 && !(d > 0.0) && *info < 0) *info = j0 + k;
-        const double piv = sqrt(d);
-        r[k] = (lane == k) ? piv : (lane > k ? r[k] / piv : r[k]);
+        const double piv = sqrt(d), pinv = 1.0 / piv;
+        r[k] = (lane == k) ? piv : (lane > k ? r[k] * pinv : r[k]);
         colk[lane] = r[k];
         __syncthreads();
         const double lik = (lane > k) ? r[k] : 0.0;
@@ -147,6 +148,7 @@ potrf_trsm(double* __restrict__ K, int64_t n, int64_t j0, int bs, int64_t* __res
     }
 #pragma unroll
     for (int j = 0; j < kNb; ++j) a[lane][j] = (j <= lane) ? r[j] : 0.0;
+    colk[lane] = 1.0 / ((lane < bs) ? a[lane][lane] : 1.0);  // diagonal reciprocals
   }
   __syncthreads();
   if (blockIdx.x == 0) {
@@ -164,7 +166,7 @@ potrf_trsm(double* __restrict__ K, int64_t n, int64_t j0, int bs, int64_t* __res
 #pragma unroll
     for (int c = 0; c < kNb; ++c) {
       if (c < bs) {  // uniform
-        xr[c] = xr[c] / a[c][c];
+        xr[c] = xr[c] * rinv[c];
 #pragma unroll
         for (int t = c + 1; t < kNb; ++t) xr[t] -= xr[c] * a[t][c];
       }
