@@ -211,8 +211,11 @@ void p2o_batch_destroy(p2o_batch b);
  *              unit-vector method, the lower triangle mirrored by the Gram
  *              form.
  * Requires a P2O_FP64 plan (else P2O_EUNSUPPORTED).  Allocates a temporary
- * workspace (up to ~8 GB by the unit-vector method; see p2o_assembly for
- * the Gram form) and synchronises `stream`. */
+ * workspace and synchronises `stream`.  The unit-vector method keeps the
+ * time-domain blocks ((Nt Nd) Nm doubles, three times that with a spatial
+ * prior) plus per-pass buffers bounded by the environment variable
+ * P2O_WORKSPACE_MB (MiB; default 8 GiB; at least one unit vector's
+ * spectra); see p2o_assembly for the Gram form. */
 p2o_status p2o_hessian_assemble(p2o_handle h, double prior_var,
                                 const double* noise_var, double* K,
                                 void* stream);

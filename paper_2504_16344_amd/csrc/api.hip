@@ -739,6 +739,16 @@ hipError_t time_blocks(const p2o_plan_s* h, double* out, hipStream_t s) {
   return launch_rfft_inv_f64(h->fft, h->tw64, h->perm, io, 1, s);
 }
 
+// Bound on the temporaries of the unit-vector assembly: P2O_WORKSPACE_MB
+// (MiB) when set to a positive integer, else 8 GiB.
+size_t workspace_budget() {
+  if (const char* v = std::getenv("P2O_WORKSPACE_MB")) {
+    const long long mb = std::atoll(v);
+    if (mb > 0) return (size_t)mb << 20;
+  }
+  return (size_t)8 << 30;
+}
+
 // Rows of hf's F applied after Gamma_prior times ha's F*: for every unit
 // vector e_j of ha's data space (j = i Nd_a + s: sensor s, step i),
 // row j of `out` (leading dimension ldo) receives F_hf Gamma_prior F_ha^* e_j
@@ -764,35 +774,38 @@ p2o_status assemble_rows(p2o_plan_s* ha, p2o_plan_s* hf, const p2o_plan_s* hp,
                                static_cast<double*>(t2), Nt * nda, hp->prior_nx, hp->prior_ny,
                                hp->prior_w, hp->prior_r, hp->prior_delta, s));
   }
-  // whole sensors per pass: every unit vector's parameter spectrum and
-  // partial data spectra
+  // unit vectors per pass: whole sensors when the temporary budget holds a
+  // sensor's Nt steps, else runs of steps of one sensor
   const size_t per = (size_t)hf->nf * Nm * 16 + (size_t)hf->n_pc * hf->nf * hf->Nd * 16;
-  const size_t budget = (size_t)8 << 30;
-  const int64_t ns = std::max<int64_t>(
-      1, std::min<int64_t>({nda, 65535 / Nt, (int64_t)(budget / (per * Nt))}));
+  const int64_t upp = std::max<int64_t>(1, std::min<int64_t>(65535, (int64_t)(workspace_budget() / per)));
+  const int64_t ni = std::min(Nt, upp);
+  const int64_t ns = ni < Nt ? 1 : std::max<int64_t>(1, std::min(nda, upp / Nt));
   void *xh, *parts;
-  TRY_HIP(bufs.alloc(&xh, (size_t)ns * Nt * hf->nf * Nm * 16));
-  TRY_HIP(bufs.alloc(&parts, (size_t)ns * Nt * hf->n_pc * hf->nf * hf->Nd * 16));
+  TRY_HIP(bufs.alloc(&xh, (size_t)ns * ni * hf->nf * Nm * 16));
+  TRY_HIP(bufs.alloc(&parts, (size_t)ns * ni * hf->n_pc * hf->nf * hf->Nd * 16));
   const int64_t in_batch = hf->n_pc * hf->nf * hf->Nd;  // complex entries a unit vector
   for (int64_t s0 = 0; s0 < nda; s0 += ns) {
     const int nsb = (int)std::min(ns, nda - s0);
-    TRY_HIP(launch_unit_spectra(static_cast<const double*>(a), nda, Nm, Nt, hf->nf, hf->L,
-                                hf->tw64, s0, nsb, prior_var, static_cast<cpx<double>*>(xh),
-                                s));
-    TRY_HIP(launch_product(hf, P2O_F, xh, parts, nullptr, (int64_t)nsb * Nt, hf->cfg[P2O_F], s));
-    for (int j = 0; j < nsb; ++j) {  // sensor s0 + j: steps i to rows i Nd_a + s0 + j
-      FftIo o{};
-      o.in = static_cast<const cpx<double>*>(parts) + (int64_t)j * Nt * in_batch;
-      o.out = out + (s0 + j) * ldo;
-      o.ncols = hf->Nd;
-      o.in_row = hf->Nd;
-      o.nparts = (int)hf->n_pc;
-      o.part_stride = hf->nf * hf->Nd;
-      o.in_batch = in_batch;
-      o.out_row = hf->Nd;
-      o.out_batch = nda * ldo;
-      o.scale = 1.0 / (double)hf->L;
-      TRY_HIP(launch_rfft_inv_f64(hf->fft, hf->tw64, hf->perm, o, Nt, s));
+    for (int64_t i0 = 0; i0 < Nt; i0 += ni) {
+      const int64_t nib = std::min(ni, Nt - i0);
+      TRY_HIP(launch_unit_spectra(static_cast<const double*>(a), nda, Nm, hf->nf, hf->L,
+                                  hf->tw64, s0, nsb, i0, nib, prior_var,
+                                  static_cast<cpx<double>*>(xh), s));
+      TRY_HIP(launch_product(hf, P2O_F, xh, parts, nullptr, nsb * nib, hf->cfg[P2O_F], s));
+      for (int j = 0; j < nsb; ++j) {  // sensor s0 + j: step i to row i Nd_a + s0 + j
+        FftIo o{};
+        o.in = static_cast<const cpx<double>*>(parts) + (int64_t)j * nib * in_batch;
+        o.out = out + (i0 * nda + s0 + j) * ldo;
+        o.ncols = hf->Nd;
+        o.in_row = hf->Nd;
+        o.nparts = (int)hf->n_pc;
+        o.part_stride = hf->nf * hf->Nd;
+        o.in_batch = in_batch;
+        o.out_row = hf->Nd;
+        o.out_batch = nda * ldo;
+        o.scale = 1.0 / (double)hf->L;
+        TRY_HIP(launch_rfft_inv_f64(hf->fft, hf->tw64, hf->perm, o, nib, s));
+      }
     }
   }
   // the scratch buffers are freed on return: finish their users first

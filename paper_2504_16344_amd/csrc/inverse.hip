@@ -23,32 +23,34 @@ namespace {
 constexpr int kNb = 64;  // Cholesky / triangular-solve block size
 
 // ------------------------------------------------------------ assembly
-// Spectra of the adjoint unit vectors e_(i,s), i = 0 .. Nt-1, of sensors
-// s0 .. s0 + ns - 1 (time-shift major: batch b = (s - s0) Nt + i), already
+// Spectra of the adjoint unit vectors e_(i,s), steps i0 <= i < i0 + ni of
+// sensors s0 .. s0 + ns - 1 (batch b = (s - s0) ni + i - i0), already
 // truncated to Nt steps and zero padded to L.  The time-domain F^* e_(i,s)
 // is row s of F_(i-t) at step t <= i and zero after, so its spectrum is
 //   xh_b[k][p] = scale W^(ik) P_i(k, p),  P_i = P_(i-1) + A[(i, s)][p] W^(-ik),
-// a running sum over the shifts (A: the time-domain rows, row i Nd + s =
-// row s of F_i, with the prior's spatial factor already applied).  One
-// thread per (k, p) walks the shifts; tw holds W^m = exp(-2 pi i m / L).
+// a running sum over the steps (A: the time-domain rows, row i Nd + s =
+// row s of F_i, with the prior's spatial factor already applied); the sum
+// starts at step 0 whatever i0 is.  One thread per (k, p) walks the steps;
+// tw holds W^m = exp(-2 pi i m / L).
 __global__ void __launch_bounds__(256)
-unit_spectra(const double* __restrict__ A, int64_t Nd, int64_t Nm, int64_t Nt, int64_t nf,
-             int64_t L, const cpx<double>* __restrict__ tw, int64_t s0, int ns, double scale,
-             cpx<double>* __restrict__ xh) {
+unit_spectra(const double* __restrict__ A, int64_t Nd, int64_t Nm, int64_t nf, int64_t L,
+             const cpx<double>* __restrict__ tw, int64_t s0, int ns, int64_t i0, int64_t ni,
+             double scale, cpx<double>* __restrict__ xh) {
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t k = blockIdx.y;
   if (p >= Nm) return;
   for (int j = 0; j < ns; ++j) {
     const double* __restrict__ a = A + (s0 + j) * Nm + p;
-    cpx<double>* __restrict__ o = xh + ((int64_t)j * Nt * nf + k) * Nm + p;
+    cpx<double>* __restrict__ o = xh + ((int64_t)j * ni * nf + k) * Nm + p;
     double pr = 0.0, pi = 0.0;
     int64_t m = 0;  // i k mod L
-    for (int64_t i = 0; i < Nt; ++i) {
+    for (int64_t i = 0; i < i0 + ni; ++i) {
       const cpx<double> w = tw[m];
       const double v = a[i * Nd * Nm];
       pr += v * w.x;  // v W^(-ik) = v conj(W^(ik))
       pi -= v * w.y;
-      o[i * nf * Nm] = {scale * (w.x * pr - w.y * pi), scale * (w.x * pi + w.y * pr)};
+      if (i >= i0)
+        o[(i - i0) * nf * Nm] = {scale * (w.x * pr - w.y * pi), scale * (w.x * pi + w.y * pr)};
       m += k;
       if (m >= L) m -= L;
     }
@@ -375,14 +377,14 @@ unsigned grid1(int64_t n, int per = 256) {
 
 }  // namespace
 
-hipError_t launch_unit_spectra(const double* A, int64_t Nd, int64_t Nm, int64_t Nt, int64_t nf,
-                               int64_t L, const cpx<double>* tw, int64_t s0, int ns,
+hipError_t launch_unit_spectra(const double* A, int64_t Nd, int64_t Nm, int64_t nf, int64_t L,
+                               const cpx<double>* tw, int64_t s0, int ns, int64_t i0, int64_t ni,
                                double scale, cpx<double>* xh, hipStream_t s) {
-  if (Nm <= 0 || nf <= 0 || ns <= 0) return hipSuccess;
+  if (Nm <= 0 || nf <= 0 || ns <= 0 || ni <= 0) return hipSuccess;
   if (nf > 65535) return hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)((Nm + 255) / 256), (unsigned)nf);
-  hipLaunchKernelGGL(unit_spectra, grid, dim3(256), 0, s, A, Nd, Nm, Nt, nf, L, tw, s0, ns, scale,
-                     xh);
+  hipLaunchKernelGGL(unit_spectra, grid, dim3(256), 0, s, A, Nd, Nm, nf, L, tw, s0, ns, i0, ni,
+                     scale, xh);
   return hipGetLastError();
 }
 

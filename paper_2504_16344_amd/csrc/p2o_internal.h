@@ -176,11 +176,12 @@ hipError_t launch_batch_product(BatchClass cls, p2o_op op, const BatchInst* inst
                                 int64_t total_units, hipStream_t s);
 
 // ------------------------------------------------------- inversion kernels
-// xh[(s - s0) Nt + i][k][p] (k < nf, p < Nm): spectra of the truncated,
-// zero-padded adjoint unit vectors e_(i,s), s0 <= s < s0 + ns, times scale,
-// from the time-domain rows A[(i Nd + s)][Nm] by a running sum over i.
-hipError_t launch_unit_spectra(const double* A, int64_t Nd, int64_t Nm, int64_t Nt, int64_t nf,
-                               int64_t L, const cpx<double>* tw, int64_t s0, int ns,
+// xh[(s - s0) ni + i - i0][k][p] (k < nf, p < Nm): spectra of the
+// truncated, zero-padded adjoint unit vectors e_(i,s), s0 <= s < s0 + ns,
+// i0 <= i < i0 + ni, times scale, from the time-domain rows A[(i Nd + s)][Nm]
+// by a running sum over i.
+hipError_t launch_unit_spectra(const double* A, int64_t Nd, int64_t Nm, int64_t nf, int64_t L,
+                               const cpx<double>* tw, int64_t s0, int ns, int64_t i0, int64_t ni,
                                double scale, cpx<double>* xh, hipStream_t s);
 hipError_t launch_add_diagonal(double* K, const double* v, int64_t n, hipStream_t s);
 hipError_t launch_symmetrize(double* K, int64_t n, hipStream_t s);    // (K + K^T) / 2

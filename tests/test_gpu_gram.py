@@ -1,7 +1,7 @@
 """Gram-form assembly (p2o_set_assembly(P2O_ASSEMBLE_GRAM)) through the C
 ABI: K = Gn + F Gp F* against the oracle's dense definition at small and
 ragged sizes (several 64-wide GEMM tiles with ragged tails, contraction
-lengths off the 16-entry chunk, a single time step), against the unit-vector
+lengths off the 32-entry chunk, a single time step), against the unit-vector
 method, with a spatial prior, the QoI maps (rectangular block-diagonal sums
 with different row and column steps), sampled columns at the
 100 x 5000 x 200 inversion workload, and the argument checks."""
@@ -137,3 +137,27 @@ def test_set_assembly_checks():
         lib = P.load_library()
         assert lib.p2o_set_assembly(plan._handle(), 2) == 1
         assert lib.p2o_set_assembly(None, 0) == 1
+
+
+def test_unit_vector_assembly_in_step_runs(monkeypatch):
+    """Temporary budgets below one sensor's spectra split the unit-vector
+    assembly into runs of time steps (the running sum restarted per run,
+    with a ragged last run); a budget of two sensors gives passes of 2 and 1
+    sensors.  K must not change."""
+    Nd, Nm, Nt = 3, 500, 40
+    blocks, _, _ = workload(45, Nd, Nm, Nt, tau=12.0)
+    n = Nt * Nd
+    nv = _noise(45, n)
+    K_ref = oracle.hessian_dense(blocks, 0.25, nv)
+    with P.Plan(dev(blocks), "fp64") as plan:
+        K_all = host(plan.hessian(0.25, dev(nv), method="matvec"))
+        # one unit vector's spectra: nf * Nm * 16 bytes = 41 * 500 * 16 = 0.33 MB
+        monkeypatch.setenv("P2O_WORKSPACE_MB", "3")  # ~9 unit vectors a pass
+        K_run = host(plan.hessian(0.25, dev(nv)))
+        monkeypatch.setenv("P2O_WORKSPACE_MB", "27")  # two sensors (80 unit vectors)
+        K_two = host(plan.hessian(0.25, dev(nv)))
+    scale = np.abs(K_ref).max()
+    print(f"\n[gram] step runs: {np.abs(K_run - K_ref).max() / scale:.2e}", flush=True)
+    assert np.abs(K_run - K_ref).max() <= 1e-12 * scale
+    assert np.abs(K_run - K_all).max() <= 1e-13 * scale
+    assert np.abs(K_two - K_all).max() <= 1e-13 * scale
