@@ -108,11 +108,14 @@ def step_bytes(prec, Nd, Nm, Nt, nf, n_pc):
             + fF + iF + fA + iA)
 
 
-def n_chunks(Nd, Nm, nf):
-    """Column chunking of the F product (mirrors the library's choice)."""
+def n_chunks(Nd, Nm, nf, prec="fp64"):
+    """Column chunking of the F product (mirrors the library's choice: the
+    16-bit tiers also cap a chunk at 4096 columns)."""
     base = nf * ((Nd + 3) // 4)
     n = max(1, (16384 + base - 1) // base)
     n = min(n, max(1, Nm // 256))
+    if prec != "fp64":
+        n = max(n, (Nm + 4095) // 4096)
     ln = (Nm + n - 1) // n
     ln = (ln + 63) // 64 * 64
     return (Nm + ln - 1) // ln
@@ -235,7 +238,7 @@ def bench_batch(args):
     nf = L // 2 + 1
     stream = torch.cuda.current_stream()
     prec = "mixed_bf16"
-    npc = [n_chunks(int(Nd[i]), int(Nm[i]), nf) for i in range(n)]
+    npc = [n_chunks(int(Nd[i]), int(Nm[i]), nf, prec) for i in range(n)]
     need = [instance_bytes(prec, int(Nd[i]), int(Nm[i]), Nt, int(R[i]), nf, npc[i]) for i in range(n)]
     budget = args.budget_gb * 1e9
     waves, cur, used = [], [], 0
@@ -392,7 +395,6 @@ def bench_mrhs(args):
     Nd, Nm, Nt, B = args.Nd, args.Nm, args.Nt, args.nrhs
     L = P.smooth_length(Nt)
     nf = L // 2 + 1
-    n_pc = n_chunks(Nd, Nm, nf)
     precs = [p.strip() for p in args.precs.split(",") if p.strip()]
     if args.precs == DEFAULT_PRECS:
         precs = ["mixed_bf16", "fp64"]
@@ -437,7 +439,7 @@ def bench_mrhs(args):
              "roofline": {}}
         for op in ("F", "FADJ"):
             ms = r["product_kernel_ms"][op]
-            nbytes = mrhs_product_bytes(prec, op, Nd, Nm, nf, n_pc, B)
+            nbytes = mrhs_product_bytes(prec, op, Nd, Nm, nf, n_chunks(Nd, Nm, nf, prec), B)
             hw = flops * SPLIT_FACTOR[prec]
             t_hbm = nbytes / (PEAK_HBM_GBS * 1e9)
             t_mfma = hw / (PEAK_TFLOPS[prec] * 1e12)
@@ -455,6 +457,7 @@ def bench_mrhs(args):
                        "mfma_frac": round(tfs / PEAK_TFLOPS[prec], 4)})
             r["roofline"][op] = rf
         r["ms_per_step"] = r["apply_ms"]["F"] + r["apply_ms"]["FADJ"]
+        n_pc = n_chunks(Nd, Nm, nf, prec)
         r["step_bytes"] = (mrhs_product_bytes(prec, "F", Nd, Nm, nf, n_pc, B)
                            + mrhs_product_bytes(prec, "FADJ", Nd, Nm, nf, 1, B)
                            + B * (Nt * Nm * 8 * 2 + Nt * Nd * 8 * 2))
@@ -619,7 +622,6 @@ def main():
     Nd, Nm, Nt = args.Nd, args.Nm, args.Nt
     L = P.smooth_length(Nt)
     nf = L // 2 + 1
-    n_pc = n_chunks(Nd, Nm, nf)
     precs = [p.strip() for p in args.precs.split(",") if p.strip()]
     stream = torch.cuda.current_stream()
     env = S.envelope(Nt, args.tau, 1.0 / np.sqrt(Nm))
@@ -679,9 +681,9 @@ def main():
             "apply_ms": {"F": ev[0].elapsed_time(ev[1]) / args.steps,
                          "FADJ": ev[1].elapsed_time(ev[2]) / args.steps},
             "product_kernel_ms": {"F": msF / max(nF, 1), "FADJ": msA / max(nA, 1)},
-            "product_bytes": {"F": product_bytes(prec, "F", Nd, Nm, nf, n_pc),
+            "product_bytes": {"F": product_bytes(prec, "F", Nd, Nm, nf, n_chunks(Nd, Nm, nf, prec)),
                               "FADJ": product_bytes(prec, "FADJ", Nd, Nm, nf, 1)},
-            "step_bytes": step_bytes(prec, Nd, Nm, Nt, nf, n_pc),
+            "step_bytes": step_bytes(prec, Nd, Nm, Nt, nf, n_chunks(Nd, Nm, nf, prec)),
             "autotune": tuned,
         }
         r["gbs"] = r["step_bytes"] / (r["ms_per_step"] * 1e-3) / 1e9

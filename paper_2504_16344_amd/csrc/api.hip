@@ -67,11 +67,19 @@ constexpr int kRowsPerWave = 4;        // must match the row kernels
 constexpr int64_t kTargetWaves = 16384;
 
 // Column chunking of the F product: enough wavefronts to fill the chip,
-// chunks of at least 256 columns, chunk length a multiple of 64.
+// chunks of at least 256 columns, chunk length a multiple of 64.  For the
+// 16-bit tiers a chunk is also at most kMixedChainCols columns: the
+// matrix-core products accumulate a chunk in float32 accumulators, whose
+// rounding at each 32-column step is not free of bias (measured: an error
+// growing linearly with the chunk length that adds up coherently in the
+// first output steps), and the chunks' partial sums are added in float64.
+constexpr int64_t kMixedChainCols = 4096;
 void choose_chunks(p2o_plan_s* h, int64_t* n_pc, int64_t* pc_len) {
   const int64_t base = h->nf * ((h->Nd + kRowsPerWave - 1) / kRowsPerWave);
   int64_t n = std::max<int64_t>(1, (kTargetWaves + base - 1) / base);
   n = std::min<int64_t>(n, std::max<int64_t>(1, h->Nm / 256));
+  if (is_mixed(h->prec))
+    n = std::max<int64_t>(n, (h->Nm + kMixedChainCols - 1) / kMixedChainCols);
   int64_t len = (h->Nm + n - 1) / n;
   len = (len + 63) / 64 * 64;
   *pc_len = len;
