@@ -44,15 +44,25 @@ unit_spectra(const double* __restrict__ A, int64_t Nd, int64_t Nm, int64_t nf, i
     cpx<double>* __restrict__ o = xh + ((int64_t)j * ni * nf + k) * Nm + p;
     double pr = 0.0, pi = 0.0;
     int64_t m = 0;  // i k mod L
-    for (int64_t i = 0; i < i0 + ni; ++i) {
-      const cpx<double> w = tw[m];
-      const double v = a[i * Nd * Nm];
-      pr += v * w.x;  // v W^(-ik) = v conj(W^(ik))
-      pi -= v * w.y;
-      if (i >= i0)
-        o[(i - i0) * nf * Nm] = {scale * (w.x * pr - w.y * pi), scale * (w.x * pi + w.y * pr)};
-      m += k;
-      if (m >= L) m -= L;
+    const int64_t iend = i0 + ni;
+    constexpr int G = 8;  // steps whose block entries are loaded ahead
+    for (int64_t ib = 0; ib < iend; ib += G) {
+      double v[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) v[g] = a[min(ib + g, iend - 1) * Nd * Nm];  // clamped
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int64_t i = ib + g;
+        if (i < iend) {
+          const cpx<double> w = tw[m];
+          pr += v[g] * w.x;  // v W^(-ik) = v conj(W^(ik))
+          pi -= v[g] * w.y;
+          if (i >= i0)
+            o[(i - i0) * nf * Nm] = {scale * (w.x * pr - w.y * pi), scale * (w.x * pi + w.y * pr)};
+          m += k;
+          if (m >= L) m -= L;
+        }
+      }
     }
   }
 }
