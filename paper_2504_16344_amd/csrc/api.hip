@@ -920,12 +920,9 @@ p2o_status p2o_qoi_precompute(p2o_handle hF, p2o_handle hq, const double* Kfac,
   // Q = Fq Gp F^* K^{-1} = (K^{-1} B)^T: row j of Q is K^{-1} (column j of B)
   TRY_HIP(hipMemcpyAsync(Q, Bt, (size_t)nq * n * 8, hipMemcpyDeviceToDevice, s));
   TRY_HIP(launch_cholesky_solve_many(Kfac, Q, n, nq, s));
-  // Gq = Fq Gp Fq^* - Q B
-  TRY_HIP(launch_dgemm(true, nq, nq, n, -1.0, Q, n, Bt, n, Gq, nq, s));
-  if (gram)
-    TRY_HIP(launch_mirror_lower(Gq, nq, s));
-  else
-    TRY_HIP(launch_symmetrize(Gq, nq, s));
+  // Gq = Fq Gp Fq^* - Q B (symmetric: lower triangle, then mirrored)
+  TRY_HIP(launch_dgemm_nt_lower(nq, n, -1.0, Q, n, Bt, n, Gq, nq, s));
+  TRY_HIP(launch_mirror_lower(Gq, nq, s));
   TRY_HIP(hipStreamSynchronize(s));
   return P2O_OK;
 }

@@ -354,6 +354,12 @@ hipError_t launch_dgemm_nt_set(bool lower, int64_t M, int64_t N, int64_t K, doub
   return launch_gemm<true, kFullCols, false>(M, N, K, alpha, A, lda, B, ldb, C, ldc, s);
 }
 
+hipError_t launch_dgemm_nt_lower(int64_t n, int64_t K, double alpha, const double* A,
+                                 int64_t lda, const double* B, int64_t ldb, double* C,
+                                 int64_t ldc, hipStream_t s) {
+  return launch_gemm<true, kTriGrid, true>(n, n, K, alpha, A, lda, B, ldb, C, ldc, s);
+}
+
 hipError_t launch_dgemm_nt_lower_mask(int64_t M, int64_t N, int64_t K, double alpha,
                                       const double* A, int64_t lda, const double* B,
                                       int64_t ldb, double* C, int64_t ldc, hipStream_t s) {

@@ -216,6 +216,11 @@ hipError_t launch_dgemm_nt_set(bool lower, int64_t M, int64_t N, int64_t K, doub
 // with lower (P == Q) only the lower triangle is read and written.
 hipError_t launch_block_diag_scan(double* X, int64_t ld, int64_t T, int64_t P, int64_t Q,
                                   bool lower, hipStream_t s);
+// Lower triangle of C[n x n] += alpha A B^T (A, B [n x K]); entries above
+// the diagonal untouched.
+hipError_t launch_dgemm_nt_lower(int64_t n, int64_t K, double alpha, const double* A,
+                                 int64_t lda, const double* B, int64_t ldb, double* C,
+                                 int64_t ldc, hipStream_t s);
 // C[i][j] += alpha sum_k A[i][k] B[j][k] for i < M, j < N with j <= i only
 // (C's origin on the diagonal of a symmetric matrix kept in its lower
 // triangle; the entries above it are not touched).
