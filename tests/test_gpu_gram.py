@@ -43,9 +43,12 @@ def test_gram_hessian_matches_dense_definition(shape):
     assert em <= 1e-12
 
 
-def test_gram_posterior_and_qoi_match_oracle():
-    Nd, Nq, Nm, Nt, nrhs = 6, 3, 200, 30, 2
-    print("\n[gram] posterior + QoI", flush=True)
+@pytest.mark.parametrize("Nd,Nq", [(6, 3), (3, 7)])
+def test_gram_posterior_and_qoi_match_oracle(Nd, Nq):
+    """Both row-step orders of the rectangular block-diagonal sums (N_q below
+    and above N_d)."""
+    Nm, Nt, nrhs = 200, 30, 2
+    print(f"\n[gram] posterior + QoI Nd={Nd} Nq={Nq}", flush=True)
     blocks, _, _ = workload(42, Nd, Nm, Nt, tau=10.0)
     env = S.envelope(Nt, 10.0, 1.0 / np.sqrt(Nm))
     blocks_q = S.blocks(42 + S.QOI_SEED_OFFSET, Nq, Nm, Nt, env)
