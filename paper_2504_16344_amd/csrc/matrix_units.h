@@ -391,10 +391,16 @@ __device__ __forceinline__ BlockOps unpack_block(const uint32_t (&w0)[8], const 
 }
 
 // F chunk: t[b] += Fhat[rows, chunk] X[chunk, b] for the 16 NT right-hand
-// sides; re: Hr xr - Hi xi, im: Hr xi + Hi xr, each with hi/lo splits.
+// sides; re: Hr xr - Hi xi, im: Hr xi + Hi xr, each with hi/lo splits.  The
+// hi x hi products go to tr / ti, the hi x lo and lo x hi products (about
+// 2^-8 of them) to their own accumulators sr / si: added to an accumulator
+// 2^8 and more times larger, the matrix cores lose their low bits with a
+// bias toward minus infinity (measured on gfx950), which over thousands of
+// steps adds up coherently; summed among themselves they do not.
 template <int NT, bool LO>
 __device__ __forceinline__ void rows_bf16_products(const BlockOps& a, const u4v* xs, int kg,
-                                                   int col, f4v (&tr)[NT], f4v (&ti)[NT]) {
+                                                   int col, f4v (&tr)[NT], f4v (&ti)[NT],
+                                                   f4v (&sr)[NT], f4v (&si)[NT]) {
   constexpr int PP = NT * 16 + 1;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -403,17 +409,17 @@ __device__ __forceinline__ void rows_bf16_products(const BlockOps& a, const u4v*
     const u4v xih = xs[(2 * 4 + kg) * PP + b], xil = xs[(3 * 4 + kg) * PP + b];
     tr[t] = mma(a.hr, xrh, tr[t]);
     ti[t] = mma(a.hr, xih, ti[t]);
-    tr[t] = mma(a.hr, xrl, tr[t]);
-    ti[t] = mma(a.hr, xil, ti[t]);
+    sr[t] = mma(a.hr, xrl, sr[t]);
+    si[t] = mma(a.hr, xil, si[t]);
     tr[t] = mma(a.nhi, xih, tr[t]);
     ti[t] = mma(a.hi, xrh, ti[t]);
-    tr[t] = mma(a.nhi, xil, tr[t]);
-    ti[t] = mma(a.hi, xrl, ti[t]);
+    sr[t] = mma(a.nhi, xil, sr[t]);
+    si[t] = mma(a.hi, xrl, si[t]);
     if constexpr (LO) {
-      tr[t] = mma(a.lr, xrh, tr[t]);
-      ti[t] = mma(a.lr, xih, ti[t]);
-      tr[t] = mma(a.nli, xih, tr[t]);
-      ti[t] = mma(a.li, xrh, ti[t]);
+      sr[t] = mma(a.lr, xrh, sr[t]);
+      si[t] = mma(a.lr, xih, si[t]);
+      sr[t] = mma(a.nli, xih, sr[t]);
+      si[t] = mma(a.li, xrh, si[t]);
     }
   }
 }
@@ -467,9 +473,9 @@ __device__ __forceinline__ void mfma_rows_bf16_wg(const uint32_t* __restrict__ A
   const int64_t nch = (p1 - p0 + 31) / 32;
   const int64_t row0 = mt * kBf16Tile + 16 * wave;
   const uint32_t* __restrict__ Arow = A + (k * g.Nd + min(row0 + col, g.Nd - 1)) * g.Nm * WPE;
-  f4v tr[NT], ti[NT];
+  f4v tr[NT], ti[NT], sr[NT], si[NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) tr[t] = ti[t] = (f4v){0, 0, 0, 0};
+  for (int t = 0; t < NT; ++t) tr[t] = ti[t] = sr[t] = si[t] = (f4v){0, 0, 0, 0};
   // chunk c uses ring slot c % RING for its block words and for its vector
   // stage; both are loaded RING chunks ahead, vector part first, so every
   // wait (in-order load counter) targets loads issued RING steps earlier.
@@ -493,7 +499,7 @@ __device__ __forceinline__ void mfma_rows_bf16_wg(const uint32_t* __restrict__ A
     stage_planes_load<NT, kBf16Threads>(Xs, g.nf, k, n8, b0, nb, ahead, aend, xv[d]);
     load_row_slots<LO, VEC>(Arow, ahead, kg, aend, r0[d], r1[d]);
     __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
-    rows_bf16_products<NT, LO>(a, sx + (c & 1) * BUF, kg, col, tr, ti);
+    rows_bf16_products<NT, LO>(a, sx + (c & 1) * BUF, kg, col, tr, ti, sr, si);
     __builtin_amdgcn_sched_barrier(0);  // the store waits for its loads: after the products
     stage_planes_store_rows<NT, LO, kBf16Threads>(xv[(d + 1) % RING], nb, base + 32, c + 1 < nch ? p1 : 0,
                                     sx + ((c + 1) & 1) * BUF);
@@ -515,7 +521,8 @@ __device__ __forceinline__ void mfma_rows_bf16_wg(const uint32_t* __restrict__ A
     for (int i = 0; i < 4; ++i) {
       const int64_t s = row0 + 4 * kg + i;
       if (s < g.Nd)
-        P[(((b0 + b) * g.n_pc + pc) * g.nf + k) * g.Nd + s] = {(double)tr[t][i], (double)ti[t][i]};
+        P[(((b0 + b) * g.n_pc + pc) * g.nf + k) * g.Nd + s] = {
+            (double)tr[t][i] + (double)sr[t][i], (double)ti[t][i] + (double)si[t][i]};
     }
   }
 }

@@ -58,3 +58,42 @@ def test_bf16_matrix_core_path_matches_oracle(shape, prec, tol):
             eA = rel_err(host(plan.FT(dev(d))), ref_A)
             print(f"  {name}: F {eF:.2e}  F* {eA:.2e}", flush=True)
             assert eF <= tol and eA <= tol
+
+
+def test_bf16_matrix_core_error_not_coherent_in_time():
+    """Regression: the bfloat16 matrix-core F path once carried an error that
+    added up coherently over the frequencies into the first output steps (a
+    rounding bias of small addends in a large float32 accumulator).  At
+    200 x 20000 x 420 with 16 right-hand sides its error at t = 0, measured
+    against the FP64 plan (itself checked against the oracle), must look
+    like the error elsewhere: mean signed error over all sensors and
+    right-hand sides small against its RMS."""
+    import p2o_synth as S
+    Nd, Nm, Nt, B = 200, 20000, 420, 16
+    stream = torch.cuda.current_stream()
+    env = torch.from_numpy(S.envelope(Nt, 80.0, 1.0 / np.sqrt(Nm))).cuda()
+    m = torch.empty((B, Nt, Nm), dtype=torch.float64, device="cuda")
+    S.device_normals(m.data_ptr(), m.numel(), 0, 8, S.ARRAY_M, 1.0, stream.cuda_stream)
+    ys = {}
+    for prec in ("fp64", "mixed_bf16"):
+        plan = P.Plan.begin(Nd, Nm, Nt, prec)
+        for p0 in range(0, Nm, 2048):
+            p1 = min(Nm, p0 + 2048)
+            chunk = torch.empty((Nt, Nd, p1 - p0), dtype=torch.float64, device="cuda")
+            S.device_blocks(chunk.data_ptr(), Nt, Nd, Nm, p0, p1, 8, env.data_ptr(),
+                            stream.cuda_stream)
+            plan.setup_columns(chunk, p0, p1)
+        plan.setup_end()
+        if prec != "fp64":
+            plan.set_mfma_threshold(P.OP_F, 1)
+        ys[prec] = host(plan.F(m))
+        plan.close()
+        torch.cuda.empty_cache()
+    ref = ys["fp64"]
+    sc = np.sqrt((ref ** 2).mean(axis=1, keepdims=True))
+    en = (ys["mixed_bf16"] - ref) / sc
+    for t in (0, 1, 3):
+        mean, rms = float(en[:, t, :].mean()), float(np.sqrt((en[:, t, :] ** 2).mean()))
+        print(f"\n  t={t}: mean signed {mean:.2e}  rms {rms:.2e}", flush=True)
+        assert abs(mean) <= 0.2 * rms
+    assert rel_err(ys["mixed_bf16"], ref) <= 1e-5
