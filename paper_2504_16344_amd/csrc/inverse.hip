@@ -193,18 +193,22 @@ potrf_trsm(double* __restrict__ K, int64_t n, int64_t j0, int bs, int64_t* __res
 }
 
 // ------------------------------------------------------ triangular solves
-// Y is [nrhs][n].  One kernel per 64-block and direction: every work-group
-// solves the diagonal block itself (L11 is 32 KB, an L2 hit after the first
-// work-group) and then applies that block's update to its own share of the
-// rest; work-group 0 stores the block's solution.  The block's right-hand
-// side is read from one buffer and its solution written to another, so no
-// work-group can see a block already solved by another:
+// Y is [nrhs][n].  The diagonal blocks L_jj (64 x 64, the last one ragged)
+// are inverted first, all in one launch, into two copies: column-major
+// (for L_jj^{-1} z) and row-major (for L_jj^{-T} x).  Then one kernel per
+// 64-block and direction: every work-group forms the block's solution as a
+// 64 x 64 matrix-vector product with the inverse (no serial substitution on
+// the sweep's critical path) and applies that block's update to its own
+// share of the rest; work-group 0 stores the block's solution.  The block's
+// right-hand side is read from one buffer and its solution written to
+// another, so no work-group can see a block already solved by another:
 //   forward  (L z = y): reads Y[:, blk], writes Z[:, blk], updates Y rows
 //            i >= j1 (y_i -= L[i, blk] z_blk);
 //   backward (L^T x = z): reads Z[:, blk], writes Y[:, blk], updates Z
 //            entries c < j0 (z_c -= L[blk, c]^T x_blk).
 constexpr int kFwdRows = 64;    // forward: rows updated per work-group
 constexpr int kBwdCols = 256;   // backward: entries updated per work-group
+constexpr int kQuarter = kNb / 4;  // inverse columns per wavefront in a product
 
 __device__ __forceinline__ double wave_total(double v) {
 #pragma unroll
@@ -212,33 +216,62 @@ __device__ __forceinline__ double wave_total(double v) {
   return v;
 }
 
-// L11 (lower, zero above the diagonal and outside bs) into LDS; 256
-// threads, coalesced rows, all loads issued first at clamped addresses.
-__device__ __forceinline__ void load_diag_block(const double* __restrict__ K, int64_t n,
-                                                int64_t j0, int bs, double (*l)[kNb + 1]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// One work-group (one wavefront) per diagonal block: lane c computes column
+// c of L_jj^{-1} by forward substitution, x_c = 1 / l_cc and
+// x_i = -(sum_{c <= k < i} l_ik x_k) / l_ii for i > c, with the column in
+// registers (static indices: the loops are unrolled) and L_jj in LDS.  The
+// block is padded to 64 with the identity so padded lanes stay finite;
+// entries outside bs x bs are stored as zeros.
+__global__ void __launch_bounds__(64)
+invert_diag_blocks(const double* __restrict__ K, int64_t n, double* __restrict__ Dcm,
+                   double* __restrict__ Drm) {
+  __shared__ double a[kNb][kNb + 1];
+  const int lane = threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.x * kNb;
+  const int bs = (int)min<int64_t>(kNb, n - j0);
   const int cl = min(lane, bs - 1);
-  double v[kNb / 4];
+#pragma unroll 16
+  for (int u = 0; u < kNb; ++u) {
+    const double v = K[(j0 + min(u, bs - 1)) * n + j0 + cl];
+    a[u][lane] = (u < bs && lane < bs) ? (lane <= u ? v : 0.0) : (lane == u ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  double x[kNb];
 #pragma unroll
-  for (int u = 0; u < kNb / 4; ++u) v[u] = K[(j0 + min(4 * u + wave, bs - 1)) * n + j0 + cl];
+  for (int i = 0; i < kNb; ++i) {
+    double s = 0.0;
 #pragma unroll
-  for (int u = 0; u < kNb / 4; ++u) {
-    const int row = 4 * u + wave;
-    l[row][lane] = (row < bs && lane <= row) ? v[u] : 0.0;
+    for (int k = 0; k < i; ++k) s += a[i][k] * x[k];
+    const double d = a[i][i];
+    x[i] = (i < lane) ? 0.0 : (i == lane ? 1.0 / d : -s / d);
+  }
+  __syncthreads();  // a is reused for the transpose
+#pragma unroll
+  for (int i = 0; i < kNb; ++i) a[i][lane] = (i < bs && lane < bs) ? x[i] : 0.0;
+  __syncthreads();
+  double* cm = Dcm + (int64_t)blockIdx.x * kNb * kNb;
+  double* rm = Drm + (int64_t)blockIdx.x * kNb * kNb;
+#pragma unroll 16
+  for (int u = 0; u < kNb; ++u) {
+    rm[u * kNb + lane] = a[u][lane];  // (u, lane): row-major
+    cm[u * kNb + lane] = a[lane][u];  // (lane, u): column-major
   }
 }
 
 // Both sweeps issue every global load of a right-hand side (the block's
-// entries, the entries they update) before the first barrier or before the
-// solve, and the diagonal's reciprocals are formed in parallel, so the
-// serial part is one multiply and one cross-lane broadcast per unknown.
+// entries, the entries they update) and the wavefront's quarter of the
+// inverse before the first barrier; the block's solution is the sum of four
+// wavefront partial products (lane = output entry).
 __global__ void __launch_bounds__(256)
-trsv_fwd_step(const double* __restrict__ K, double* __restrict__ Y, double* __restrict__ Z,
-              int64_t n, int64_t nrhs, int64_t j0, int bs) {
-  __shared__ double l[kNb][kNb + 1];
-  __shared__ double zb[kNb];
+trsv_fwd_step(const double* __restrict__ K, const double* __restrict__ Dcm,
+              double* __restrict__ Y, double* __restrict__ Z, int64_t n, int64_t nrhs,
+              int64_t j0, int bs) {
+  __shared__ double part[4][kNb];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  load_diag_block(K, n, j0, bs, l);
+  const double* M = Dcm + (j0 / kNb) * kNb * kNb;
+  double mv[kQuarter];  // mv[u] = (L_jj^{-1})[lane][wave kQuarter + u]
+#pragma unroll
+  for (int u = 0; u < kQuarter; ++u) mv[u] = M[(wave * kQuarter + u) * kNb + lane];
   const int64_t j1 = j0 + bs;
   const int64_t rbeg = j1 + (int64_t)blockIdx.x * kFwdRows;
   // this work-group's rows of the column panel, 16 a wavefront
@@ -250,23 +283,23 @@ trsv_fwd_step(const double* __restrict__ K, double* __restrict__ Y, double* __re
     lr[u] = K[i * n + j0 + min(lane, bs - 1)];
   }
   const int64_t my_row = min(rbeg + wave * kPer + min(lane, kPer - 1), n - 1);
-  const int bl = min(lane, bs - 1);
-  double yb = Y[j0 + bl], yo = Y[my_row];  // right-hand side 0
-  __syncthreads();
-  const double rl = 1.0 / l[bl][bl];
+  double yv[kQuarter];  // the block's right-hand side, this wavefront's quarter
+#pragma unroll
+  for (int u = 0; u < kQuarter; ++u) {
+    const int k = wave * kQuarter + u;
+    yv[u] = (k < bs) ? Y[j0 + k] : 0.0;
+  }
+  double yo = Y[my_row];  // right-hand side 0
   for (int64_t r = 0; r < nrhs; ++r) {
-    if (wave == 0) {  // lane c holds unknown c; at step c lane c finishes it
-      double v = (lane < bs) ? yb : 0.0;
-      for (int c = 0; c < bs; ++c) {
-        const double zc = __shfl(v * rl, c, 64);
-        if (lane == c) v = zc;
-        else if (lane > c) v -= l[lane][c] * zc;
-      }
-      zb[lane] = v;
-      if (blockIdx.x == 0 && lane < bs) Z[r * n + j0 + lane] = v;
-    }
+    double p = 0.0;
+#pragma unroll
+    for (int u = 0; u < kQuarter; ++u) p += mv[u] * yv[u];
+    part[wave][lane] = p;
     __syncthreads();
-    const double zl = (lane < bs) ? zb[lane] : 0.0;
+    // zero at lanes >= bs (the inverse's padding), so the clamped panel
+    // columns there add nothing
+    const double zl = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+    if (blockIdx.x == 0 && wave == 0 && lane < bs) Z[r * n + j0 + lane] = zl;
     double mine = 0.0;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
@@ -275,20 +308,28 @@ trsv_fwd_step(const double* __restrict__ K, double* __restrict__ Y, double* __re
     }
     if (lane < kPer && rbeg + wave * kPer + lane < n) Y[r * n + my_row] = yo - mine;
     if (r + 1 < nrhs) {
-      yb = Y[(r + 1) * n + j0 + bl];
+#pragma unroll
+      for (int u = 0; u < kQuarter; ++u) {
+        const int k = wave * kQuarter + u;
+        yv[u] = (k < bs) ? Y[(r + 1) * n + j0 + k] : 0.0;
+      }
       yo = Y[(r + 1) * n + my_row];
     }
-    __syncthreads();  // zb is rewritten for the next right-hand side
+    __syncthreads();  // part is rewritten for the next right-hand side
   }
 }
 
 __global__ void __launch_bounds__(256)
-trsv_bwd_step(const double* __restrict__ K, double* __restrict__ Y, double* __restrict__ Z,
-              int64_t n, int64_t nrhs, int64_t j0, int bs) {
-  __shared__ double l[kNb][kNb + 1];
+trsv_bwd_step(const double* __restrict__ K, const double* __restrict__ Drm,
+              double* __restrict__ Y, double* __restrict__ Z, int64_t n, int64_t nrhs,
+              int64_t j0, int bs) {
+  __shared__ double part[4][kNb];
   __shared__ double xb[kNb];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  load_diag_block(K, n, j0, bs, l);
+  const double* M = Drm + (j0 / kNb) * kNb * kNb;
+  double mv[kQuarter];  // mv[u] = (L_jj^{-T})[lane][wave kQuarter + u]
+#pragma unroll
+  for (int u = 0; u < kQuarter; ++u) mv[u] = M[(wave * kQuarter + u) * kNb + lane];
   // this work-group's entries c < j0: column c of the block's row panel
   const int64_t c = (int64_t)blockIdx.x * kBwdCols + threadIdx.x;
   const bool own = c < j0;
@@ -296,18 +337,21 @@ trsv_bwd_step(const double* __restrict__ K, double* __restrict__ Y, double* __re
   double lc[kNb];
 #pragma unroll
   for (int t = 0; t < kNb; ++t) lc[t] = K[(j0 + min(t, bs - 1)) * n + cc];
-  const int bl = min(lane, bs - 1);
-  double zv = Z[j0 + bl], zo = Z[cc];  // right-hand side 0
-  __syncthreads();
-  const double rl = 1.0 / l[bl][bl];
+  double zv[kQuarter];
+#pragma unroll
+  for (int u = 0; u < kQuarter; ++u) {
+    const int k = wave * kQuarter + u;
+    zv[u] = (k < bs) ? Z[j0 + k] : 0.0;
+  }
+  double zo = Z[cc];  // right-hand side 0
   for (int64_t r = 0; r < nrhs; ++r) {
-    if (wave == 0) {  // lane t holds unknown t; from the last one down
-      double v = (lane < bs) ? zv : 0.0;
-      for (int t = bs - 1; t >= 0; --t) {
-        const double xt = __shfl(v * rl, t, 64);
-        if (lane == t) v = xt;
-        else if (lane < t) v -= l[t][lane] * xt;
-      }
+    double p = 0.0;
+#pragma unroll
+    for (int u = 0; u < kQuarter; ++u) p += mv[u] * zv[u];
+    part[wave][lane] = p;
+    __syncthreads();
+    if (wave == 0) {
+      const double v = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
       xb[lane] = v;
       if (blockIdx.x == 0 && lane < bs) Y[r * n + j0 + lane] = v;
     }
@@ -317,10 +361,14 @@ trsv_bwd_step(const double* __restrict__ K, double* __restrict__ Y, double* __re
     for (int t = 0; t < kNb; ++t) acc += (t < bs ? lc[t] : 0.0) * xb[t];
     if (own) Z[r * n + c] = zo - acc;
     if (r + 1 < nrhs) {
-      zv = Z[(r + 1) * n + j0 + bl];
+#pragma unroll
+      for (int u = 0; u < kQuarter; ++u) {
+        const int k = wave * kQuarter + u;
+        zv[u] = (k < bs) ? Z[(r + 1) * n + j0 + k] : 0.0;
+      }
       zo = Z[(r + 1) * n + cc];
     }
-    __syncthreads();  // xb is rewritten for the next right-hand side
+    __syncthreads();  // part and xb are rewritten for the next right-hand side
   }
 }
 
@@ -454,26 +502,39 @@ hipError_t launch_cholesky(double* K, int64_t n, int64_t* info_dev, hipStream_t 
   return hipSuccess;
 }
 
-// In place: Y <- (L L^T)^{-1} Y; Z: scratch of nrhs * n doubles (the
-// forward solution).
-hipError_t launch_cholesky_solve(const double* K, double* Y, double* Z, int64_t n,
+// In place: Y <- (L L^T)^{-1} Y; scratch: cholesky_solve_scratch(n, nrhs)
+// bytes (the forward solution, then both copies of the inverted diagonal
+// blocks).
+namespace {
+int64_t solve_inverse_offset(int64_t n, int64_t nrhs) {  // doubles, 256-byte aligned
+  return (n * nrhs + 31) / 32 * 32;
+}
+}  // namespace
+
+hipError_t launch_cholesky_solve(const double* K, double* Y, double* scratch, int64_t n,
                                  int64_t nrhs, hipStream_t s) {
+  const int64_t nb = (n + kNb - 1) / kNb;
+  double* Z = scratch;
+  double* Dcm = scratch + solve_inverse_offset(n, nrhs);
+  double* Drm = Dcm + nb * kNb * kNb;
+  hipLaunchKernelGGL(invert_diag_blocks, dim3((unsigned)nb), dim3(64), 0, s, K, n, Dcm, Drm);
   for (int64_t j0 = 0; j0 < n; j0 += kNb) {
     const int bs = (int)std::min<int64_t>(kNb, n - j0);
     const int64_t m = n - j0 - bs;
     const unsigned g = (unsigned)std::max<int64_t>(1, (m + kFwdRows - 1) / kFwdRows);
-    hipLaunchKernelGGL(trsv_fwd_step, dim3(g), dim3(256), 0, s, K, Y, Z, n, nrhs, j0, bs);
+    hipLaunchKernelGGL(trsv_fwd_step, dim3(g), dim3(256), 0, s, K, Dcm, Y, Z, n, nrhs, j0, bs);
   }
   for (int64_t j0 = ((n - 1) / kNb) * kNb; j0 >= 0; j0 -= kNb) {
     const int bs = (int)std::min<int64_t>(kNb, n - j0);
     const unsigned g = (unsigned)std::max<int64_t>(1, (j0 + kBwdCols - 1) / kBwdCols);
-    hipLaunchKernelGGL(trsv_bwd_step, dim3(g), dim3(256), 0, s, K, Y, Z, n, nrhs, j0, bs);
+    hipLaunchKernelGGL(trsv_bwd_step, dim3(g), dim3(256), 0, s, K, Drm, Y, Z, n, nrhs, j0, bs);
   }
   return hipGetLastError();
 }
 
 size_t cholesky_solve_scratch(int64_t n, int64_t nrhs) {
-  return (size_t)n * nrhs * sizeof(double);
+  const int64_t nb = (n + kNb - 1) / kNb;
+  return (size_t)(solve_inverse_offset(n, nrhs) + 2 * nb * kNb * kNb) * sizeof(double);
 }
 
 hipError_t launch_copy_diagonal(const double* K, double* d, int64_t n, hipStream_t s) {
