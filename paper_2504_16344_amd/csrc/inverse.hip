@@ -196,7 +196,8 @@ potrf_trsm(double* __restrict__ K, int64_t n, int64_t j0, int bs, int64_t* __res
 // Y is [nrhs][n].  The diagonal blocks L_jj (64 x 64, the last one ragged)
 // are inverted first, all in one launch, into two copies: column-major
 // (for L_jj^{-1} z) and row-major (for L_jj^{-T} x).  Then one kernel per
-// 64-block and direction: every work-group forms the block's solution as a
+// 64-block and direction (two blocks per kernel in the forward sweep, see
+// trsv_fwd_pair): every work-group forms the block's solution as a
 // 64 x 64 matrix-vector product with the inverse (no serial substitution on
 // the sweep's critical path) and applies that block's update to its own
 // share of the rest; work-group 0 stores the block's solution.  The block's
@@ -316,6 +317,87 @@ trsv_fwd_step(const double* __restrict__ K, const double* __restrict__ Dcm,
       yo = Y[(r + 1) * n + my_row];
     }
     __syncthreads();  // part is rewritten for the next right-hand side
+  }
+}
+
+// Two blocks in one launch (half the launches of the forward sweep): block
+// A = [j0, j0 + 64), always full, and block C = [j0 + 64, j0 + 64 + bs2).
+// Every work-group forms z_A = L_AA^{-1} y_A, then y_C - L_CA z_A from the
+// first rows of A's column panel and z_C = L_CC^{-1} of it, and updates its
+// own rows below C with the columns of both blocks; work-group 0 stores z_A
+// and z_C.  Y rows of C are consumed here and not written back (nothing
+// reads them after this step).
+__global__ void __launch_bounds__(256)
+trsv_fwd_pair(const double* __restrict__ K, const double* __restrict__ Dcm,
+              double* __restrict__ Y, double* __restrict__ Z, int64_t n, int64_t nrhs,
+              int64_t j0, int bs2) {
+  __shared__ double part[4][kNb];
+  __shared__ double yc[kNb];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t jc = j0 + kNb;  // first row and column of block C
+  const double* MA = Dcm + (j0 / kNb) * kNb * kNb;
+  const double* MC = MA + kNb * kNb;
+  double ma[kQuarter], mc[kQuarter], lb[kQuarter];
+#pragma unroll
+  for (int u = 0; u < kQuarter; ++u) {
+    ma[u] = MA[(wave * kQuarter + u) * kNb + lane];
+    mc[u] = MC[(wave * kQuarter + u) * kNb + lane];
+    lb[u] = K[(jc + min(wave * kQuarter + u, bs2 - 1)) * n + j0 + lane];  // L_CA
+  }
+  const int64_t rbeg = jc + bs2 + (int64_t)blockIdx.x * kFwdRows;
+  constexpr int kPer = kFwdRows / 4;
+  double la[kPer], lc[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int64_t i = min(rbeg + wave * kPer + u, n - 1);
+    la[u] = K[i * n + j0 + lane];
+    lc[u] = K[i * n + jc + min(lane, bs2 - 1)];
+  }
+  const int64_t my_row = min(rbeg + wave * kPer + min(lane, kPer - 1), n - 1);
+  const int crow = wave * kQuarter + min(lane, kQuarter - 1);  // lanes < 16: a row of C
+  double yv[kQuarter];
+#pragma unroll
+  for (int u = 0; u < kQuarter; ++u) yv[u] = Y[j0 + wave * kQuarter + u];
+  double ycv = (crow < bs2) ? Y[jc + crow] : 0.0;
+  double yo = Y[my_row];  // right-hand side 0
+  for (int64_t r = 0; r < nrhs; ++r) {
+    double p = 0.0;
+#pragma unroll
+    for (int u = 0; u < kQuarter; ++u) p += ma[u] * yv[u];
+    part[wave][lane] = p;
+    __syncthreads();
+    const double za = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+    if (blockIdx.x == 0 && wave == 0) Z[r * n + j0 + lane] = za;
+    double mine = 0.0;
+#pragma unroll
+    for (int u = 0; u < kQuarter; ++u) {
+      const double s = wave_total(lb[u] * za);
+      if (lane == u) mine = s;
+    }
+    if (lane < kQuarter) yc[crow] = (crow < bs2) ? ycv - mine : 0.0;
+    __syncthreads();  // yc complete; every read of part above is done
+    p = 0.0;
+#pragma unroll
+    for (int u = 0; u < kQuarter; ++u) p += mc[u] * yc[wave * kQuarter + u];
+    part[wave][lane] = p;
+    __syncthreads();
+    // zero at lanes >= bs2 (the inverse's padding)
+    const double zc = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+    if (blockIdx.x == 0 && wave == 0 && lane < bs2) Z[r * n + jc + lane] = zc;
+    mine = 0.0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const double s = wave_total(la[u] * za + lc[u] * zc);
+      if (lane == u) mine = s;
+    }
+    if (lane < kPer && rbeg + wave * kPer + lane < n) Y[r * n + my_row] = yo - mine;
+    if (r + 1 < nrhs) {
+#pragma unroll
+      for (int u = 0; u < kQuarter; ++u) yv[u] = Y[(r + 1) * n + j0 + wave * kQuarter + u];
+      ycv = (crow < bs2) ? Y[(r + 1) * n + jc + crow] : 0.0;
+      yo = Y[(r + 1) * n + my_row];
+    }
+    __syncthreads();  // part and yc are rewritten for the next right-hand side
   }
 }
 
@@ -518,11 +600,20 @@ hipError_t launch_cholesky_solve(const double* K, double* Y, double* scratch, in
   double* Dcm = scratch + solve_inverse_offset(n, nrhs);
   double* Drm = Dcm + nb * kNb * kNb;
   hipLaunchKernelGGL(invert_diag_blocks, dim3((unsigned)nb), dim3(64), 0, s, K, n, Dcm, Drm);
-  for (int64_t j0 = 0; j0 < n; j0 += kNb) {
-    const int bs = (int)std::min<int64_t>(kNb, n - j0);
-    const int64_t m = n - j0 - bs;
-    const unsigned g = (unsigned)std::max<int64_t>(1, (m + kFwdRows - 1) / kFwdRows);
-    hipLaunchKernelGGL(trsv_fwd_step, dim3(g), dim3(256), 0, s, K, Dcm, Y, Z, n, nrhs, j0, bs);
+  for (int64_t j0 = 0; j0 < n;) {
+    const int64_t rest = n - j0;
+    if (rest > kNb) {  // a full block and the next one
+      const int bs2 = (int)std::min<int64_t>(kNb, rest - kNb);
+      const int64_t m = rest - kNb - bs2;
+      const unsigned g = (unsigned)std::max<int64_t>(1, (m + kFwdRows - 1) / kFwdRows);
+      hipLaunchKernelGGL(trsv_fwd_pair, dim3(g), dim3(256), 0, s, K, Dcm, Y, Z, n, nrhs, j0,
+                         bs2);
+      j0 += kNb + bs2;
+    } else {
+      hipLaunchKernelGGL(trsv_fwd_step, dim3(1), dim3(256), 0, s, K, Dcm, Y, Z, n, nrhs, j0,
+                         (int)rest);
+      j0 = n;
+    }
   }
   for (int64_t j0 = ((n - 1) / kNb) * kNb; j0 >= 0; j0 -= kNb) {
     const int bs = (int)std::min<int64_t>(kNb, n - j0);
