@@ -720,10 +720,10 @@ struct DevBufs {
 // Solves with K's Cholesky factor: the per-right-hand-side kernels for a
 // few right-hand sides, the blocked matrix-core variant for many.
 constexpr int64_t kSolveManyFrom = 16;
-hipError_t cholesky_solve(const double* K, double* Y, double* part, int64_t n, int64_t nrhs,
+hipError_t cholesky_solve(const double* K, double* Y, double* scratch, int64_t n, int64_t nrhs,
                           hipStream_t s) {
   if (nrhs >= kSolveManyFrom) return launch_cholesky_solve_many(K, Y, n, nrhs, s);
-  return launch_cholesky_solve(K, Y, part, n, nrhs, s);
+  return launch_cholesky_solve(K, Y, scratch, n, nrhs, s);
 }
 
 bool same_time_grid(const p2o_plan_s* a, const p2o_plan_s* b) {

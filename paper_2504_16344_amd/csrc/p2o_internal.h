@@ -187,7 +187,10 @@ hipError_t launch_add_diagonal(double* K, const double* v, int64_t n, hipStream_
 hipError_t launch_symmetrize(double* K, int64_t n, hipStream_t s);    // (K + K^T) / 2
 hipError_t launch_mirror_lower(double* K, int64_t n, hipStream_t s);  // upper <- lower
 hipError_t launch_cholesky(double* K, int64_t n, int64_t* info_dev, hipStream_t s);
-hipError_t launch_cholesky_solve(const double* K, double* Y, double* part, int64_t n,
+// Y[nrhs][n] <- K^{-1} Y with K's Cholesky factor in the lower triangle of K;
+// scratch: cholesky_solve_scratch(n, nrhs) bytes of device memory (the
+// forward solution and the inverted 64 x 64 diagonal blocks, two layouts).
+hipError_t launch_cholesky_solve(const double* K, double* Y, double* scratch, int64_t n,
                                  int64_t nrhs, hipStream_t s);
 size_t cholesky_solve_scratch(int64_t n, int64_t nrhs);
 hipError_t launch_copy_diagonal(const double* K, double* d, int64_t n, hipStream_t s);
