@@ -104,11 +104,14 @@ def test_inversion_needs_fp64_plan():
 
 
 @pytest.mark.parametrize("shape,nrhs", [((3, 40, 7), 1), ((5, 300, 29), 3), ((5, 300, 29), 20),
-                                        ((20, 300, 55), 2)])
+                                        ((20, 300, 55), 2), ((5, 60, 13), 2), ((4, 60, 32), 1)])
 def test_posterior_mean_from_factor(shape, nrhs):
     """Phase 4 online: m = Gp F* K^{-1} d from the factor left by posterior()
     (single- and many-right-hand-side sweeps), against the oracle; K is not
-    modified by the call."""
+    modified by the call.  n = Nt Nd covers one ragged block (21), the
+    forward sweep's block pairs with and without a ragged second block and
+    a single last block (145, 1100), a pair whose second block is one row
+    (65) and a pair with no rows below it (128)."""
     Nd, Nm, Nt = shape
     print(f"\n[inverse] online shape={shape} nrhs={nrhs}", flush=True)
     blocks, _, _ = workload(9, Nd, Nm, Nt, tau=Nt / 3)
