@@ -64,20 +64,36 @@ typedef enum {
   P2O_FADJ = 1   /* y = F* x: x data vector,      y parameter vector  */
 } p2o_op;
 
+/* Precision tiers.  The mixed tiers store every real component v of a
+ * frequency-block entry as 16-bit terms with one power-of-two float32 scale
+ * s = 2^e per (frequency k, 256 consecutive columns) sub-block, over all
+ * sensors:
+ *   e     from the sub-block's largest component magnitude M, M in
+ *         [2^(E-1), 2^E): e = E for bfloat16 (so |v/s| < 1), e = E - 15 for
+ *         binary16 (|v/s| < 2^15); clamped to [-120, 120]; E = 0 for an
+ *         all-zero sub-block;
+ *   hi    = r16(v / s),  lo = r16((v / s - hi) / c),  value = s (hi + c lo),
+ *         c = 1 (bfloat16) or 2^-11 (binary16), r16 rounding to nearest
+ *         even first to float32, then to the 16-bit format;
+ * so the stored value differs from v by about 2^-16 |v| (bfloat16) or
+ * 2^-22 |v| (binary16).  Transforms run in float32 and block products
+ * accumulate in float32; F's column-chunk partial sums are combined in
+ * float64, F*'s products (a sum over sensors) are float32 throughout.  8
+ * bytes per complex block entry (4 for the hi-only tier). */
 typedef enum {
   /* Frequency blocks stored as complex float64, transforms and block
-   * products in float64. */
+   * products in float64 (16 bytes per complex block entry). */
   P2O_FP64 = 0,
-  /* Frequency blocks stored as two 16-bit terms per real component,
-   * v ~= s * (hi + lo * 2^-11) in IEEE binary16, with one power-of-two float32
-   * scale s per (frequency, 256-column tile) sub-block; transforms in
-   * float32, block products accumulated in float32, partial sums combined in
-   * float64.  8 bytes per complex block entry. */
-  P2O_MIXED_FP16 = 1,
-  /* As P2O_MIXED_FP16 with bfloat16 terms, v ~= s * (hi + lo). */
-  P2O_MIXED_BF16 = 2,
-  /* bfloat16 hi term only (4 bytes per complex entry); error ~1e-3. */
-  P2O_FAST_BF16 = 3
+  /* bfloat16 hi + lo terms (the default mixed tier). */
+  P2O_MIXED = 1,
+  /* bfloat16 hi term only: half the block bytes, error ~1e-3 (stated, not
+   * within 1e-5). */
+  P2O_FAST = 2,
+  /* binary16 hi + lo terms (error ~1e-7; vector units only). */
+  P2O_MIXED_FP16 = 3,
+  /* Names that spell out the 16-bit format of the two bfloat16 tiers. */
+  P2O_MIXED_BF16 = P2O_MIXED,
+  P2O_FAST_BF16 = P2O_FAST
 } p2o_prec;
 
 /* ---------------------------------------------------------------- setup */
@@ -189,7 +205,11 @@ p2o_status p2o_batch_apply(p2o_batch b, p2o_op op, const double* const* x,
 /* Capture one batched apply on fixed buffers into a HIP graph (workspaces
  * are reserved before capture; the graph holds no allocation or memset).
  * p2o_graph_launch replays it on `stream`; replays read x and write y at
- * the captured addresses. */
+ * the captured addresses.  p2o_batch_capture is the same call under its
+ * earlier name. */
+p2o_status p2o_graph_capture(p2o_batch b, p2o_op op, const double* const* x,
+                             double* const* y, const int64_t* nrhs, void* stream,
+                             p2o_graph* out);
 p2o_status p2o_batch_capture(p2o_batch b, p2o_op op, const double* const* x,
                              double* const* y, const int64_t* nrhs, void* stream,
                              p2o_graph* out);

@@ -15,15 +15,17 @@ import torch
 
 __all__ = [
     "Plan", "Batch", "Graph", "P2OError", "P2OApply", "P2OAdjoint", "load_library", "LIB_PATH",
-    "FP64", "MIXED_FP16", "MIXED_BF16", "FAST_BF16", "OP_F", "OP_FADJ",
+    "FP64", "MIXED", "FAST", "MIXED_FP16", "MIXED_BF16", "FAST_BF16", "OP_F", "OP_FADJ",
     "smooth_length", "EXPORTED_SYMBOLS", "qoi_predict",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libp2o.so")
 
-FP64, MIXED_FP16, MIXED_BF16, FAST_BF16 = 0, 1, 2, 3
-PREC_BY_NAME = {"fp64": FP64, "mixed_fp16": MIXED_FP16, "mixed_bf16": MIXED_BF16,
-                "fast_bf16": FAST_BF16}
+# p2o_prec: P2O_MIXED is the bfloat16 hi+lo tier, P2O_FAST the bfloat16 hi-only one
+FP64, MIXED, FAST, MIXED_FP16 = 0, 1, 2, 3
+MIXED_BF16, FAST_BF16 = MIXED, FAST
+PREC_BY_NAME = {"fp64": FP64, "mixed": MIXED, "fast": FAST, "mixed_bf16": MIXED_BF16,
+                "fast_bf16": FAST_BF16, "mixed_fp16": MIXED_FP16}
 OP_F, OP_FADJ = 0, 1
 ASSEMBLY = {"matvec": 0, "gram": 1}  # p2o_assembly
 
@@ -68,6 +70,8 @@ _SIGNATURES = {
     "p2o_kernel_time": (_int, [_vp, _int, _c.POINTER(_dbl), _c.POINTER(_i64)]),
     "p2o_batch_create": (_int, [_c.POINTER(_vp), _i64, _c.POINTER(_vp)]),
     "p2o_batch_apply": (_int, [_vp, _int, _c.POINTER(_vp), _c.POINTER(_vp), _c.POINTER(_i64), _vp]),
+    "p2o_graph_capture": (_int, [_vp, _int, _c.POINTER(_vp), _c.POINTER(_vp), _c.POINTER(_i64),
+                                 _vp, _c.POINTER(_vp)]),
     "p2o_batch_capture": (_int, [_vp, _int, _c.POINTER(_vp), _c.POINTER(_vp), _c.POINTER(_i64),
                                  _vp, _c.POINTER(_vp)]),
     "p2o_graph_launch": (_int, [_vp, _vp]),
@@ -443,7 +447,7 @@ class Batch:
         """Graph of one batched apply reading xs and writing ys (fixed buffers)."""
         outs, xp, yp, nr = self._args(op, xs, ys)
         g = _vp()
-        _check("p2o_batch_capture", self._lib.p2o_batch_capture(self._h, op, xp, yp, nr,
+        _check("p2o_graph_capture", self._lib.p2o_graph_capture(self._h, op, xp, yp, nr,
                                                                 _stream_handle(stream), _c.byref(g)))
         return Graph(self._lib, g)
 

@@ -42,7 +42,7 @@ p2o_status hip_fail(hipError_t e) {
     if (s_ != P2O_OK) return s_;         \
   } while (0)
 
-bool valid_prec(int p) { return p >= P2O_FP64 && p <= P2O_FAST_BF16; }
+bool valid_prec(int p) { return p >= P2O_FP64 && p <= P2O_MIXED_FP16; }
 bool is_mixed(p2o_prec p) { return p != P2O_FP64; }
 int64_t entry_bytes(p2o_prec p) {
   switch (p) {
@@ -1132,7 +1132,7 @@ p2o_status p2o_batch_apply(p2o_batch b, p2o_op op, const double* const* x, doubl
   return batch_enqueue(b, op, x, y, nrhs, table, b->dev, total, s);
 }
 
-p2o_status p2o_batch_capture(p2o_batch b, p2o_op op, const double* const* x, double* const* y,
+p2o_status p2o_graph_capture(p2o_batch b, p2o_op op, const double* const* x, double* const* y,
                              const int64_t* nrhs, void* stream, p2o_graph* out) {
   if (!out) return P2O_EINVAL;
   *out = nullptr;
@@ -1166,6 +1166,11 @@ p2o_status p2o_batch_capture(p2o_batch b, p2o_op op, const double* const* x, dou
   }
   *out = g;
   return P2O_OK;
+}
+
+p2o_status p2o_batch_capture(p2o_batch b, p2o_op op, const double* const* x, double* const* y,
+                             const int64_t* nrhs, void* stream, p2o_graph* out) {
+  return p2o_graph_capture(b, op, x, y, nrhs, stream, out);
 }
 
 p2o_status p2o_graph_launch(p2o_graph g, void* stream) {

@@ -49,6 +49,7 @@ def test_setup_rejects_bad_arguments_on_host(lib):
     assert h.value is None
     assert lib.p2o_setup_begin(5, 5, 0, 0, None, ctypes.byref(h)) == 1
     assert lib.p2o_setup_begin(5, 5, 5, 7, None, ctypes.byref(h)) == 1
+    assert lib.p2o_setup_begin(5, 5, 5, 4, None, ctypes.byref(h)) == 1
     assert lib.p2o_setup_begin(5, 5, 5, 0, None, None) == 1
     assert lib.p2o_setup(None, 5, 5, 5, 0, None, ctypes.byref(h)) == 1
     # null handles
@@ -74,3 +75,23 @@ def test_synth_device_library_exports():
         build_library()
     lib = p2o_synth.load_device_library()
     assert hasattr(lib, "synth_blocks_f64") and hasattr(lib, "synth_normals_f64")
+
+
+def test_boundary_names_and_precision_values():
+    """The boundary's names: p2o_setup (+ chunked), p2o_apply,
+    p2o_hessian_assemble, p2o_posterior_solve, the batch and graph calls, and
+    the precision tiers P2O_FP64 = 0, P2O_MIXED = 1 (bfloat16 hi+lo),
+    P2O_FAST = 2 (bfloat16 hi only), plus the extra P2O_MIXED_FP16 = 3."""
+    names = set(header_symbols())
+    for name in ("p2o_setup", "p2o_setup_begin", "p2o_setup_columns", "p2o_setup_end",
+                 "p2o_apply", "p2o_hessian_assemble", "p2o_posterior_solve",
+                 "p2o_batch_create", "p2o_batch_apply", "p2o_graph_capture",
+                 "p2o_graph_launch", "p2o_destroy", "p2o_status_string", "p2o_last_hip_error"):
+        assert name in names, name
+    text = open(os.path.join(ROOT, "include", "p2o.h")).read()
+    vals = dict(re.findall(r"\b(P2O_[A-Z0-9_]+)\s*=\s*([A-Z0-9_]+)", text))
+    assert vals["P2O_FP64"] == "0" and vals["P2O_MIXED"] == "1" and vals["P2O_FAST"] == "2"
+    assert vals["P2O_MIXED_FP16"] == "3"
+    assert vals["P2O_MIXED_BF16"] == "P2O_MIXED" and vals["P2O_FAST_BF16"] == "P2O_FAST"
+    assert (P.FP64, P.MIXED, P.FAST, P.MIXED_FP16) == (0, 1, 2, 3)
+    assert P.PREC_BY_NAME["mixed_bf16"] == P.MIXED and P.PREC_BY_NAME["fast_bf16"] == P.FAST

@@ -10,7 +10,7 @@ import torch
 
 import oracle
 import paper_2504_16344_amd as P
-from gpu_helpers import dev, host, rel_err, workload
+from gpu_helpers import check_close, dev, host, workload
 
 pytestmark = pytest.mark.gpu
 
@@ -41,9 +41,8 @@ def test_batch_matches_single_plans_and_oracle(prec):
         for (blocks, m, d), p, x, y in zip(cases, plans, xs, ys):
             single = p.apply(op, x)
             ref = oracle.apply_F(blocks, m) if op == P.OP_F else oracle.apply_Fadj(blocks, d)
-            e = rel_err(host(y), ref)
             assert torch.equal(y, single), (p.Nd, p.Nm, p.Nt)
-            assert e <= TOL[prec], (p.Nd, p.Nm, p.Nt, e)
+            check_close(host(y), ref, TOL[prec], f"op={op} {p.Nd}x{p.Nm}x{p.Nt}")
         print(f"  op={op}: {len(plans)} instances equal to single applies", flush=True)
     batch.close()
     for p in plans:

@@ -8,7 +8,7 @@ import torch
 
 import oracle
 import paper_2504_16344_amd as P
-from gpu_helpers import dev, host, rel_err, workload
+from gpu_helpers import check_close, dev, host, rel_err, workload
 
 pytestmark = pytest.mark.gpu
 
@@ -30,9 +30,8 @@ def test_mfma_and_vector_paths_match_oracle(shape):
             plan.set_mfma_threshold(P.OP_FADJ, thr)
             yF = host(plan.F(dev(m)))
             yA = host(plan.FT(dev(d)))
-            eF, eA = rel_err(yF, ref_F), rel_err(yA, ref_A)
-            print(f"  {name}: F {eF:.2e}  F* {eA:.2e}", flush=True)
-            assert eF <= 1e-10 and eA <= 1e-10
+            check_close(yF, ref_F, 1e-10, f"{name} F")
+            check_close(yA, ref_A, 1e-10, f"{name} F*")
             out[name] = (yF, yA)
     assert rel_err(out["mfma"][0], out["vector"][0]) <= 1e-13
 
@@ -54,39 +53,45 @@ def test_bf16_matrix_core_path_matches_oracle(shape, prec, tol):
         for name, thr in (("mfma", 1), ("vector", 0)):
             plan.set_mfma_threshold(P.OP_F, thr)
             plan.set_mfma_threshold(P.OP_FADJ, thr)
-            eF = rel_err(host(plan.F(dev(m))), ref_F)
-            eA = rel_err(host(plan.FT(dev(d))), ref_A)
-            print(f"  {name}: F {eF:.2e}  F* {eA:.2e}", flush=True)
-            assert eF <= tol and eA <= tol
+            check_close(host(plan.F(dev(m))), ref_F, tol, f"{name} F")
+            check_close(host(plan.FT(dev(d))), ref_A, tol, f"{name} F*")
 
 
-def test_bf16_matrix_core_error_not_coherent_in_time():
+@pytest.mark.parametrize("op", ["F", "FADJ"])
+def test_bf16_matrix_core_error_not_coherent_in_time(op):
     """Regression: the bfloat16 matrix-core F path once carried an error that
     added up coherently over the frequencies into the first output steps (a
-    rounding bias of small addends in a large float32 accumulator).  At
-    200 x 20000 x 420 with 16 right-hand sides its error at t = 0, measured
-    against the FP64 plan (itself checked against the oracle), must look
-    like the error elsewhere: mean signed error over all sensors and
-    right-hand sides small against its RMS."""
+    rounding bias of small addends in a large float32 accumulator).  Its
+    error at t = 0, 1, 3, measured against the FP64 plan (itself checked
+    against the oracle), must look like the error elsewhere: mean signed
+    error over all outputs and right-hand sides small against its RMS.
+    F: 200 x 20000 x 420, 16 right-hand sides (contraction over 4096-column
+    chunks).  F*: 2048 sensors, so the contraction over sensors is as long as
+    an F chunk's (64 steps of 32), at 2048 x 2000 x 420."""
     import p2o_synth as S
-    Nd, Nm, Nt, B = 200, 20000, 420, 16
+    Nd, Nm = (200, 20000) if op == "F" else (2048, 2000)
+    Nt, B, seed = 420, 16, 8
+    code = P.OP_F if op == "F" else P.OP_FADJ
     stream = torch.cuda.current_stream()
     env = torch.from_numpy(S.envelope(Nt, 80.0, 1.0 / np.sqrt(Nm))).cuda()
-    m = torch.empty((B, Nt, Nm), dtype=torch.float64, device="cuda")
-    S.device_normals(m.data_ptr(), m.numel(), 0, 8, S.ARRAY_M, 1.0, stream.cuda_stream)
+    n_in = Nm if op == "F" else Nd
+    x = torch.empty((B, Nt, n_in), dtype=torch.float64, device="cuda")
+    S.device_normals(x.data_ptr(), x.numel(), 0, seed, S.ARRAY_M if op == "F" else S.ARRAY_D,
+                     1.0, stream.cuda_stream)
     ys = {}
     for prec in ("fp64", "mixed_bf16"):
         plan = P.Plan.begin(Nd, Nm, Nt, prec)
         for p0 in range(0, Nm, 2048):
             p1 = min(Nm, p0 + 2048)
             chunk = torch.empty((Nt, Nd, p1 - p0), dtype=torch.float64, device="cuda")
-            S.device_blocks(chunk.data_ptr(), Nt, Nd, Nm, p0, p1, 8, env.data_ptr(),
+            S.device_blocks(chunk.data_ptr(), Nt, Nd, Nm, p0, p1, seed, env.data_ptr(),
                             stream.cuda_stream)
             plan.setup_columns(chunk, p0, p1)
+            del chunk
         plan.setup_end()
         if prec != "fp64":
-            plan.set_mfma_threshold(P.OP_F, 1)
-        ys[prec] = host(plan.F(m))
+            plan.set_mfma_threshold(code, 1)
+        ys[prec] = host(plan.apply(code, x))
         plan.close()
         torch.cuda.empty_cache()
     ref = ys["fp64"]
@@ -94,6 +99,6 @@ def test_bf16_matrix_core_error_not_coherent_in_time():
     en = (ys["mixed_bf16"] - ref) / sc
     for t in (0, 1, 3):
         mean, rms = float(en[:, t, :].mean()), float(np.sqrt((en[:, t, :] ** 2).mean()))
-        print(f"\n  t={t}: mean signed {mean:.2e}  rms {rms:.2e}", flush=True)
+        print(f"\n  {op} t={t}: mean signed {mean:.2e}  rms {rms:.2e}", flush=True)
         assert abs(mean) <= 0.2 * rms
     assert rel_err(ys["mixed_bf16"], ref) <= 1e-5

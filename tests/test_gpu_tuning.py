@@ -10,7 +10,7 @@ import torch
 
 import oracle
 import paper_2504_16344_amd as P
-from gpu_helpers import dev, host, rel_err, workload
+from gpu_helpers import check_close, dev, host, rel_err, workload
 
 pytestmark = pytest.mark.gpu
 
@@ -38,9 +38,7 @@ def test_every_candidate_matches_oracle(shape, prec):
                     assert e.status == 6  # vector width does not divide Nm
                     continue
                 y = host(plan.apply(op, x[op]))
-                err = rel_err(y, ref[op])
-                print(f"  op={op} cfg={c} rel err {err:.2e}", flush=True)
-                assert err <= TOL[prec], (op, c, err)
+                check_close(y, ref[op], TOL[prec], f"op={op} cfg={c}")
                 ran += 1
             assert ran >= 1
 
