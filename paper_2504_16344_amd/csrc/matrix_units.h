@@ -425,9 +425,14 @@ __device__ __forceinline__ void rows_bf16_products(const BlockOps& a, const u4v*
 }
 
 // F* chunk: x[b] += conj(f) d[b]: re = dr fr + di fi, im = di fr - dr fi.
+// As in the F chunk, the hi x hi products go to xr / xi and the hi x lo and
+// lo x hi products to their own accumulators sr / si (the matrix cores'
+// biased rounding of small addends would otherwise add up over the sensor
+// contraction; F* contractions are as long as N_d).
 template <int MT, bool LO>
 __device__ __forceinline__ void cols_bf16_products(const BlockOps& f, const u4v* ds, int kg,
-                                                   int col, f4v (&xr)[MT], f4v (&xi)[MT]) {
+                                                   int col, f4v (&xr)[MT], f4v (&xi)[MT],
+                                                   f4v (&sr)[MT], f4v (&si)[MT]) {
   constexpr int PP = MT * 16 + 1;
 #pragma unroll
   for (int t = 0; t < MT; ++t) {
@@ -436,17 +441,17 @@ __device__ __forceinline__ void cols_bf16_products(const BlockOps& f, const u4v*
     const u4v dih = ds[(2 * 4 + kg) * PP + b], dil = ds[(3 * 4 + kg) * PP + b];
     xr[t] = mma(drh, f.hr, xr[t]);
     xi[t] = mma(dih, f.hr, xi[t]);
-    xr[t] = mma(drl, f.hr, xr[t]);
-    xi[t] = mma(dil, f.hr, xi[t]);
+    sr[t] = mma(drl, f.hr, sr[t]);
+    si[t] = mma(dil, f.hr, si[t]);
     xr[t] = mma(dih, f.hi, xr[t]);
     xi[t] = mma(drh, f.nhi, xi[t]);
-    xr[t] = mma(dil, f.hi, xr[t]);
-    xi[t] = mma(drl, f.nhi, xi[t]);
+    sr[t] = mma(dil, f.hi, sr[t]);
+    si[t] = mma(drl, f.nhi, si[t]);
     if constexpr (LO) {
-      xr[t] = mma(drh, f.lr, xr[t]);
-      xi[t] = mma(dih, f.lr, xi[t]);
-      xr[t] = mma(dih, f.li, xr[t]);
-      xi[t] = mma(drh, f.nli, xi[t]);
+      sr[t] = mma(drh, f.lr, sr[t]);
+      si[t] = mma(dih, f.lr, si[t]);
+      sr[t] = mma(dih, f.li, sr[t]);
+      si[t] = mma(drh, f.nli, si[t]);
     }
   }
 }
@@ -544,9 +549,9 @@ __device__ __forceinline__ void mfma_cols_bf16_wg(const uint32_t* __restrict__ A
   const int64_t nch = (g.Nd + 31) / 32;
   const int64_t col0 = pt * kBf16Tile + 16 * wave;
   const uint32_t* __restrict__ Ak = A + (k * g.Nd * g.Nm + min(col0 + col, g.Nm - 1)) * WPE;
-  f4v xr[MT], xi[MT];
+  f4v xr[MT], xi[MT], sr[MT], si[MT];
 #pragma unroll
-  for (int t = 0; t < MT; ++t) xr[t] = xi[t] = (f4v){0, 0, 0, 0};
+  for (int t = 0; t < MT; ++t) xr[t] = xi[t] = sr[t] = si[t] = (f4v){0, 0, 0, 0};
   // ring and loop structure as in the F unit
   uint32_t r0[RING][8], r1[RING][8];
   constexpr int PER = parts_per_thread<MT, kBf16Threads>();
@@ -566,7 +571,7 @@ __device__ __forceinline__ void mfma_cols_bf16_wg(const uint32_t* __restrict__ A
     stage_planes_load<MT, kBf16Threads>(Ds, g.nf, k, nd8, b0, nb, ahead, aend, dv[d]);
     load_col8<LO>(Ak, ahead + 8 * kg, aend, g.Nm, r0[d], r1[d]);
     __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
-    cols_bf16_products<MT, LO>(f, sd + (c & 1) * BUF, kg, col, xr, xi);
+    cols_bf16_products<MT, LO>(f, sd + (c & 1) * BUF, kg, col, xr, xi, sr, si);
     __builtin_amdgcn_sched_barrier(0);  // the store waits for its loads: after the products
     stage_planes_store_cols<MT, kBf16Threads>(dv[(d + 1) % RING], nb, base + 32, c + 1 < nch ? g.Nd : 0,
                                 sd + ((c + 1) & 1) * BUF);
@@ -589,7 +594,10 @@ __device__ __forceinline__ void mfma_cols_bf16_wg(const uint32_t* __restrict__ A
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int b = t * 16 + 4 * kg + i;
-      if (b < nb) Y[((b0 + b) * g.nf + k) * g.Nm + p] = {xr[t][i] * sc, xi[t][i] * sc};
+      if (b < nb)  // the two parts added in float64, scaled (a power of two), rounded once
+        Y[((b0 + b) * g.nf + k) * g.Nm + p] = {
+            (float)(((double)xr[t][i] + (double)sr[t][i]) * sc),
+            (float)(((double)xi[t][i] + (double)si[t][i]) * sc)};
     }
 }
 

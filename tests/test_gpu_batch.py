@@ -10,11 +10,11 @@ import torch
 
 import oracle
 import paper_2504_16344_amd as P
-from gpu_helpers import check_close, dev, host, workload
+from gpu_helpers import TOL_VS_FP64, check_close, check_tier, dev, host, workload
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-10, "mixed_fp16": 1e-5, "mixed_bf16": 1e-5, "fast_bf16": 2e-2}
+TOL = TOL_VS_FP64
 # (Nd, Nm, Nt, nrhs): uneven shapes, odd and even Nm, 1..70 right-hand sides
 INSTANCES = [(1, 1, 5, 1), (37, 300, 13, 5), (130, 1028, 33, 70), (17, 1001, 21, 20),
              (64, 777, 40, 3), (5, 4100, 8, 17), (9, 512, 1, 9)]
@@ -42,7 +42,7 @@ def test_batch_matches_single_plans_and_oracle(prec):
             single = p.apply(op, x)
             ref = oracle.apply_F(blocks, m) if op == P.OP_F else oracle.apply_Fadj(blocks, d)
             assert torch.equal(y, single), (p.Nd, p.Nm, p.Nt)
-            check_close(host(y), ref, TOL[prec], f"op={op} {p.Nd}x{p.Nm}x{p.Nt}")
+            check_tier(host(y), ref, prec, f"op={op} {p.Nd}x{p.Nm}x{p.Nt}")
         print(f"  op={op}: {len(plans)} instances equal to single applies", flush=True)
     batch.close()
     for p in plans:
