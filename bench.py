@@ -554,6 +554,24 @@ def bench_inversion(torch, S, P):
     torch.cuda.synchronize()
     t_on = ev[0].elapsed_time(ev[1]) / 5 * 1e-3
     e_on = (torch.linalg.norm(m_on - m) / torch.linalg.norm(m)).item()
+    # Phase 4 online from K^{-1} (formed offline from the factor): one pass
+    # over K^{-1} and one F*
+    Kinv = torch.empty_like(K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.posterior_invert(K, out=Kinv)
+    torch.cuda.synchronize()
+    t_inv = time.perf_counter() - t0
+    m_ki = plan.posterior_mean_kinv(Kinv, d_obs, 0.25)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(20):
+        plan.posterior_mean_kinv(Kinv, d_obs, 0.25, out=m_ki)
+    ev[1].record()
+    torch.cuda.synchronize()
+    t_ki = ev[0].elapsed_time(ev[1]) / 20 * 1e-3
+    e_ki = (torch.linalg.norm(m_ki - m) / torch.linalg.norm(m)).item()
+    del Kinv
     # MAP optimality residual F* Gn^-1 (F m - d) + m / Gp, relative to m / Gp
     g = plan.FT((plan.F(m) - d_obs) / s2) + m / 0.25
     res = (torch.linalg.norm(g) / torch.linalg.norm(m / 0.25)).item()
@@ -598,6 +616,9 @@ def bench_inversion(torch, S, P):
             "hessian_gram_s": round(t_kg, 4), "hessian_gram_vs_matvec_rel": e_kg,
             "posterior_solve_s": round(t_m, 3), "map_gradient_rel": res,
             "posterior_online_ms": round(t_on * 1e3, 3), "posterior_online_vs_refined_rel": e_on,
+            "posterior_invert_s": round(t_inv, 3),
+            "posterior_online_kinv_ms": round(t_ki * 1e3, 3),
+            "posterior_online_kinv_vs_refined_rel": e_ki,
             "qoi_precompute_s": round(t_q, 3), "qoi_precompute_gram_s": round(t_qg, 3),
             "qoi_gram_vs_matvec_rel": e_qg,
             "qoi_predict_ms": round(t_p * 1e3, 4),

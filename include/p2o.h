@@ -289,10 +289,45 @@ p2o_status p2o_posterior_solve(p2o_handle h, double* K, const double* d,
  *          its lower triangle; the upper triangle is not read).
  *   d      device [nrhs][Nt][Nd];  m_out device [nrhs][Nt][Nm].
  * Requires a P2O_FP64 plan (else P2O_EUNSUPPORTED); P2O_EINVAL on null
- * pointers or nrhs outside 1 .. 65535.  Allocates its temporaries and
- * synchronises `stream`. */
+ * pointers or nrhs outside 1 .. 65535.  Its temporaries (n*nrhs doubles,
+ * the inverted 64 x 64 diagonal blocks of the factor, which every call
+ * forms again, and the F* apply workspace) are plan-owned and grow on
+ * demand.  Synchronises `stream`. */
 p2o_status p2o_posterior_mean(p2o_handle h, const double* Kfac, const double* d, double* m_out,
                               int64_t nrhs, double prior_var, void* stream);
+
+/* Offline, once per factorisation (the paper's Phases 2-3 end with K
+ * factored; this goes one step further): K^{-1} itself, so that the online
+ * posterior mean is one pass over a matrix instead of two sequential
+ * triangular sweeps (section "Real-time Bayesian inference and prediction
+ * framework": Phase 4 must run in real time).
+ *   Kfac  device [(Nt*Nd)^2]: K after p2o_posterior_solve (the factor in its
+ *         lower triangle; the upper triangle is not read).
+ *   Kinv  device [(Nt*Nd)^2] float64 row-major, caller-allocated, must not
+ *         overlap Kfac; receives K^{-1}, exactly symmetric (the solutions
+ *         of K X = I for all n = Nt*Nd unit vectors at once with the blocked
+ *         matrix-core solve, about 2 n^3 flops, lower triangle mirrored).
+ * An explicit inverse applied to d has an error of the order of
+ * cond(K) u ||K^{-1}|| ||d||, against cond(K) u ||K^{-1} d|| for the
+ * triangular sweeps: the same for a well-conditioned K, possibly larger
+ * for a badly conditioned one.
+ * Requires a P2O_FP64 plan (else P2O_EUNSUPPORTED); P2O_EINVAL on null
+ * pointers.  Synchronises `stream`. */
+p2o_status p2o_posterior_invert(p2o_handle h, const double* Kfac, double* Kinv, void* stream);
+
+/* Phase 4 online inference from K^{-1} (p2o_posterior_invert):
+ * m = Gamma_prior F* (K^{-1} d): one pass over K^{-1} (an HBM-bound
+ * matrix-vector product, 8 n^2 bytes) and one F* apply.
+ *   Kinv  device [(Nt*Nd)^2] (all of it is read).
+ *   d     device [nrhs][Nt][Nd];  m_out device [nrhs][Nt][Nm].
+ * Requires a P2O_FP64 plan (else P2O_EUNSUPPORTED); P2O_EINVAL on null
+ * pointers or nrhs outside 1 .. 65535.  Stream-ordered: does not
+ * synchronise.  Temporaries (n*nrhs doubles plus the F* apply workspace,
+ * and 2*nrhs*Nt*Nm doubles with a spatial prior) are plan-owned: the first
+ * call with a larger nrhs allocates them (draining `stream` first if an
+ * older buffer is replaced), later calls allocate nothing. */
+p2o_status p2o_posterior_mean_kinv(p2o_handle h, const double* Kinv, const double* d,
+                                   double* m_out, int64_t nrhs, double prior_var, void* stream);
 
 /* --------------------------------------------- spatial prior covariance
  * The inversion calls below take Gamma_prior = prior_var * (I_Nt (x) C):

@@ -58,6 +58,8 @@ _SIGNATURES = {
     "p2o_set_prior": (_int, [_vp, _c.POINTER(_PriorGrid), _vp]),
     "p2o_set_assembly": (_int, [_vp, _int]),
     "p2o_posterior_mean": (_int, [_vp, _vp, _vp, _vp, _i64, _dbl, _vp]),
+    "p2o_posterior_invert": (_int, [_vp, _vp, _vp, _vp]),
+    "p2o_posterior_mean_kinv": (_int, [_vp, _vp, _vp, _vp, _i64, _dbl, _vp]),
     "p2o_qoi_predict": (_int, [_vp, _i64, _i64, _vp, _vp, _i64, _vp]),
     "p2o_destroy": (None, [_vp]),
     "p2o_status_string": (_c.c_char_p, [_int]),
@@ -303,6 +305,44 @@ class Plan:
             out = torch.empty(d.shape[:-1] + (self.Nm,), dtype=torch.float64, device=d.device)
         _check("p2o_posterior_mean", self._lib.p2o_posterior_mean(
             self._handle(), Kfac.data_ptr(), d.data_ptr(), out.data_ptr(), nrhs,
+            float(prior_var), _stream_handle(stream)))
+        return out
+
+    def posterior_invert(self, Kfac: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+        """Offline: K^{-1} (exactly symmetric) from the factor left in Kfac's
+        lower triangle by posterior()."""
+        Kfac = _dev_f64(Kfac, "Kfac")
+        n = self.Nt * self.Nd
+        if tuple(Kfac.shape) != (n, n):
+            raise ValueError(f"Kfac must be ({n}, {n})")
+        if out is None:
+            out = torch.empty((n, n), dtype=torch.float64, device=Kfac.device)
+        else:
+            out = _dev_f64(out, "out")
+        _check("p2o_posterior_invert", self._lib.p2o_posterior_invert(
+            self._handle(), Kfac.data_ptr(), out.data_ptr(), _stream_handle(stream)))
+        return out
+
+    def _kinv_args(self, Kinv, d, out):
+        Kinv = _dev_f64(Kinv, "Kinv")
+        d = _dev_f64(d, "d")
+        nrhs = 1 if d.dim() == 2 else int(d.shape[0])
+        if d.shape[-2:] != (self.Nt, self.Nd):
+            raise ValueError("d must end in (Nt, Nd)")
+        n = self.Nt * self.Nd
+        if tuple(Kinv.shape) != (n, n):
+            raise ValueError(f"Kinv must be ({n}, {n})")
+        if out is None:
+            out = torch.empty(d.shape[:-1] + (self.Nm,), dtype=torch.float64, device=d.device)
+        return Kinv, d, out, nrhs
+
+    def posterior_mean_kinv(self, Kinv: torch.Tensor, d: torch.Tensor, prior_var: float,
+                            out=None, stream=None) -> torch.Tensor:
+        """Phase 4 online: m = Gamma_prior F* (K^{-1} d) from posterior_invert()'s
+        K^{-1} (stream-ordered)."""
+        Kinv, d, out, nrhs = self._kinv_args(Kinv, d, out)
+        _check("p2o_posterior_mean_kinv", self._lib.p2o_posterior_mean_kinv(
+            self._handle(), Kinv.data_ptr(), d.data_ptr(), out.data_ptr(), nrhs,
             float(prior_var), _stream_handle(stream)))
         return out
 

@@ -137,6 +137,22 @@ p2o_status ensure_ws(p2o_plan_s* h, int64_t nrhs) {
   return P2O_OK;
 }
 
+// The plan-owned temporaries of the online posterior mean grow on demand
+// (the stream is drained before an older, smaller buffer is freed) and are
+// kept for later calls.
+p2o_status ensure_aux(p2o_plan_s* h, size_t need, hipStream_t s) {
+  if (need <= h->aux_bytes) return P2O_OK;
+  if (h->aux) {
+    TRY_HIP(hipStreamSynchronize(s));
+    TRY_HIP(hipFree(h->aux));
+    h->aux = nullptr;
+    h->aux_bytes = 0;
+  }
+  TRY_HIP(hipMalloc(&h->aux, need));
+  h->aux_bytes = need;
+  return P2O_OK;
+}
+
 void free_plan(p2o_plan_s* h) {
   if (!h) return;
   (void)hipFree(h->tw64);
@@ -146,6 +162,7 @@ void free_plan(p2o_plan_s* h) {
   (void)hipFree(h->scales);
   (void)hipFree(h->scratch);
   (void)hipFree(h->ws);
+  (void)hipFree(h->aux);
   (void)hipFree(h->prior_w);
   for (int op = 0; op < 2; ++op) {
     for (auto& pr : h->pending[op]) {
@@ -401,12 +418,12 @@ p2o_status timed_end(p2o_plan_s* h, p2o_op op, hipStream_t s) {
 // Forward transform of x (float64, [nrhs][Nt][n_in]) into the workspace's
 // input-spectrum region (float64 or float32 by plan precision).
 hipError_t enqueue_forward(const p2o_plan_s* h, p2o_op op, const double* x, int64_t nrhs,
-                           hipStream_t s) {
+                           char* ws, hipStream_t s) {
   const WsLayout w = ws_layout(h, op, nrhs);
   const int64_t nin = (op == P2O_F) ? h->Nm : h->Nd;
   FftIo f{};
   f.in = x;
-  f.out = static_cast<char*>(h->ws) + w.a_off;
+  f.out = ws + w.a_off;
   f.ncols = nin;
   f.in_row = nin;
   f.in_batch = h->Nt * nin;
@@ -416,7 +433,7 @@ hipError_t enqueue_forward(const p2o_plan_s* h, p2o_op op, const double* x, int6
   f.scale = 1.0;
   if (planes_path(h, op, nrhs)) {
     f.out = nullptr;
-    f.planes = reinterpret_cast<uint16_t*>(static_cast<char*>(h->ws) + w.c_off);
+    f.planes = reinterpret_cast<uint16_t*>(ws + w.c_off);
     f.n8 = round8(nin);
     f.nbins = h->nf;
     f.col_scales = (op == P2O_F) ? h->scales : nullptr;  // F's operand carries the scales
@@ -428,11 +445,11 @@ hipError_t enqueue_forward(const p2o_plan_s* h, p2o_op op, const double* x, int6
 // Inverse transform of the product region into y ([nrhs][Nt][n_out]),
 // summing F's partial spectra, truncating to Nt steps, times out_scale.
 hipError_t enqueue_inverse(const p2o_plan_s* h, p2o_op op, double* y, int64_t nrhs,
-                           double out_scale, hipStream_t s) {
+                           double out_scale, const char* ws, hipStream_t s) {
   const WsLayout w = ws_layout(h, op, nrhs);
   const int64_t nout = (op == P2O_F) ? h->Nd : h->Nm;
   FftIo v{};
-  v.in = static_cast<char*>(h->ws) + w.b_off;
+  v.in = ws + w.b_off;
   v.out = y;
   v.ncols = nout;
   v.in_row = nout;
@@ -447,16 +464,23 @@ hipError_t enqueue_inverse(const p2o_plan_s* h, p2o_op op, double* y, int64_t nr
   return launch_rfft_inv_f32(h->fft, h->tw32, h->perm, v, op == P2O_F, nrhs, s);
 }
 
+// One apply on the workspace `ws` (ws_layout(h, op, nrhs).total bytes; the
+// plan's own workspace unless a caller brings another), with the product
+// kernel timed when the plan's timing is on and `timed`.
+p2o_status apply_on(p2o_plan_s* h, p2o_op op, const double* x, double* y, int64_t nrhs,
+                    char* ws, bool timed, hipStream_t s, double out_scale) {
+  const WsLayout w = ws_layout(h, op, nrhs);
+  TRY_HIP(enqueue_forward(h, op, x, nrhs, ws, s));
+  if (timed) TRY_ST(timed_begin(h, op, s));
+  TRY_HIP(launch_product(h, op, ws + w.a_off, ws + w.b_off, ws + w.c_off, nrhs, h->cfg[op], s));
+  if (timed) TRY_ST(timed_end(h, op, s));
+  TRY_HIP(enqueue_inverse(h, op, y, nrhs, out_scale, ws, s));
+  return P2O_OK;
+}
+
 p2o_status apply_impl(p2o_plan_s* h, p2o_op op, const double* x, double* y, int64_t nrhs,
                       hipStream_t s, double out_scale = 1.0) {
-  const WsLayout w = ws_layout(h, op, nrhs);
-  char* ws = static_cast<char*>(h->ws);
-  TRY_HIP(enqueue_forward(h, op, x, nrhs, s));
-  TRY_ST(timed_begin(h, op, s));
-  TRY_HIP(launch_product(h, op, ws + w.a_off, ws + w.b_off, ws + w.c_off, nrhs, h->cfg[op], s));
-  TRY_ST(timed_end(h, op, s));
-  TRY_HIP(enqueue_inverse(h, op, y, nrhs, out_scale, s));
-  return P2O_OK;
+  return apply_on(h, op, x, y, nrhs, static_cast<char*>(h->ws), true, s, out_scale);
 }
 
 }  // namespace
@@ -999,25 +1023,98 @@ p2o_status p2o_posterior_mean(p2o_handle h, const double* Kfac, const double* d,
   (void)hipGetLastError();
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = h->Nt * h->Nd;
-  DevBufs bufs;
-  void *x, *psolve;
-  TRY_HIP(bufs.alloc(&x, (size_t)nrhs * n * 8));
-  TRY_HIP(bufs.alloc(&psolve, cholesky_solve_scratch(n, nrhs)));
-  double* X = static_cast<double*>(x);
-  TRY_HIP(hipMemcpyAsync(X, d, (size_t)nrhs * n * 8, hipMemcpyDeviceToDevice, s));
-  TRY_HIP(cholesky_solve(Kfac, X, static_cast<double*>(psolve), n, nrhs, s));
+  // plan-owned: [x: nrhs n][solve scratch][prior temporaries: 2 nrhs Nt Nm]
+  const size_t x_bytes = align_up((size_t)nrhs * n * 8);
+  const size_t solve_bytes = align_up(cholesky_solve_scratch(n, nrhs));
+  const size_t prior_bytes = h->prior_w ? 2 * align_up((size_t)nrhs * h->Nt * h->Nm * 8) : 0;
+  TRY_ST(ensure_aux(h, x_bytes + solve_bytes + prior_bytes, s));
   TRY_ST(ensure_ws(h, nrhs));
+  char* aux = static_cast<char*>(h->aux);
+  double* X = reinterpret_cast<double*>(aux);
+  TRY_HIP(hipMemcpyAsync(X, d, (size_t)nrhs * n * 8, hipMemcpyDeviceToDevice, s));
+  TRY_HIP(cholesky_solve(Kfac, X, reinterpret_cast<double*>(aux + x_bytes), n, nrhs, s));
   TRY_ST(apply_impl(h, P2O_FADJ, X, m_out, nrhs, s, prior_var));
   if (h->prior_w) {  // Gamma_prior = prior_var (I (x) C)
-    void *t1, *t2;
-    TRY_HIP(bufs.alloc(&t1, (size_t)nrhs * h->Nt * h->Nm * 8));
-    TRY_HIP(bufs.alloc(&t2, (size_t)nrhs * h->Nt * h->Nm * 8));
-    TRY_HIP(launch_apply_prior(m_out, static_cast<double*>(t1), static_cast<double*>(t2),
-                               nrhs * h->Nt, h->prior_nx, h->prior_ny, h->prior_w, h->prior_r,
-                               h->prior_delta, s));
+    double* t1 = reinterpret_cast<double*>(aux + x_bytes + solve_bytes);
+    double* t2 = t1 + prior_bytes / 16;
+    TRY_HIP(launch_apply_prior(m_out, t1, t2, nrhs * h->Nt, h->prior_nx, h->prior_ny,
+                               h->prior_w, h->prior_r, h->prior_delta, s));
   }
   TRY_HIP(hipStreamSynchronize(s));
   return P2O_OK;
+}
+
+p2o_status p2o_posterior_invert(p2o_handle h, const double* Kfac, double* Kinv, void* stream) {
+  if (!h || !Kfac || !Kinv) return P2O_EINVAL;
+  if (!h->ready) return P2O_ESTATE;
+  if (h->prec != P2O_FP64) return P2O_EUNSUPPORTED;
+  (void)hipGetLastError();
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = h->Nt * h->Nd;
+  // row j of Kinv = K^{-1} e_j: the solves of K X = I, all n at once
+  TRY_HIP(launch_identity(Kinv, n, s));
+  TRY_HIP(launch_cholesky_solve_many(Kfac, Kinv, n, n, s));
+  TRY_HIP(launch_mirror_lower(Kinv, n, s));  // exactly symmetric
+  TRY_HIP(hipStreamSynchronize(s));
+  return P2O_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Bytes of the temporaries of the online posterior mean from K^{-1}:
+// [x = K^{-1} d: nrhs n][F* apply workspace][prior temporaries].
+struct KinvLayout {
+  size_t ws_off, prior_off, total;
+};
+
+KinvLayout kinv_layout(const p2o_plan_s* h, int64_t nrhs) {
+  const int64_t n = h->Nt * h->Nd;
+  KinvLayout l{};
+  l.ws_off = align_up((size_t)nrhs * n * 8);
+  l.prior_off = l.ws_off + align_up(ws_layout(h, P2O_FADJ, nrhs).total);
+  l.total = l.prior_off + (h->prior_w ? 2 * align_up((size_t)nrhs * h->Nt * h->Nm * 8) : 0);
+  return l;
+}
+
+p2o_status kinv_check(const p2o_plan_s* h, const double* Kinv, const double* d,
+                      const double* m_out, int64_t nrhs) {
+  if (!h || !Kinv || !d || !m_out || nrhs < 1 || nrhs > 65535) return P2O_EINVAL;
+  if (!h->ready) return P2O_ESTATE;
+  if (h->prec != P2O_FP64) return P2O_EUNSUPPORTED;
+  return P2O_OK;
+}
+
+// m = prior_var (I (x) C) F* (Kinv d) on the temporaries at `tmp`
+// (kinv_layout bytes); stream-ordered, allocates nothing.
+p2o_status kinv_enqueue(p2o_plan_s* h, const double* Kinv, const double* d, double* m_out,
+                        int64_t nrhs, double prior_var, char* tmp, bool timed, hipStream_t s) {
+  const int64_t n = h->Nt * h->Nd;
+  const KinvLayout l = kinv_layout(h, nrhs);
+  double* X = reinterpret_cast<double*>(tmp);
+  TRY_HIP(launch_qoi_gemv(Kinv, d, X, n, n, nrhs, s));
+  TRY_ST(apply_on(h, P2O_FADJ, X, m_out, nrhs, tmp + l.ws_off, timed, s, prior_var));
+  if (h->prior_w) {
+    double* t1 = reinterpret_cast<double*>(tmp + l.prior_off);
+    double* t2 = t1 + (l.total - l.prior_off) / 16;
+    TRY_HIP(launch_apply_prior(m_out, t1, t2, nrhs * h->Nt, h->prior_nx, h->prior_ny,
+                               h->prior_w, h->prior_r, h->prior_delta, s));
+  }
+  return P2O_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+p2o_status p2o_posterior_mean_kinv(p2o_handle h, const double* Kinv, const double* d,
+                                   double* m_out, int64_t nrhs, double prior_var, void* stream) {
+  TRY_ST(kinv_check(h, Kinv, d, m_out, nrhs));
+  (void)hipGetLastError();
+  hipStream_t s = (hipStream_t)stream;
+  TRY_ST(ensure_aux(h, kinv_layout(h, nrhs).total, s));
+  return kinv_enqueue(h, Kinv, d, m_out, nrhs, prior_var, static_cast<char*>(h->aux), true, s);
 }
 
 }  // extern "C"
@@ -1085,9 +1182,12 @@ p2o_status batch_enqueue(p2o_batch b, p2o_op op, const double* const* x, double*
                          const int64_t* nrhs, const std::vector<BatchInst>& table,
                          const BatchInst* dev_table, int64_t total, hipStream_t s) {
   const size_t n = b->plans.size();
-  for (size_t i = 0; i < n; ++i) TRY_HIP(enqueue_forward(b->plans[i], op, x[i], nrhs[i], s));
+  for (size_t i = 0; i < n; ++i)
+    TRY_HIP(enqueue_forward(b->plans[i], op, x[i], nrhs[i], static_cast<char*>(b->plans[i]->ws), s));
   TRY_HIP(launch_batch_product(b->cls, op, dev_table, (int)n, total, s));
-  for (size_t i = 0; i < n; ++i) TRY_HIP(enqueue_inverse(b->plans[i], op, y[i], nrhs[i], 1.0, s));
+  for (size_t i = 0; i < n; ++i)
+    TRY_HIP(enqueue_inverse(b->plans[i], op, y[i], nrhs[i], 1.0,
+                            static_cast<const char*>(b->plans[i]->ws), s));
   return P2O_OK;
 }
 

@@ -505,6 +505,14 @@ __global__ void copy_diagonal(const double* __restrict__ K, double* __restrict__
   if (i < n) d[i] = K[i * n + i];
 }
 
+// X = I (n x n, row-major): one thread per entry, grid-stride.
+__global__ void identity(double* __restrict__ X, int64_t n) {
+  const int64_t total = n * n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x)
+    X[i] = (i / n == i % n) ? 1.0 : 0.0;
+}
+
 __global__ void axpy(double* __restrict__ y, const double* __restrict__ x, double a, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] += a * x[i];
@@ -644,6 +652,12 @@ hipError_t launch_residual(const double* K, const double* diag, const double* D,
                      part, n, nrhs);
   hipLaunchKernelGGL(residual, dim3(grid1(n * nrhs)), dim3(256), 0, s, D, X, diag, rows, part,
                      (int)nc, R, n, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_identity(double* X, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(identity, dim3(std::min<unsigned>(grid1(n * n), 65536u)), dim3(256), 0, s,
+                     X, n);
   return hipGetLastError();
 }
 

@@ -198,6 +198,7 @@ hipError_t launch_residual(const double* K, const double* diag, const double* D,
                            const double* X, double* R, double* rows, double* part, int64_t n,
                            int64_t nrhs, hipStream_t s);
 hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t s);
+hipError_t launch_identity(double* X, int64_t n, hipStream_t s);  // X = I (n x n)
 
 // ------------------------------------------------- dense float64 (dense.hip)
 // C[M x N] += alpha A[M x K] op(B), row-major; op(B) = B^T ([N x K]) when
@@ -273,6 +274,8 @@ struct p2o_plan_s {
   size_t scratch_bytes = 0;
   void* ws = nullptr;                // apply workspace
   size_t ws_bytes = 0;
+  void* aux = nullptr;               // temporaries of the online posterior mean
+  size_t aux_bytes = 0;
   bool timing = false;
   hipEvent_t ev_begin[2] = {nullptr, nullptr};
   hipEvent_t ev_end[2] = {nullptr, nullptr};

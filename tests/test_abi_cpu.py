@@ -59,6 +59,9 @@ def test_setup_rejects_bad_arguments_on_host(lib):
     assert lib.p2o_get_info(None, None, None, None, None, None) == 1
     assert lib.p2o_hessian_assemble(None, 1.0, None, None, None) == 1
     assert lib.p2o_posterior_solve(None, None, None, None, 1, 1.0, 1, None, None) == 1
+    assert lib.p2o_posterior_mean(None, None, None, None, 1, 1.0, None) == 1
+    assert lib.p2o_posterior_invert(None, None, None, None) == 1
+    assert lib.p2o_posterior_mean_kinv(None, None, None, None, 1, 1.0, None) == 1
     assert lib.p2o_kernel_time(None, 0, None, None) == 1
     assert lib.p2o_last_hip_error(None) == 1
     lib.p2o_destroy(None)

@@ -73,7 +73,16 @@ def test_inversion_workload_100x5000x200():
             e = np.abs(got - ref).max() / np.abs(ref).max()
             print(f"  K column {col}: err {e:.2e}", flush=True)
             assert e <= 1e-12
-        m = host(plan.posterior(K, dev(d_obs), 0.25, refine_steps=1))
+        m_dev = plan.posterior(K, dev(d_obs), 0.25, refine_steps=1)
+        m = host(m_dev)
+        # Phase 4 online, from the factor and from K^{-1}, against the refined m
+        m_fac = host(plan.posterior_mean(K, dev(d_obs), 0.25))
+        Kinv = plan.posterior_invert(K)
+        m_inv = host(plan.posterior_mean_kinv(Kinv, dev(d_obs), 0.25))
+        del Kinv
+    e_fac, e_inv = rel_err(m_fac, m), rel_err(m_inv, m)
+    print(f"  online m vs refined: from the factor {e_fac:.2e}, from K^-1 {e_inv:.2e}", flush=True)
+    assert e_fac <= 1e-12 and e_inv <= 1e-12
     g = oracle.map_objective_gradient(blocks, 0.25, nv, d_obs, m)
     scale = np.linalg.norm(m / 0.25)
     print(f"  MAP gradient rel {np.linalg.norm(g) / scale:.2e}", flush=True)
@@ -149,4 +158,90 @@ def test_posterior_mean_errors():
         with pytest.raises(P.P2OError) as e:
             plan.posterior_mean(torch.eye(16, dtype=torch.float64, device="cuda"),
                                 dev(np.ones((8, 2))), 0.25)
+        assert e.value.status == 6
+
+
+@pytest.mark.parametrize("shape,nrhs", [((3, 40, 7), 1), ((5, 300, 29), 3), ((5, 300, 29), 20),
+                                        ((4, 60, 32), 2), ((20, 300, 55), 1)])
+def test_posterior_mean_from_inverse(shape, nrhs):
+    """Phase 4 online from K^{-1}: posterior_invert() forms K^{-1} from the
+    factor (checked by K K^{-1} = I against the oracle's K, and exact
+    symmetry), then m = Gp F* (K^{-1} d) against the oracle's posterior mean;
+    a second call with one right-hand side reuses the plan's temporaries and
+    gives the same first result (bit for bit when both calls take the
+    vector-unit F* kernels)."""
+    Nd, Nm, Nt = shape
+    print(f"\n[inverse] explicit inverse shape={shape} nrhs={nrhs}", flush=True)
+    blocks, _, _ = workload(11, Nd, Nm, Nt, tau=Nt / 3)
+    n = Nt * Nd
+    nv = _noise(11, n)
+    d = S.vector(11, S.ARRAY_D, nrhs * n).reshape(nrhs, Nt, Nd)
+    K_ref = oracle.hessian_gram(blocks, 0.25, nv)
+    m_ref = np.stack([oracle.posterior_mean(blocks, 0.25, nv, d[r], K=K_ref) for r in range(nrhs)])
+    with P.Plan(dev(blocks), "fp64") as plan:
+        K = plan.hessian(0.25, dev(nv))
+        plan.posterior(K, dev(np.zeros((Nt, Nd))), 0.25, refine_steps=0)  # factor K
+        K_before = K.clone()
+        Kinv = plan.posterior_invert(K)
+        assert torch.equal(K, K_before)
+        m = plan.posterior_mean_kinv(Kinv, dev(d), 0.25)
+        m1 = plan.posterior_mean_kinv(Kinv, dev(d[:1]), 0.25)
+        torch.cuda.synchronize()
+        Ki, m, m1 = host(Kinv), host(m), host(m1)
+    assert np.array_equal(Ki, Ki.T)
+    eI = np.abs(K_ref @ Ki - np.eye(n)).max()
+    e = rel_err(m, m_ref)
+    print(f"  |K K^-1 - I| {eI:.2e}  m err {e:.2e}", flush=True)
+    assert eI <= 1e-12
+    assert e <= 1e-10
+    if nrhs < 8:  # same product kernels (vector units) for both calls
+        assert np.array_equal(m1[0], m[0])
+    else:         # 20 right-hand sides: F* on the float64 matrix cores
+        assert rel_err(m1[0], m[0]) <= 1e-13
+
+
+def test_posterior_mean_from_inverse_with_prior():
+    """The explicit-inverse path with a spatial prior C (Gp = 0.25 (I (x) C))."""
+    Nd, nx, ny, Nt, nrhs = 6, 10, 6, 24, 2
+    Nm = nx * ny
+    blocks, _, _ = workload(12, Nd, Nm, Nt, tau=Nt / 3)
+    n = Nt * Nd
+    nv = _noise(12, n)
+    d = S.vector(12, S.ARRAY_D, nrhs * n).reshape(nrhs, Nt, Nd)
+    C = oracle.prior_grid_matrix(nx, ny, 1, 0.8, 0.3)
+    K_ref = oracle.hessian_gram(blocks, 0.25, nv, C)
+    m_ref = np.stack([oracle.posterior_mean(blocks, 0.25, nv, d[i], K=K_ref, prior_C=C)
+                      for i in range(nrhs)])
+    with P.Plan(dev(blocks), "fp64") as plan:
+        plan.set_prior((nx, ny), radius=1, length=0.8, delta=0.3)
+        K = plan.hessian(0.25, dev(nv))
+        plan.posterior(K, dev(np.zeros((Nt, Nd))), 0.25, refine_steps=0)
+        m = host(plan.posterior_mean_kinv(plan.posterior_invert(K), dev(d), 0.25))
+    e = rel_err(m, m_ref)
+    print(f"\n[inverse] explicit inverse with prior: m err {e:.2e}", flush=True)
+    assert e <= 1e-10
+
+
+def test_posterior_inverse_errors():
+    blocks, _, _ = workload(10, 2, 24, 8, tau=3.0)
+    lib = P.load_library()
+    with P.Plan(dev(blocks), "fp64") as plan:
+        K = torch.eye(16, dtype=torch.float64, device="cuda")
+        with pytest.raises(ValueError):
+            plan.posterior_invert(torch.eye(15, dtype=torch.float64, device="cuda"))
+        d = dev(np.ones((8, 2)))
+        m = torch.empty((8, 24), dtype=torch.float64, device="cuda")
+        assert lib.p2o_posterior_invert(plan._handle(), K.data_ptr(), None, None) == 1
+        assert lib.p2o_posterior_mean_kinv(plan._handle(), None, d.data_ptr(), m.data_ptr(), 1,
+                                           0.25, None) == 1
+        assert lib.p2o_posterior_mean_kinv(plan._handle(), K.data_ptr(), d.data_ptr(),
+                                           m.data_ptr(), 0, 0.25, None) == 1
+    b256, _, _ = workload(10, 2, 256, 8, tau=3.0)
+    with P.Plan(dev(b256), "mixed_bf16") as plan:
+        K = torch.eye(16, dtype=torch.float64, device="cuda")
+        with pytest.raises(P.P2OError) as e:
+            plan.posterior_invert(K)
+        assert e.value.status == 6
+        with pytest.raises(P.P2OError) as e:
+            plan.posterior_mean_kinv(K, dev(np.ones((8, 2))), 0.25)
         assert e.value.status == 6
