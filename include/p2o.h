@@ -329,6 +329,27 @@ p2o_status p2o_posterior_invert(p2o_handle h, const double* Kfac, double* Kinv, 
 p2o_status p2o_posterior_mean_kinv(p2o_handle h, const double* Kinv, const double* d,
                                    double* m_out, int64_t nrhs, double prior_var, void* stream);
 
+/* p2o_posterior_mean_kinv for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation on the same kernels (results equal to
+ * p2o_posterior_mean_kinv's bit for bit), with every temporary in one
+ * fixed 64 MiB device array that each GPU the library runs on holds until
+ * the process ends.  Calls no hipMalloc, hipFree or other allocating
+ * routine; the first call on a device looks up that array's address
+ * (hipGetSymbolAddress) and keeps it.  The temporaries need
+ *   8 n nrhs + (16 nf Nd + 16 nf Nm) nrhs bytes (n = Nt*Nd, nf = L/2 + 1,
+ *   each part rounded up to 256 bytes), plus 2 * 8 nrhs Nt Nm with a
+ *   spatial prior;
+ * beyond 64 MiB the call returns P2O_ENOMEM and does nothing (at Nd = 100,
+ * Nm = 5000, Nt = 200: up to 3 right-hand sides without a spatial prior).
+ * All calls on one GPU share that GPU's array, which keeps the last call's
+ * contents: calls that overlap on one GPU (other streams, other threads,
+ * other plans) race and must be serialised by the caller.  Arguments,
+ * errors and stream ordering as p2o_posterior_mean_kinv. */
+p2o_status p2o_posterior_mean_kinv_noalloc(p2o_handle h, const double* Kinv, const double* d,
+                                           double* m_out, int64_t nrhs, double prior_var,
+                                           void* stream);
+
 /* --------------------------------------------- spatial prior covariance
  * The inversion calls below take Gamma_prior = prior_var * (I_Nt (x) C):
  * the same spatial covariance C on every time step (time-invariant, which

@@ -60,6 +60,7 @@ _SIGNATURES = {
     "p2o_posterior_mean": (_int, [_vp, _vp, _vp, _vp, _i64, _dbl, _vp]),
     "p2o_posterior_invert": (_int, [_vp, _vp, _vp, _vp]),
     "p2o_posterior_mean_kinv": (_int, [_vp, _vp, _vp, _vp, _i64, _dbl, _vp]),
+    "p2o_posterior_mean_kinv_noalloc": (_int, [_vp, _vp, _vp, _vp, _i64, _dbl, _vp]),
     "p2o_qoi_predict": (_int, [_vp, _i64, _i64, _vp, _vp, _i64, _vp]),
     "p2o_destroy": (None, [_vp]),
     "p2o_status_string": (_c.c_char_p, [_int]),
@@ -342,6 +343,17 @@ class Plan:
         K^{-1} (stream-ordered)."""
         Kinv, d, out, nrhs = self._kinv_args(Kinv, d, out)
         _check("p2o_posterior_mean_kinv", self._lib.p2o_posterior_mean_kinv(
+            self._handle(), Kinv.data_ptr(), d.data_ptr(), out.data_ptr(), nrhs,
+            float(prior_var), _stream_handle(stream)))
+        return out
+
+    def posterior_mean_kinv_noalloc(self, Kinv: torch.Tensor, d: torch.Tensor, prior_var: float,
+                                    out: torch.Tensor = None, stream=None) -> torch.Tensor:
+        """As posterior_mean_kinv, on the library's fixed device scratch (no
+        device allocation inside the call; pass `out` to allocate nothing at
+        all)."""
+        Kinv, d, out, nrhs = self._kinv_args(Kinv, d, out)
+        _check("p2o_posterior_mean_kinv_noalloc", self._lib.p2o_posterior_mean_kinv_noalloc(
             self._handle(), Kinv.data_ptr(), d.data_ptr(), out.data_ptr(), nrhs,
             float(prior_var), _stream_handle(stream)))
         return out

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -1115,6 +1116,61 @@ p2o_status p2o_posterior_mean_kinv(p2o_handle h, const double* Kinv, const doubl
   hipStream_t s = (hipStream_t)stream;
   TRY_ST(ensure_aux(h, kinv_layout(h, nrhs).total, s));
   return kinv_enqueue(h, Kinv, d, m_out, nrhs, prior_var, static_cast<char*>(h->aux), true, s);
+}
+
+}  // extern "C"
+
+// ---------------------------------------- allocation-free online variant
+// Fixed device scratch of p2o_posterior_mean_kinv_noalloc: every device the
+// library runs on holds its own copy of this array until the process ends.
+// In host code `scratch` names a host-side stand-in, not device memory:
+// only the per-device address obtained from hipGetSymbolAddress is ever
+// handed to kernels or copies.
+namespace {
+
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mutex;
+char* g_scratch_dev[kMaxScratchDevices] = {};
+
+// The device address of `scratch` on `device`, looked up once per device
+// with that device current (the caller's current device is restored).
+p2o_status scratch_on_device(int device, char** out) {
+  if (device < 0 || device >= kMaxScratchDevices) return P2O_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_dev[device]) {
+    int current = 0;
+    TRY_HIP(hipGetDevice(&current));
+    if (current != device) TRY_HIP(hipSetDevice(device));
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (current != device) (void)hipSetDevice(current);
+    if (e != hipSuccess) return hip_fail(e);
+    if (!ptr) return P2O_EHIP;
+    g_scratch_dev[device] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_dev[device];
+  return P2O_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+p2o_status p2o_posterior_mean_kinv_noalloc(p2o_handle h, const double* Kinv, const double* d,
+                                           double* m_out, int64_t nrhs, double prior_var,
+                                           void* stream) {
+  TRY_ST(kinv_check(h, Kinv, d, m_out, nrhs));
+  if (kinv_layout(h, nrhs).total > kNoAllocScratchBytes) return P2O_ENOMEM;
+  char* base = nullptr;
+  TRY_ST(scratch_on_device(h->device, &base));
+  (void)hipGetLastError();
+  // no part of the scratch needs to start at zero: every kernel writes what
+  // a later one reads (K^{-1} d, the transformed d, the products, the prior
+  // temporaries); the product kernel is not event-timed here
+  return kinv_enqueue(h, Kinv, d, m_out, nrhs, prior_var, base, false, (hipStream_t)stream);
 }
 
 }  // extern "C"
