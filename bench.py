@@ -31,7 +31,7 @@ PEAK_HBM_GBS = 8000.0
 ENTRY_BYTES = {"fp64": 16, "mixed_fp16": 8, "mixed_bf16": 8, "fast_bf16": 4}
 VEC_BYTES = {"fp64": 16, "mixed_fp16": 8, "mixed_bf16": 8, "fast_bf16": 8}
 SCALE_TILE = 256
-DEFAULT_PRECS = "mixed_bf16,fp64,mixed_fp16"
+DEFAULT_PRECS = "mixed_bf16,fp64,mixed_fp16,fast_bf16"
 
 
 def parse():
@@ -49,7 +49,15 @@ def parse():
                     help="columns of the workload the CPU oracle baseline runs on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-gb", type=float, default=4.0,
-                    help="size of the plain device copy timed as the measured HBM ceiling")
+                    help="size of the plain device copy (the byte counters' calibration kernel)")
+    ap.add_argument("--read-gb", type=float, default=8.0,
+                    help="size of the streaming read timed as the measured HBM read ceiling")
+    ap.add_argument("--mrhs", type=int, default=64,
+                    help="single workload: also time this many right-hand sides per apply on "
+                         "the float64 and bfloat16 hi+lo plans (matrix cores); 0 skips")
+    ap.add_argument("--mrhs-steps", type=int, default=3)
+    ap.add_argument("--no-c2", action="store_true",
+                    help="skip the float64 100x5000x200 single-RHS leg")
     ap.add_argument("--workload", default="single", choices=["single", "batch", "mrhs"],
                     help="single: the 600x40000x420 F+F* step (default); batch: 64 uneven "
                          "instances with 1..256 right-hand sides each; mrhs: one plan, "
@@ -502,7 +510,44 @@ def bench_mrhs(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_inversion(torch, S, P):
+def inversion_cpu_baseline(torch, S, K_dev, env_dev, Nd, Nm, Nt, seed, s2, t_chol, t_gram):
+    """The oracle beside the inversion workload on the host cores: LAPACK
+    Cholesky (scipy cho_factor, as the oracle's posterior mean uses it) of
+    the same K, and the oracle's Gram-recurrence K from the same blocks
+    (drawn on the device, copied to the host outside the timed region)."""
+    import scipy.linalg
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count()
+    n = Nt * Nd
+    Kh = K_dev.cpu().numpy()
+    t0 = time.perf_counter()
+    scipy.linalg.cho_factor(Kh, lower=True, overwrite_a=True, check_finite=False)
+    t_potrf = time.perf_counter() - t0
+    del Kh
+    blk = torch.empty((Nt, Nd, Nm), dtype=torch.float64, device="cuda")
+    S.device_blocks(blk.data_ptr(), Nt, Nd, Nm, 0, Nm, seed, env_dev.data_ptr(),
+                    torch.cuda.current_stream().cuda_stream)
+    blocks = blk.cpu().numpy()
+    del blk
+    t0 = time.perf_counter()
+    oracle.hessian_gram(blocks, 0.25, s2)
+    t_k = time.perf_counter() - t0
+    del blocks
+    return {"kind": "oracle", "cores": int(cores),
+            "cholesky_s": round(t_potrf, 3), "cholesky_gflops": round(n ** 3 / 3 / t_potrf / 1e9, 1),
+            "hessian_gram_s": round(t_k, 3),
+            "gpu_over_cpu": {"cholesky": round(t_potrf / t_chol, 1),
+                             "hessian_gram": round(t_k / t_gram, 1)},
+            "sample": f"the whole {n}x{n} K: scipy.linalg.cho_factor (LAPACK dpotrf) and the "
+                      f"oracle's hessian_gram (one {n}x{Nm}x{n} GEMM plus the block-diagonal "
+                      f"recurrence)"}
+
+
+def bench_inversion(torch, S, P, cpu=True):
     """K = Gn + F Gp F* (20000 x 20000; by the paper's unit-vector matvecs
     and in Gram form), the posterior mean, and the QoI posterior
     (Q, Gamma_post(q); both assembly methods) with its online prediction
@@ -539,10 +584,19 @@ def bench_inversion(torch, S, P):
     e_kg = ((K2 - K).abs().max() / K.abs().max()).item()
     del K2
     plan.set_assembly("matvec")
+    K_keep = K.clone()
     t0 = time.perf_counter()
     m = plan.posterior(K, d_obs, 0.25, refine_steps=1)
     torch.cuda.synchronize()
     t_m = time.perf_counter() - t0
+    # without refinement: factorisation + two sweeps + F*, for the Cholesky estimate
+    Kc = K_keep.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.posterior(Kc, d_obs, 0.25, refine_steps=0)
+    torch.cuda.synchronize()
+    t_m0 = time.perf_counter() - t0
+    del Kc
     # Phase 4 online: m from the factor alone (two triangular sweeps + F*)
     m_on = plan.posterior_mean(K, d_obs, 0.25)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -611,7 +665,35 @@ def bench_inversion(torch, S, P):
     del K, Q, Gq
     torch.cuda.empty_cache()
     units = n
+    nf = P.smooth_length(Nt) // 2 + 1
+    # roofline fractions: float64 matrix-core peak for the assembly and the
+    # factorisation, HBM for the online steps (one pass over the factor per
+    # sweep, or over K^{-1}, plus one F* product's bytes)
+    fadj_bytes = product_bytes("fp64", "FADJ", Nd, Nm, nf, 1)
+    t_chol = max(t_m0 - t_on, 1e-9)
+    flops = {"hessian_unit_vectors": 8 * nf * Nd * Nm * n, "hessian_gram": n * n * Nm,
+             "cholesky": n ** 3 / 3}
+    secs = {"hessian_unit_vectors": t_k, "hessian_gram": t_kg, "cholesky": t_chol}
+    roof = {}
+    for k in flops:
+        tf = flops[k] / secs[k] / 1e12
+        roof[k] = {"bound": "mfma", "achieved": round(tf, 2), "peak": 78.6, "unit": "TFLOP/s",
+                   "frac": round(tf / 78.6, 4), "flops": flops[k], "s": round(secs[k], 4)}
+    hbm = {"posterior_online_factor": (n * n * 8 + fadj_bytes, t_on),
+           "posterior_online_kinv": (n * n * 8 + fadj_bytes, t_ki),
+           "qoi_predict": (q_bytes, t_p)}
+    for k, (b, t) in hbm.items():
+        gbs = b / t / 1e9
+        roof[k] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                   "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes": b, "ms": round(t * 1e3, 4)}
+    cpu_out = None
+    if cpu:
+        cpu_out = inversion_cpu_baseline(torch, S, K_keep, env, Nd, Nm, Nt, seed, s2, t_chol, t_kg)
+    del K_keep
+    torch.cuda.empty_cache()
     return {"workload": f"Nd={Nd} Nm={Nm} Nt={Nt}, K {n}x{n} float64; Nq={Nq} QoI locations",
+            "roofline": roof, "cholesky_s_est": round(t_chol, 4),
+            "posterior_solve_norefine_s": round(t_m0, 4), "cpu_baseline": cpu_out,
             "hessian_assemble_s": round(t_k, 3), "unit_vectors_per_s": round(units / t_k, 1),
             "hessian_gram_s": round(t_kg, 4), "hessian_gram_vs_matvec_rel": e_kg,
             "posterior_solve_s": round(t_m, 3), "map_gradient_rel": res,
@@ -624,6 +706,134 @@ def bench_inversion(torch, S, P):
             "qoi_predict_ms": round(t_p * 1e3, 4),
             "qoi_predict_hbm_gbs": round(q_bytes / t_p / 1e9, 1),
             "qoi_predict_vs_fq_mmap_rel": e_q}
+
+
+def read_ceiling(torch, P, gb, reps=5):
+    """The device's streaming-read ceiling: the library's plain read kernel
+    (the product kernels' non-temporal 16-byte loads, nothing else) over
+    `gb` GB, timed by events on the current stream."""
+    n = int(gb * 1e9) // 16 * 2
+    buf = torch.empty(n, dtype=torch.float64, device="cuda").fill_(1.0)
+    sink = torch.zeros(1, dtype=torch.float64, device="cuda")
+    P.read_bandwidth(buf, sink)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        P.read_bandwidth(buf, sink)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    del buf
+    torch.cuda.empty_cache()
+    return {"bytes": n * 8, "ms": ms, "gbs": n * 8 / (ms * 1e-3) / 1e9,
+            "frac_of_peak": round(n * 8 / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+
+
+def time_ops(torch, P, plan, xF, xA, yF, yA, warmup, steps):
+    """Apply time (events on the current stream) and product-kernel time
+    (the library's events around each product launch) of F and F*."""
+    for _ in range(warmup):
+        plan.F(xF, out=yF)
+        plan.FT(xA, out=yA)
+    torch.cuda.synchronize()
+    plan.set_kernel_timing(True)
+    plan.kernel_time(P.OP_F)
+    plan.kernel_time(P.OP_FADJ)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    for _ in range(steps):
+        plan.F(xF, out=yF)
+    ev[1].record()
+    for _ in range(steps):
+        plan.FT(xA, out=yA)
+    ev[2].record()
+    torch.cuda.synchronize()
+    kF, nF = plan.kernel_time(P.OP_F)
+    kA, nA = plan.kernel_time(P.OP_FADJ)
+    plan.set_kernel_timing(False)
+    return ({"F": ev[0].elapsed_time(ev[1]) / steps, "FADJ": ev[1].elapsed_time(ev[2]) / steps},
+            {"F": kF / max(nF, 1), "FADJ": kA / max(nA, 1)})
+
+
+def mrhs_roofline(prec, op, Nd, Nm, nf, B, ms):
+    """Roofline of one many-RHS product launch sequence (matrix cores):
+    algorithmic bytes and matrix-core flops against HBM and the dtype's
+    dense matrix-core peak; `bound` is whichever the algorithm hits first."""
+    nbytes = mrhs_product_bytes(prec, op, Nd, Nm, nf, n_chunks(Nd, Nm, nf, prec), B)
+    hw = 8 * nf * Nd * Nm * B * SPLIT_FACTOR[prec]
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    tfs = hw / (ms * 1e-3) / 1e12
+    if hw / (PEAK_TFLOPS[prec] * 1e12) >= nbytes / (PEAK_HBM_GBS * 1e9):
+        rf = {"bound": "mfma", "achieved": round(tfs, 2), "peak": PEAK_TFLOPS[prec],
+              "unit": "TFLOP/s", "frac": round(tfs / PEAK_TFLOPS[prec], 4)}
+    else:
+        rf = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+              "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    rf.update({"traffic": None, "avg_ms": round(ms, 4), "bytes_per_launch": nbytes,
+               "mfma_flops_per_launch": hw, "hbm_gbs": round(gbs, 1),
+               "mfma_tflops": round(tfs, 2), "mfma_frac": round(tfs / PEAK_TFLOPS[prec], 4)})
+    return rf
+
+
+def c2_fp64_leg(torch, S, P, reps=200, rotate=4):
+    """FP64 single-RHS F and F* at 100 x 5000 x 200 (201 frequency blocks,
+    1.6 GB per plan).  The blocks are only ~6x the 256 MB last-level cache,
+    so `rotate` plans with different seeds take turns (each launch streams
+    blocks the previous launches did not touch); product-kernel time from
+    the library's events, apply time from events around all launches."""
+    Nd, Nm, Nt = 100, 5000, 200
+    nf = P.smooth_length(Nt) // 2 + 1
+    stream = torch.cuda.current_stream()
+    env = torch.from_numpy(S.envelope(Nt, 40.0, 1.0 / np.sqrt(Nm))).cuda()
+    plans = [make_plan(P, S, torch, "fp64", Nd, Nm, Nt, env, 2 + j, stream) for j in range(rotate)]
+    m = torch.empty((Nt, Nm), dtype=torch.float64, device="cuda")
+    d = torch.empty((Nt, Nd), dtype=torch.float64, device="cuda")
+    S.device_normals(m.data_ptr(), m.numel(), 0, 2, S.ARRAY_M, 1.0, stream.cuda_stream)
+    S.device_normals(d.data_ptr(), d.numel(), 0, 2, S.ARRAY_D, 1.0, stream.cuda_stream)
+    yF = torch.empty((Nt, Nd), dtype=torch.float64, device="cuda")
+    yA = torch.empty((Nt, Nm), dtype=torch.float64, device="cuda")
+    for p in plans:
+        p.reserve(1)
+        for op in (P.OP_F, P.OP_FADJ):
+            p.autotune(op, reps=3)
+        p.F(m, out=yF)
+        p.FT(d, out=yA)
+    torch.cuda.synchronize()
+    for p in plans:
+        p.set_kernel_timing(True)
+        p.kernel_time(P.OP_F)
+        p.kernel_time(P.OP_FADJ)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    for i in range(reps):
+        plans[i % rotate].F(m, out=yF)
+    ev[1].record()
+    for i in range(reps):
+        plans[i % rotate].FT(d, out=yA)
+    ev[2].record()
+    torch.cuda.synchronize()
+    k = {"F": [0.0, 0], "FADJ": [0.0, 0]}
+    for p in plans:
+        for op, name in ((P.OP_F, "F"), (P.OP_FADJ, "FADJ")):
+            ms, n = p.kernel_time(op)
+            k[name][0] += ms
+            k[name][1] += n
+        p.set_kernel_timing(False)
+    out = {"workload": f"p2o F and F* single RHS, Nd={Nd} Nm={Nm} Nt={Nt} ({nf} frequency "
+                       f"blocks), float64, {rotate} plans in rotation, {reps} launches per op",
+           "apply_ms": {"F": ev[0].elapsed_time(ev[1]) / reps, "FADJ": ev[1].elapsed_time(ev[2]) / reps}}
+    for name in ("F", "FADJ"):
+        ms = k[name][0] / max(k[name][1], 1)
+        nbytes = product_bytes("fp64", name, Nd, Nm, nf, n_chunks(Nd, Nm, nf, "fp64") if name == "F" else 1)
+        ach = nbytes / (ms * 1e-3) / 1e9
+        out[name] = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(ach / PEAK_HBM_GBS, 4), "avg_ms": round(ms, 5),
+                     "bytes_per_launch": nbytes}
+    for p in plans:
+        p.close()
+    del plans
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -640,7 +850,7 @@ def main():
     import p2o_synth as S
     import paper_2504_16344_amd as P
 
-    Nd, Nm, Nt = args.Nd, args.Nm, args.Nt
+    Nd, Nm, Nt, B = args.Nd, args.Nm, args.Nt, args.mrhs
     L = P.smooth_length(Nt)
     nf = L // 2 + 1
     precs = [p.strip() for p in args.precs.split(",") if p.strip()]
@@ -651,11 +861,18 @@ def main():
     d = torch.empty((Nt, Nd), dtype=torch.float64, device="cuda")
     S.device_normals(m.data_ptr(), m.numel(), 0, args.seed, S.ARRAY_M, 1.0, stream.cuda_stream)
     S.device_normals(d.data_ptr(), d.numel(), 0, args.seed, S.ARRAY_D, 1.0, stream.cuda_stream)
+    mB = dB = None
+    if B > 0:  # right-hand side 0 of the B is the single one above
+        mB = torch.empty((B, Nt, Nm), dtype=torch.float64, device="cuda")
+        dB = torch.empty((B, Nt, Nd), dtype=torch.float64, device="cuda")
+        S.device_normals(mB.data_ptr(), mB.numel(), 0, args.seed, S.ARRAY_M, 1.0, stream.cuda_stream)
+        S.device_normals(dB.data_ptr(), dB.numel(), 0, args.seed, S.ARRAY_D, 1.0, stream.cuda_stream)
     torch.cuda.synchronize()
 
+    read = read_ceiling(torch, P, args.read_gb) if args.read_gb > 0 else None
     copy = measured_copy(torch, args.copy_gb) if args.copy_gb > 0 else None
     results = {}
-    ref = None
+    ref = refB = None
     order = (["fp64"] if "fp64" in precs else []) + [p for p in precs if p != "fp64"]
     for prec in order:
         t_setup = time.perf_counter()
@@ -686,21 +903,11 @@ def main():
         msF, nF = plan.kernel_time(P.OP_F)
         msA, nA = plan.kernel_time(P.OP_FADJ)
         plan.set_kernel_timing(False)
-        # per-op apply times (not overlapped with each other)
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-        ev[0].record()
-        for _ in range(args.steps):
-            plan.F(m, out=yF)
-        ev[1].record()
-        for _ in range(args.steps):
-            plan.FT(d, out=yA)
-        ev[2].record()
-        torch.cuda.synchronize()
+        apply_ms, _ = time_ops(torch, P, plan, m, d, yF, yA, 0, args.steps)
         r = {
             "setup_s": round(t_setup, 3),
             "ms_per_step": wall * 1e3 / args.steps,
-            "apply_ms": {"F": ev[0].elapsed_time(ev[1]) / args.steps,
-                         "FADJ": ev[1].elapsed_time(ev[2]) / args.steps},
+            "apply_ms": apply_ms,
             "product_kernel_ms": {"F": msF / max(nF, 1), "FADJ": msA / max(nA, 1)},
             "product_bytes": {"F": product_bytes(prec, "F", Nd, Nm, nf, n_chunks(Nd, Nm, nf, prec)),
                               "FADJ": product_bytes(prec, "FADJ", Nd, Nm, nf, 1)},
@@ -708,12 +915,35 @@ def main():
             "autotune": tuned,
         }
         r["gbs"] = r["step_bytes"] / (r["ms_per_step"] * 1e-3) / 1e9
+        for op in ("F", "FADJ"):
+            r.setdefault("product_frac_of_peak", {})[op] = round(
+                r["product_bytes"][op] / (r["product_kernel_ms"][op] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
         if prec == "fp64":
             ref = (yF.clone(), yA.clone())
         elif ref is not None:
             eF = (torch.linalg.norm(yF - ref[0]) / torch.linalg.norm(ref[0])).item()
             eA = (torch.linalg.norm(yA - ref[1]) / torch.linalg.norm(ref[1])).item()
             r["rel_err_vs_fp64"] = {"F": eF, "FADJ": eA}
+        if B > 0 and prec in PEAK_TFLOPS and prec != "fast_bf16":
+            # B right-hand sides on the same plan: the matrix-core products
+            plan.reserve(B)
+            yFB = torch.empty((B, Nt, Nd), dtype=torch.float64, device="cuda")
+            yAB = torch.empty((B, Nt, Nm), dtype=torch.float64, device="cuda")
+            appB, kB = time_ops(torch, P, plan, mB, dB, yFB, yAB, 1, args.mrhs_steps)
+            rb = {"nrhs": B, "apply_ms": appB, "product_kernel_ms": kB,
+                  "ms_per_step": appB["F"] + appB["FADJ"],
+                  "roofline": {op: mrhs_roofline(prec, op, Nd, Nm, nf, B, kB[op])
+                               for op in ("F", "FADJ")}}
+            if prec == "fp64":
+                refB = (yFB, yAB)
+            elif refB is not None:
+                rb["rel_err_vs_fp64"] = {
+                    "F": (torch.linalg.norm(yFB - refB[0]) / torch.linalg.norm(refB[0])).item(),
+                    "FADJ": (torch.linalg.norm(yAB - refB[1]) / torch.linalg.norm(refB[1])).item()}
+            r["mrhs"] = rb
+            del yFB, yAB
+            print(f"[bench] {prec} {B} RHS: F {appB['F']:.2f} ms (product {kB['F']:.2f}), "
+                  f"F* {appB['FADJ']:.2f} ms (product {kB['FADJ']:.2f})", file=sys.stderr, flush=True)
         results[prec] = r
         plan.close()
         del plan
@@ -723,6 +953,8 @@ def main():
               f"kernels F {r['product_kernel_ms']['F']:.3f} ms F* "
               f"{r['product_kernel_ms']['FADJ']:.3f} ms, setup {t_setup:.1f} s",
               file=sys.stderr, flush=True)
+    del mB, dB, refB
+    torch.cuda.empty_cache()
 
     head = precs[0]
     h = results[head]
@@ -733,9 +965,9 @@ def main():
                          "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
                          "kernel": kname, "avg_ms": h["product_kernel_ms"][op],
                          "bytes_per_launch": h["product_bytes"][op]}
-    if copy:
+    if read:
         for r in rooflines.values():
-            r["frac_of_measured_copy"] = round(r["achieved"] / copy["gbs"], 4)
+            r["frac_of_measured_read"] = round(r["achieved"] / read["gbs"], 4)
     traffic = load_traffic()
     if traffic is not None:
         for op, r in rooflines.items():
@@ -765,12 +997,24 @@ def main():
         "roofline": rooflines[dom],
         "roofline_other": rooflines["FADJ" if dom == "F" else "F"],
         "paths": {p: {k: v for k, v in r.items()} for p, r in results.items()},
+        "measured_read": read,
         "measured_copy": copy,
     }
     if "fp64" in results and head != "fp64":
         out["speedup_vs_fp64"] = round(results["fp64"]["ms_per_step"] / h["ms_per_step"], 3)
+    if head in results and "mrhs" in results[head]:
+        hb = results[head]["mrhs"]
+        domB = max(("F", "FADJ"), key=lambda o: hb["product_kernel_ms"][o])
+        out["mrhs"] = {"nrhs": B, "precision": head, "roofline": hb["roofline"][domB],
+                       "roofline_other": hb["roofline"]["FADJ" if domB == "F" else "F"]}
+        if "fp64" in results and "mrhs" in results["fp64"]:
+            out["mrhs"]["speedup_vs_fp64"] = round(
+                results["fp64"]["mrhs"]["ms_per_step"] / hb["ms_per_step"], 3)
+    if not args.no_c2:
+        out["c2_fp64"] = c2_fp64_leg(torch, S, P)
+        print(f"[bench] 100x5000x200 fp64: {out['c2_fp64']}", file=sys.stderr, flush=True)
     if not args.no_inversion:
-        out["inversion"] = bench_inversion(torch, S, P)
+        out["inversion"] = bench_inversion(torch, S, P, cpu=not args.no_cpu_baseline)
         print(f"[bench] inversion: {out['inversion']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(torch, S, args, nf, h["step_bytes"], env)

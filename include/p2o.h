@@ -424,6 +424,17 @@ const char* p2o_status_string(p2o_status s);
 /* The HIP error behind the last P2O_EHIP returned on this thread. */
 p2o_status p2o_last_hip_error(int* code);
 
+/* Measurement aid: reads `bytes` of device memory at `buf` once with the
+ * non-temporal 16-byte loads the block-product kernels stream their
+ * frequency blocks with, and nothing else, so that the caller can time the
+ * device's streaming-read ceiling (section "Peak performance" quotes the
+ * paper's kernels as a fraction of memory bandwidth).
+ *   buf    device, 16-byte aligned;  bytes a positive multiple of 16.
+ *   sink   device [1] double; written only in the (practically impossible)
+ *          case that the folded data equal a fixed pattern.
+ * Stream-ordered, allocates nothing; P2O_EINVAL on bad arguments. */
+p2o_status p2o_read_bandwidth(const void* buf, int64_t bytes, double* sink, void* stream);
+
 /* Kernel timing: when enabled, p2o_apply brackets each frequency-block
  * product kernel with HIP events on `stream`.  p2o_kernel_time reads back
  * the summed milliseconds and launch count since the last reset for

@@ -61,6 +61,7 @@ _SIGNATURES = {
     "p2o_posterior_invert": (_int, [_vp, _vp, _vp, _vp]),
     "p2o_posterior_mean_kinv": (_int, [_vp, _vp, _vp, _vp, _i64, _dbl, _vp]),
     "p2o_posterior_mean_kinv_noalloc": (_int, [_vp, _vp, _vp, _vp, _i64, _dbl, _vp]),
+    "p2o_read_bandwidth": (_int, [_vp, _i64, _vp, _vp]),
     "p2o_qoi_predict": (_int, [_vp, _i64, _i64, _vp, _vp, _i64, _vp]),
     "p2o_destroy": (None, [_vp]),
     "p2o_status_string": (_c.c_char_p, [_int]),
@@ -458,6 +459,17 @@ def qoi_predict(Q: torch.Tensor, d: torch.Tensor, stream=None) -> torch.Tensor:
     _check("p2o_qoi_predict", load_library().p2o_qoi_predict(
         Q.data_ptr(), nq, n, d.data_ptr(), q.data_ptr(), nrhs, _stream_handle(stream)))
     return q[0] if single else q
+
+
+def read_bandwidth(buf: torch.Tensor, sink: torch.Tensor, stream=None) -> None:
+    """Enqueue one streaming read of all of `buf` (a device tensor whose byte
+    size is a multiple of 16): the device's streaming-read ceiling, timed by
+    the caller.  `sink`: a device float64 tensor of at least one entry."""
+    if not buf.is_cuda or not sink.is_cuda or sink.dtype != torch.float64:
+        raise ValueError("buf and sink must be device tensors, sink float64")
+    nbytes = buf.numel() * buf.element_size()
+    _check("p2o_read_bandwidth", load_library().p2o_read_bandwidth(
+        buf.data_ptr(), nbytes, sink.data_ptr(), _stream_handle(stream)))
 
 
 class Batch:

@@ -572,6 +572,14 @@ p2o_status p2o_apply(p2o_handle h, p2o_op op, const double* x, double* y,
 
 void p2o_destroy(p2o_handle h) { free_plan(h); }
 
+p2o_status p2o_read_bandwidth(const void* buf, int64_t bytes, double* sink, void* stream) {
+  if (!buf || !sink || bytes < 16 || bytes % 16 != 0 || ((uintptr_t)buf & 15) != 0)
+    return P2O_EINVAL;
+  (void)hipGetLastError();
+  TRY_HIP(launch_read_stream(buf, bytes, sink, (hipStream_t)stream));
+  return P2O_OK;
+}
+
 const char* p2o_status_string(p2o_status s) {
   switch (s) {
     case P2O_OK: return "ok";

@@ -199,6 +199,8 @@ hipError_t launch_residual(const double* K, const double* diag, const double* D,
                            int64_t nrhs, hipStream_t s);
 hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t s);
 hipError_t launch_identity(double* X, int64_t n, hipStream_t s);  // X = I (n x n)
+// Streaming-read ceiling: reads `bytes` (a multiple of 16) of `buf` once.
+hipError_t launch_read_stream(const void* buf, int64_t bytes, double* sink, hipStream_t s);
 
 // ------------------------------------------------- dense float64 (dense.hip)
 // C[M x N] += alpha A[M x K] op(B), row-major; op(B) = B^T ([N x K]) when

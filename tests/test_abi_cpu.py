@@ -63,6 +63,7 @@ def test_setup_rejects_bad_arguments_on_host(lib):
     assert lib.p2o_posterior_invert(None, None, None, None) == 1
     assert lib.p2o_posterior_mean_kinv(None, None, None, None, 1, 1.0, None) == 1
     assert lib.p2o_posterior_mean_kinv_noalloc(None, None, None, None, 1, 1.0, None) == 1
+    assert lib.p2o_read_bandwidth(None, 16, None, None) == 1
     assert lib.p2o_kernel_time(None, 0, None, None) == 1
     assert lib.p2o_last_hip_error(None) == 1
     lib.p2o_destroy(None)
