@@ -69,6 +69,8 @@ def parse():
                     help="batch workload: device memory per wave of resident instances")
     ap.add_argument("--no-inversion", action="store_true",
                     help="skip the K-assembly / posterior-solve timing (100x5000x200)")
+    ap.add_argument("--no-batch-tune", action="store_true",
+                    help="batch workload: keep the persistent kernel's default configuration")
     ap.add_argument("--no-fp64-loop", action="store_true",
                     help="batch workload: skip the instance-by-instance float64 comparison")
     return ap.parse_args()
@@ -280,6 +282,12 @@ def bench_batch(args):
         yF = [torch.empty((int(R[i]), Nt, int(Nd[i])), dtype=torch.float64, device="cuda") for i in ids]
         yA = [torch.empty((int(R[i]), Nt, int(Nm[i])), dtype=torch.float64, device="cuda") for i in ids]
         batch = P.Batch(plans)
+        tuned = {}
+        if not args.no_batch_tune:  # the persistent kernel's tiles, timed on this wave
+            for op, name, xs, ys in ((P.OP_F, "F", [v[0] for v in vecs], yF),
+                                     (P.OP_FADJ, "FADJ", [v[1] for v in vecs], yA)):
+                c, t = batch.autotune(op, xs, ys, reps=1)
+                tuned[name] = {"chosen": c, "candidate_ms": [round(x, 3) for x in t]}
         gF = batch.capture(P.OP_F, [v[0] for v in vecs], yF)
         gA = batch.capture(P.OP_FADJ, [v[1] for v in vecs], yA)
         torch.cuda.synchronize()
@@ -302,7 +310,8 @@ def bench_batch(args):
         for j, i in enumerate(ids):
             samples[i] = (yF[j][0].cpu(), yA[j][0].cpu())
         wave_info.append({"instances": len(ids), "resident_gb": round(sum(need[i] for i in ids) / 1e9, 1),
-                          "ms_F": round(msF, 3), "ms_FADJ": round(msA, 3), "setup_s": round(setup_s, 1)})
+                          "ms_F": round(msF, 3), "ms_FADJ": round(msA, 3), "setup_s": round(setup_s, 1),
+                          "tuned": tuned})
         print(f"[batch] wave {w}: {len(ids)} instances, F {msF:.2f} ms, F* {msA:.2f} ms, "
               f"setup {setup_s:.1f} s", file=sys.stderr, flush=True)
         gF.close()

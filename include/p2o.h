@@ -202,6 +202,33 @@ p2o_status p2o_batch_create(const p2o_handle* plans, int64_t n, p2o_batch* out);
 p2o_status p2o_batch_apply(p2o_batch b, p2o_op op, const double* const* x,
                            double* const* y, const int64_t* nrhs, void* stream);
 
+/* The persistent kernel has a small table of configurations (its tiles):
+ * vector-unit rows per wavefront for F (4, 4, 2, 8), column groups per
+ * wavefront for F* (2, 2, 1, 4), and the load ring depth of the bfloat16
+ * matrix-core units (1, 2, 1, 1) for candidates 0..3.  All give the same
+ * results bit for bit (each output's sums run in the same order).
+ * p2o_batch_autotune times every candidate's product launch for `op` on
+ * these inputs (one whole apply first, then `reps` timed launches), keeps
+ * the fastest for this batch and, when P2O_TUNE_CACHE names a file, stores
+ * it there under a key of the architecture, precision class, op and a
+ * digest of every instance's (Nd, Nm, Nt, nrhs, matrix-core threshold);
+ * applies and captures of a batch with no configuration set look that key
+ * up, else use candidate 0.  Arguments as p2o_batch_apply, plus
+ *   times_ms  host array (may be NULL when max_times = 0) receiving each
+ *             candidate's mean product time in ms;
+ *   chosen    host pointer (may be NULL) receiving the chosen index.
+ * Synchronises `stream`; overwrites y. */
+p2o_status p2o_batch_autotune(p2o_batch b, p2o_op op, const double* const* x,
+                              double* const* y, const int64_t* nrhs, int reps,
+                              double* times_ms, int64_t max_times, int64_t* chosen,
+                              void* stream);
+/* Force candidate cfg (0 .. n-1) for `op`, or -1 to return to the tune
+ * cache / default; P2O_EINVAL out of range.  Host-side only. */
+p2o_status p2o_batch_set_config(p2o_batch b, p2o_op op, int64_t cfg);
+/* The configuration set for `op` (-1 if none) and the number of candidates
+ * (host pointers, may be NULL). */
+p2o_status p2o_batch_get_config(p2o_batch b, p2o_op op, int64_t* cfg, int64_t* n_candidates);
+
 /* Capture one batched apply on fixed buffers into a HIP graph (workspaces
  * are reserved before capture; the graph holds no allocation or memset).
  * p2o_graph_launch replays it on `stream`; replays read x and write y at

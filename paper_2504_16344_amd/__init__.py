@@ -81,6 +81,10 @@ _SIGNATURES = {
     "p2o_graph_launch": (_int, [_vp, _vp]),
     "p2o_graph_destroy": (None, [_vp]),
     "p2o_batch_destroy": (None, [_vp]),
+    "p2o_batch_autotune": (_int, [_vp, _int, _c.POINTER(_vp), _c.POINTER(_vp), _c.POINTER(_i64),
+                                  _int, _c.POINTER(_dbl), _i64, _c.POINTER(_i64), _vp]),
+    "p2o_batch_set_config": (_int, [_vp, _int, _i64]),
+    "p2o_batch_get_config": (_int, [_vp, _int, _c.POINTER(_i64), _c.POINTER(_i64)]),
 }
 EXPORTED_SYMBOLS = tuple(_SIGNATURES)
 
@@ -506,6 +510,27 @@ class Batch:
         _check("p2o_batch_apply", self._lib.p2o_batch_apply(self._h, op, xp, yp, nr,
                                                             _stream_handle(stream)))
         return outs
+
+    def autotune(self, op: int, xs, ys=None, reps: int = 2, stream=None):
+        """Time every configuration of the persistent kernel on these inputs
+        and keep the fastest.  Returns (chosen, per-candidate ms)."""
+        outs, xp, yp, nr = self._args(op, xs, ys)
+        n = self.config(op)[1]
+        times = (_dbl * n)()
+        chosen = _i64(-1)
+        _check("p2o_batch_autotune", self._lib.p2o_batch_autotune(
+            self._h, op, xp, yp, nr, reps, times, n, _c.byref(chosen), _stream_handle(stream)))
+        return chosen.value, list(times)
+
+    def config(self, op: int):
+        """(configuration set for op or -1, number of candidates)."""
+        c, n = _i64(0), _i64(0)
+        _check("p2o_batch_get_config", self._lib.p2o_batch_get_config(self._h, op, _c.byref(c),
+                                                                      _c.byref(n)))
+        return c.value, n.value
+
+    def set_config(self, op: int, cfg: int) -> None:
+        _check("p2o_batch_set_config", self._lib.p2o_batch_set_config(self._h, op, cfg))
 
     def capture(self, op: int, xs, ys, stream=None) -> "Graph":
         """Graph of one batched apply reading xs and writing ys (fixed buffers)."""

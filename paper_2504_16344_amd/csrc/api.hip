@@ -1188,6 +1188,7 @@ struct p2o_batch_s {
   std::vector<p2o_handle> plans;
   BatchClass cls = kClassF64;
   BatchInst* dev = nullptr;  // work table of the last p2o_batch_apply
+  int cfg[2] = {-1, -1};     // persistent-kernel configuration per op (-1: tune cache or 0)
 };
 
 struct p2o_graph_s {
@@ -1208,10 +1209,50 @@ BatchClass class_of(p2o_prec p) {
   return kClassF64;
 }
 
+// Tune-cache key of a batch: architecture, class, op and a digest (FNV-1a)
+// of every instance's shape and right-hand-side count.
+std::string batch_key(p2o_batch b, p2o_op op, const int64_t* nrhs) {
+  uint64_t hsh = 1469598103934665603ull;
+  auto mix = [&](int64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      hsh ^= (uint64_t)((v >> (8 * i)) & 0xff);
+      hsh *= 1099511628211ull;
+    }
+  };
+  for (size_t i = 0; i < b->plans.size(); ++i) {
+    const p2o_plan_s* h = b->plans[i];
+    mix(h->Nd);
+    mix(h->Nm);
+    mix(h->Nt);
+    mix(nrhs[i]);
+    mix(h->mfma_min_rhs[op]);
+  }
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, b->plans[0]->device) == hipSuccess) arch = prop.gcnArchName;
+  std::ostringstream k;
+  k << arch << "|batch|class" << (int)b->cls << "|op" << (int)op << "|n" << b->plans.size()
+    << "|" << std::hex << hsh;
+  return k.str();
+}
+
+// The configuration an apply uses: the one set or tuned on this batch, else
+// a tune-cache entry for these shapes and counts, else configuration 0.
+int batch_cfg(p2o_batch b, p2o_op op, const int64_t* nrhs) {
+  if (b->cfg[op] >= 0) return b->cfg[op];
+  if (const char* path = std::getenv("P2O_TUNE_CACHE")) {
+    const auto m = read_cache(path);
+    const auto it = m.find(batch_key(b, op, nrhs));
+    if (it != m.end() && it->second >= 0 && it->second < batch_config_count()) return it->second;
+  }
+  return 0;
+}
+
 // Validate the per-instance arguments, reserve workspaces and build the
-// work table (host copy) for one batched apply.
+// work table (host copy) for one batched apply in configuration `cfg`.
 p2o_status batch_prepare(p2o_batch b, p2o_op op, const double* const* x, double* const* y,
-                         const int64_t* nrhs, std::vector<BatchInst>* table, int64_t* total) {
+                         const int64_t* nrhs, int cfg, std::vector<BatchInst>* table,
+                         int64_t* total) {
   if (!b || !x || !y || !nrhs || (op != P2O_F && op != P2O_FADJ)) return P2O_EINVAL;
   const size_t n = b->plans.size();
   table->assign(n, BatchInst{});
@@ -1232,7 +1273,7 @@ p2o_status batch_prepare(p2o_batch b, p2o_op op, const double* const* x, double*
     I.n8 = round8(op == P2O_F ? h->Nm : h->Nd);
     I.path = matrix ? kPathMatrix : kPathVector;
     I.unit_begin = units;
-    units += batch_units(b->cls, op, I.path, I.g);
+    units += batch_units(b->cls, op, I.path, I.g, cfg);
   }
   *total = units;
   return P2O_OK;
@@ -1244,11 +1285,11 @@ p2o_status batch_prepare(p2o_batch b, p2o_op op, const double* const* x, double*
 // instance's inverse transform.
 p2o_status batch_enqueue(p2o_batch b, p2o_op op, const double* const* x, double* const* y,
                          const int64_t* nrhs, const std::vector<BatchInst>& table,
-                         const BatchInst* dev_table, int64_t total, hipStream_t s) {
+                         const BatchInst* dev_table, int64_t total, int cfg, hipStream_t s) {
   const size_t n = b->plans.size();
   for (size_t i = 0; i < n; ++i)
     TRY_HIP(enqueue_forward(b->plans[i], op, x[i], nrhs[i], static_cast<char*>(b->plans[i]->ws), s));
-  TRY_HIP(launch_batch_product(b->cls, op, dev_table, (int)n, total, s));
+  TRY_HIP(launch_batch_product(b->cls, op, dev_table, (int)n, total, cfg, s));
   for (size_t i = 0; i < n; ++i)
     TRY_HIP(enqueue_inverse(b->plans[i], op, y[i], nrhs[i], 1.0,
                             static_cast<const char*>(b->plans[i]->ws), s));
@@ -1287,13 +1328,85 @@ p2o_status p2o_batch_create(const p2o_handle* plans, int64_t n, p2o_batch* out) 
 p2o_status p2o_batch_apply(p2o_batch b, p2o_op op, const double* const* x, double* const* y,
                            const int64_t* nrhs, void* stream) {
   (void)hipGetLastError();
+  if (!b || !nrhs || (op != P2O_F && op != P2O_FADJ)) return P2O_EINVAL;
   std::vector<BatchInst> table;
   int64_t total = 0;
-  TRY_ST(batch_prepare(b, op, x, y, nrhs, &table, &total));
+  const int cfg = batch_cfg(b, op, nrhs);
+  TRY_ST(batch_prepare(b, op, x, y, nrhs, cfg, &table, &total));
   hipStream_t s = (hipStream_t)stream;
   TRY_HIP(hipStreamSynchronize(s));  // the previous apply has finished reading the table
   TRY_HIP(hipMemcpy(b->dev, table.data(), sizeof(BatchInst) * table.size(), hipMemcpyHostToDevice));
-  return batch_enqueue(b, op, x, y, nrhs, table, b->dev, total, s);
+  return batch_enqueue(b, op, x, y, nrhs, table, b->dev, total, cfg, s);
+}
+
+p2o_status p2o_batch_set_config(p2o_batch b, p2o_op op, int64_t cfg) {
+  if (!b || (op != P2O_F && op != P2O_FADJ)) return P2O_EINVAL;
+  if (cfg < -1 || cfg >= batch_config_count()) return P2O_EINVAL;
+  b->cfg[op] = (int)cfg;
+  return P2O_OK;
+}
+
+p2o_status p2o_batch_get_config(p2o_batch b, p2o_op op, int64_t* cfg, int64_t* n_candidates) {
+  if (!b || (op != P2O_F && op != P2O_FADJ)) return P2O_EINVAL;
+  if (cfg) *cfg = b->cfg[op];
+  if (n_candidates) *n_candidates = batch_config_count();
+  return P2O_OK;
+}
+
+p2o_status p2o_batch_autotune(p2o_batch b, p2o_op op, const double* const* x, double* const* y,
+                              const int64_t* nrhs, int reps, double* times_ms, int64_t max_times,
+                              int64_t* chosen, void* stream) {
+  if (!b || !nrhs || (op != P2O_F && op != P2O_FADJ) || reps < 1 || max_times < 0 ||
+      (max_times > 0 && !times_ms))
+    return P2O_EINVAL;
+  (void)hipGetLastError();
+  hipStream_t s = (hipStream_t)stream;
+  const int n = batch_config_count();
+  hipEvent_t e0, e1;
+  TRY_HIP(hipEventCreate(&e0));
+  TRY_HIP(hipEventCreate(&e1));
+  int best = -1;
+  float best_ms = 0.f;
+  p2o_status st = P2O_OK;
+  for (int c = 0; c < n && st == P2O_OK; ++c) {
+    std::vector<BatchInst> table;
+    int64_t total = 0;
+    st = batch_prepare(b, op, x, y, nrhs, c, &table, &total);
+    if (st != P2O_OK) break;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess)
+      e = hipMemcpy(b->dev, table.data(), sizeof(BatchInst) * table.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { st = hip_fail(e); break; }
+    // one whole apply (transforms included) leaves valid inputs in the
+    // workspaces, then the product launch alone is timed
+    st = batch_enqueue(b, op, x, y, nrhs, table, b->dev, total, c, s);
+    if (st != P2O_OK) break;
+    e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r)
+      e = launch_batch_product(b->cls, op, b->dev, (int)b->plans.size(), total, c, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) { st = hip_fail(e); break; }
+    ms /= (float)reps;
+    if (c < max_times) times_ms[c] = ms;
+    if (best < 0 || ms < best_ms) {
+      best = c;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != P2O_OK) return st;
+  b->cfg[op] = best;
+  if (chosen) *chosen = best;
+  if (const char* path = std::getenv("P2O_TUNE_CACHE")) {
+    auto m = read_cache(path);
+    m[batch_key(b, op, nrhs)] = best;
+    write_cache(path, m);
+  }
+  return P2O_OK;
 }
 
 p2o_status p2o_graph_capture(p2o_batch b, p2o_op op, const double* const* x, double* const* y,
@@ -1301,9 +1414,11 @@ p2o_status p2o_graph_capture(p2o_batch b, p2o_op op, const double* const* x, dou
   if (!out) return P2O_EINVAL;
   *out = nullptr;
   (void)hipGetLastError();
+  if (!b || !nrhs || (op != P2O_F && op != P2O_FADJ)) return P2O_EINVAL;
   std::vector<BatchInst> table;
   int64_t total = 0;
-  TRY_ST(batch_prepare(b, op, x, y, nrhs, &table, &total));
+  const int cfg = batch_cfg(b, op, nrhs);
+  TRY_ST(batch_prepare(b, op, x, y, nrhs, cfg, &table, &total));
   TRY_HIP(hipStreamSynchronize((hipStream_t)stream));
   auto* g = new (std::nothrow) p2o_graph_s;
   if (!g) return P2O_ENOMEM;
@@ -1315,7 +1430,7 @@ p2o_status p2o_graph_capture(p2o_batch b, p2o_op op, const double* const* x, dou
   p2o_status st = P2O_OK;
   if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    st = batch_enqueue(b, op, x, y, nrhs, table, g->dev, total, cs);
+    st = batch_enqueue(b, op, x, y, nrhs, table, g->dev, total, cfg, cs);
     const hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
     if (st == P2O_OK && e2 != hipSuccess) e = e2;
   }

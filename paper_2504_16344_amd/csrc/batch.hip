@@ -16,11 +16,16 @@
 namespace p2o {
 namespace {
 
-constexpr int kRowsV = 4;   // vector-unit rows per wavefront (F)
-constexpr int kColsV = 2;   // vector-unit column groups per wavefront (F*)
-// Load ring depth of the matrix-core units here: this kernel inlines every
-// path, and a shallower ring keeps the largest one within 256 registers.
-constexpr int kBatchRing = 2;
+// Tunable configurations of the persistent kernel: vector-unit rows per
+// wavefront (F), vector-unit column groups per wavefront (F*), and the load
+// ring depth of the bfloat16 matrix-core units (the kernel inlines every
+// path, so the ring decides whether the largest one fits 256 registers
+// without spilling).  p2o_batch_autotune times them on the batch itself.
+struct BatchCfg {
+  int rows_v, cols_v, ring;
+};
+constexpr BatchCfg kBatchCfgs[] = {{4, 2, 1}, {4, 2, 2}, {2, 1, 1}, {8, 4, 1}};
+constexpr int kBatchCfgCount = sizeof(kBatchCfgs) / sizeof(kBatchCfgs[0]);
 
 template <int CLS>
 struct ClassTraits;
@@ -53,13 +58,16 @@ __host__ __device__ constexpr int class_tile(int cls) {
 
 // Vector-path wave units of one instance (a workgroup unit is
 // threads / 64 of them).
-__device__ __forceinline__ int64_t vector_wave_units(p2o_op op, const GemvShape& g) {
-  if (op == P2O_F) return g.nf * ((g.Nd + kRowsV - 1) / kRowsV) * g.n_pc;
-  return g.nf * ((g.Nm + 64 * kColsV - 1) / (64 * kColsV));
+__host__ __device__ __forceinline__ int64_t vector_wave_units(p2o_op op, const GemvShape& g,
+                                                              int rows_v, int cols_v) {
+  if (op == P2O_F) return g.nf * ((g.Nd + rows_v - 1) / rows_v) * g.n_pc;
+  return g.nf * ((g.Nm + 64 * cols_v - 1) / (64 * cols_v));
 }
 
-template <int CLS>
+template <int CLS, int CFG>
 __device__ __forceinline__ void rows_unit(const BatchInst& I, int64_t u, void* lds) {
+  constexpr int kRowsV = kBatchCfgs[CFG].rows_v;
+  constexpr int kBatchRing = kBatchCfgs[CFG].ring;
   const GemvShape& g = I.g;
   if (I.path == kPathMatrix) {
     constexpr int64_t tile = class_tile(CLS);
@@ -94,7 +102,7 @@ __device__ __forceinline__ void rows_unit(const BatchInst& I, int64_t u, void* l
     return;
   }
   const int64_t wu = u * (class_threads<CLS>() / 64) + wave_id_in_block();
-  if (wu >= vector_wave_units(P2O_F, g)) return;
+  if (wu >= vector_wave_units(P2O_F, g, kRowsV, 1)) return;
   const int64_t nsg = (g.Nd + kRowsV - 1) / kRowsV, rest = wu / nsg;
   const int64_t sg = wu % nsg, k = rest % g.nf, pc = rest / g.nf;
   if constexpr (CLS == kClassF64) {
@@ -116,8 +124,10 @@ __device__ __forceinline__ void rows_unit(const BatchInst& I, int64_t u, void* l
   }
 }
 
-template <int CLS>
+template <int CLS, int CFG>
 __device__ __forceinline__ void cols_unit(const BatchInst& I, int64_t u, void* lds) {
+  constexpr int kColsV = kBatchCfgs[CFG].cols_v;
+  constexpr int kBatchRing = kBatchCfgs[CFG].ring;
   const GemvShape& g = I.g;
   if (I.path == kPathMatrix) {
     constexpr int64_t tile = class_tile(CLS);
@@ -145,7 +155,7 @@ __device__ __forceinline__ void cols_unit(const BatchInst& I, int64_t u, void* l
     return;
   }
   const int64_t wu = u * (class_threads<CLS>() / 64) + wave_id_in_block();
-  if (wu >= vector_wave_units(P2O_FADJ, g)) return;
+  if (wu >= vector_wave_units(P2O_FADJ, g, 1, kColsV)) return;
   const int64_t npg = (g.Nm + 64 * kColsV - 1) / (64 * kColsV);
   const int64_t pg = wu % npg, k = wu / npg;
   if constexpr (CLS == kClassF64) {
@@ -169,7 +179,7 @@ __device__ __forceinline__ void cols_unit(const BatchInst& I, int64_t u, void* l
 
 // The grid is a multiple of 8 workgroups; each XCD takes a contiguous range
 // of units per round, so neighbouring tiles of one instance share its L2.
-template <int CLS, int OP>
+template <int CLS, int OP, int CFG>
 __global__ void __launch_bounds__(class_threads<CLS>())
 batch_product_kernel(const BatchInst* __restrict__ insts, int n, int64_t total) {
   __shared__ __align__(16) char lds[stage_bytes<CLS>()];
@@ -182,59 +192,71 @@ batch_product_kernel(const BatchInst* __restrict__ insts, int n, int64_t total) 
       else hi = mid - 1;
     }
     const BatchInst I = insts[lo];
-    if constexpr (OP == P2O_F) rows_unit<CLS>(I, u - I.unit_begin, lds);
-    else cols_unit<CLS>(I, u - I.unit_begin, lds);
+    if constexpr (OP == P2O_F) rows_unit<CLS, CFG>(I, u - I.unit_begin, lds);
+    else cols_unit<CLS, CFG>(I, u - I.unit_begin, lds);
   }
 }
 
-template <int CLS, int OP>
+template <int CLS, int OP, int CFG>
 hipError_t launch_one(const BatchInst* insts, int n, int64_t total, hipStream_t s) {
   int dev = 0, cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_product_kernel<CLS, OP>,
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_product_kernel<CLS, OP, CFG>,
                                                      class_threads<CLS>(), 0);
   if (e != hipSuccess) return e;
   int64_t blocks = (int64_t)std::max(1, cus) * std::max(1, per_cu);
   blocks = std::min<int64_t>(blocks, total);
   if (blocks < 1) return hipSuccess;
   blocks = (blocks + kXcds - 1) / kXcds * kXcds;
-  hipLaunchKernelGGL((batch_product_kernel<CLS, OP>), dim3((unsigned)blocks),
+  hipLaunchKernelGGL((batch_product_kernel<CLS, OP, CFG>), dim3((unsigned)blocks),
                      dim3(class_threads<CLS>()), 0, s, insts, n, total);
   return hipGetLastError();
 }
 
+template <int CLS, int CFG>
+hipError_t launch_cls(p2o_op op, const BatchInst* insts, int n, int64_t total, hipStream_t s) {
+  return op == P2O_F ? launch_one<CLS, P2O_F, CFG>(insts, n, total, s)
+                     : launch_one<CLS, P2O_FADJ, CFG>(insts, n, total, s);
+}
+
+template <int CFG>
+hipError_t launch_cfg(BatchClass cls, p2o_op op, const BatchInst* insts, int n, int64_t total,
+                      hipStream_t s) {
+  switch (cls) {
+    case kClassF64: return launch_cls<kClassF64, CFG>(op, insts, n, total, s);
+    case kClassMixedFp16: return launch_cls<kClassMixedFp16, CFG>(op, insts, n, total, s);
+    case kClassMixedBf16: return launch_cls<kClassMixedBf16, CFG>(op, insts, n, total, s);
+    case kClassFastBf16: return launch_cls<kClassFastBf16, CFG>(op, insts, n, total, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 }  // namespace
 
-int64_t batch_units(BatchClass cls, p2o_op op, int path, const GemvShape& g) {
+int batch_config_count() { return kBatchCfgCount; }
+
+int64_t batch_units(BatchClass cls, p2o_op op, int path, const GemvShape& g, int cfg) {
   if (path == kPathMatrix) {
     const int64_t tile = class_tile(cls);
     if (op == P2O_F) return g.nf * ((g.Nd + tile - 1) / tile) * g.n_pc;
     return g.nf * ((g.Nm + tile - 1) / tile);
   }
-  const int64_t waves = op == P2O_F ? g.nf * ((g.Nd + kRowsV - 1) / kRowsV) * g.n_pc
-                                    : g.nf * ((g.Nm + 64 * kColsV - 1) / (64 * kColsV));
+  const BatchCfg& c = kBatchCfgs[cfg];
+  const int64_t waves = vector_wave_units(op, g, c.rows_v, c.cols_v);
   const int64_t per = class_threads_rt(cls) / 64;
   return (waves + per - 1) / per;
 }
 
 hipError_t launch_batch_product(BatchClass cls, p2o_op op, const BatchInst* insts, int n,
-                                int64_t total_units, hipStream_t s) {
-  const bool f = op == P2O_F;
-  switch (cls) {
-    case kClassF64:
-      return f ? launch_one<kClassF64, P2O_F>(insts, n, total_units, s)
-               : launch_one<kClassF64, P2O_FADJ>(insts, n, total_units, s);
-    case kClassMixedFp16:
-      return f ? launch_one<kClassMixedFp16, P2O_F>(insts, n, total_units, s)
-               : launch_one<kClassMixedFp16, P2O_FADJ>(insts, n, total_units, s);
-    case kClassMixedBf16:
-      return f ? launch_one<kClassMixedBf16, P2O_F>(insts, n, total_units, s)
-               : launch_one<kClassMixedBf16, P2O_FADJ>(insts, n, total_units, s);
-    case kClassFastBf16:
-      return f ? launch_one<kClassFastBf16, P2O_F>(insts, n, total_units, s)
-               : launch_one<kClassFastBf16, P2O_FADJ>(insts, n, total_units, s);
+                                int64_t total_units, int cfg, hipStream_t s) {
+  static_assert(kBatchCfgCount == 4, "one launch_cfg case per configuration");
+  switch (cfg) {
+    case 0: return launch_cfg<0>(cls, op, insts, n, total_units, s);
+    case 1: return launch_cfg<1>(cls, op, insts, n, total_units, s);
+    case 2: return launch_cfg<2>(cls, op, insts, n, total_units, s);
+    case 3: return launch_cfg<3>(cls, op, insts, n, total_units, s);
   }
   return hipErrorInvalidValue;
 }

@@ -169,11 +169,14 @@ struct BatchInst {
   int path;
 };
 
-int64_t batch_units(BatchClass cls, p2o_op op, int path, const GemvShape& g);
+// Configurations of the persistent kernel (batch.hip: vector-unit tiles and
+// matrix-core ring depth); the work units of an instance depend on it.
+int batch_config_count();
+int64_t batch_units(BatchClass cls, p2o_op op, int path, const GemvShape& g, int cfg);
 // One persistent launch over all instances' units (instances sorted by
-// unit_begin, device array).
+// unit_begin, device array), in configuration `cfg`.
 hipError_t launch_batch_product(BatchClass cls, p2o_op op, const BatchInst* insts, int n,
-                                int64_t total_units, hipStream_t s);
+                                int64_t total_units, int cfg, hipStream_t s);
 
 // ------------------------------------------------------- inversion kernels
 // xh[(s - s0) ni + i - i0][k][p] (k < nf, p < Nm): spectra of the

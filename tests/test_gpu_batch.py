@@ -90,3 +90,61 @@ def test_batch_argument_errors():
     other.close()
     for p in plans:
         p.close()
+
+
+@pytest.mark.parametrize("prec", list(TOL))
+def test_every_batch_configuration_is_bitwise_equal(prec):
+    """Each configuration of the persistent kernel (vector-unit tiles,
+    matrix-core ring depth) gives the same bits as configuration 0 and as the
+    single-plan applies, for both ops."""
+    print(f"\n[batch cfg] prec={prec}", flush=True)
+    cases, plans = _setup(prec, seed=70)
+    batch = P.Batch(plans)
+    n = batch.config(P.OP_F)[1]
+    assert n >= 2
+    for op in (P.OP_F, P.OP_FADJ):
+        xs = [dev(c[1] if op == P.OP_F else c[2]) for c in cases]
+        singles = [p.apply(op, x) for p, x in zip(plans, xs)]
+        for cfg in range(n):
+            batch.set_config(op, cfg)
+            assert batch.config(op)[0] == cfg
+            ys = batch.apply(op, xs)
+            torch.cuda.synchronize()
+            for y, s1 in zip(ys, singles):
+                assert torch.equal(y, s1), (op, cfg)
+        print(f"  op={op}: {n} configurations equal", flush=True)
+    with pytest.raises(P.P2OError) as e:
+        batch.set_config(P.OP_F, n)
+    assert e.value.status == 1
+    batch.close()
+    for p in plans:
+        p.close()
+
+
+def test_batch_autotune_and_cache(tmp_path, monkeypatch):
+    """The autotuner times every configuration, keeps a valid one, stores it
+    in the tune cache, and a new batch of the same shapes picks it up from
+    there (its results unchanged)."""
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("P2O_TUNE_CACHE", str(cache))
+    cases, plans = _setup("mixed_bf16", seed=80)
+    batch = P.Batch(plans)
+    for op in (P.OP_F, P.OP_FADJ):
+        xs = [dev(c[1] if op == P.OP_F else c[2]) for c in cases]
+        chosen, times = batch.autotune(op, xs, reps=1)
+        print(f"\n  op={op} chosen {chosen} times {times}", flush=True)
+        assert 0 <= chosen < len(times) and all(t > 0 for t in times)
+        assert batch.config(op)[0] == chosen
+        ref = batch.apply(op, xs)
+        fresh = P.Batch(plans)
+        assert fresh.config(op)[0] == -1  # nothing set: the cache decides at apply time
+        ys = fresh.apply(op, xs)
+        torch.cuda.synchronize()
+        for y, r in zip(ys, ref):
+            assert torch.equal(y, r)
+        fresh.close()
+    text = cache.read_text()
+    assert "|batch|" in text
+    batch.close()
+    for p in plans:
+        p.close()
