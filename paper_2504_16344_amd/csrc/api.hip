@@ -981,7 +981,8 @@ p2o_status p2o_posterior_solve(p2o_handle h, double* K, const double* d,
   const int64_t n = h->Nt * h->Nd;
   const int64_t nchunks = (n + 1023) / 1024;
   DevBufs bufs;
-  void *diag, *info, *x, *r, *rows, *psolve, *psymv;
+  void *diag, *info, *x, *r, *rows, *psolve, *psymv, *pchol;
+  TRY_HIP(bufs.alloc(&pchol, cholesky_scratch_bytes(n)));
   TRY_HIP(bufs.alloc(&diag, n * 8));
   TRY_HIP(bufs.alloc(&info, 8));
   TRY_HIP(bufs.alloc(&x, (size_t)nrhs * n * 8));
@@ -992,7 +993,7 @@ p2o_status p2o_posterior_solve(p2o_handle h, double* K, const double* d,
   const int64_t minus_one = -1;
   TRY_HIP(hipMemcpyAsync(info, &minus_one, 8, hipMemcpyHostToDevice, s));
   TRY_HIP(launch_copy_diagonal(K, static_cast<double*>(diag), n, s));
-  TRY_HIP(launch_cholesky(K, n, static_cast<int64_t*>(info), s));
+  TRY_HIP(launch_cholesky(K, n, static_cast<int64_t*>(info), static_cast<double*>(pchol), s));
   int64_t piv = -1;
   TRY_HIP(hipMemcpyAsync(&piv, info, 8, hipMemcpyDeviceToHost, s));
   TRY_HIP(hipStreamSynchronize(s));

@@ -104,92 +104,176 @@ symmetrize(double* __restrict__ K, int64_t n, int64_t T, int mirror) {
 }
 
 // ------------------------------------------------------------ Cholesky
-// One Cholesky step on the bs x bs diagonal block at (j0, j0) and the kNb
-// rows of the column below it that this work-group owns (one wavefront,
-// lane i owning row i of each LDS tile).  Every work-group factors the
-// diagonal block itself (the redundant work is a few microseconds and saves
-// a launch and a serialised step per block); work-group 0 writes it back
-// and records the first non-positive (or NaN) pivot in *info.
-//   factor: at step k every lane reads the pivot, lane k stores its square
-//           root, lanes i > k divide their entry k by it (column k of L),
-//           then subtract L_ik L_jk from their entries k < j <= i;
-//   solve:  each owned row b of the column panel becomes b L11^{-T},
-//           column by column.
-// Tiles are loaded coalesced (row u, column = lane), all loads unconditional
-// with clamped addresses.
-__global__ void __launch_bounds__(64)
-potrf_trsm(double* __restrict__ K, int64_t n, int64_t j0, int bs, int64_t* __restrict__ info) {
-  __shared__ double a[kNb][kNb + 1];
-  __shared__ double x[kNb][kNb + 1];
-  const int lane = threadIdx.x;
-  const int cl = min(lane, bs - 1);
-#pragma unroll 16
-  for (int u = 0; u < kNb; ++u) {
-    const double v = K[(j0 + min(u, bs - 1)) * n + j0 + cl];
-    a[u][lane] = (lane <= u) ? v : 0.0;
-  }
-  const int64_t r0 = j0 + bs + (int64_t)blockIdx.x * kNb;
-  const int rows = (int)max<int64_t>(0, min<int64_t>(kNb, n - r0));
-  if (rows > 0) {  // uniform across the work-group
-#pragma unroll 16
-    for (int u = 0; u < kNb; ++u) x[u][lane] = K[(r0 + min(u, rows - 1)) * n + j0 + cl];
+// Diagonal step of the blocked Cholesky, once per block: the bs x bs
+// diagonal block at (j0, j0) is factored in place (lower triangle) and its
+// inverse W = L11^{-1} written to W[64][64] (row-major, zero above the
+// diagonal and outside bs x bs), so that the column panel below becomes a
+// matrix product L21 = A21 W^T on the matrix cores instead of a serial
+// substitution per row.  One work-group of 256 threads, the block in LDS
+// (padded with the identity, so padded entries stay finite), worked in
+// 16 x 16 sub-blocks so the serial chains are 16 steps long:
+//   for each sub-block column kb: wavefront 0 factors the diagonal
+//   sub-block (lane r keeps row r in registers; column k goes through LDS)
+//   and inverts it (lane c forms column c by substitution); then all
+//   threads form the sub-blocks below it as products with that inverse and
+//   update the trailing lower triangle;
+//   then the off-diagonal sub-blocks of the inverse, block row by block row:
+//   W_ij = -W_ii (sum_{j <= k < i} L_ik W_kj).
+// The first non-positive (or NaN) pivot goes to *info.
+constexpr int kSb = 16;               // sub-block
+constexpr int kNsb = kNb / kSb;       // sub-blocks per side
+__global__ void __launch_bounds__(256)
+potrf_diag_inv(double* __restrict__ K, int64_t n, int64_t j0, int bs, double* __restrict__ W,
+               int64_t* __restrict__ info) {
+  __shared__ double a[kNb][kNb + 1];   // the block, then L
+  __shared__ double w[kNb][kNb + 1];   // L^{-1}
+  __shared__ double colk[kSb];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int idx = tid; idx < kNb * kNb; idx += 256) {
+    const int u = idx / kNb, v = idx % kNb;
+    const double x = K[(j0 + min(u, bs - 1)) * n + j0 + min(v, bs - 1)];
+    a[u][v] = (u < bs && v < bs) ? (v <= u ? x : 0.0) : (u == v ? 1.0 : 0.0);
+    w[u][v] = 0.0;
   }
   __syncthreads();
-  __shared__ double colk[kNb + 1];  // column k of L, the pivot; then the reciprocals
-  const double* rinv = colk;
-  {  // factor with lane's row in registers; column k of L goes through LDS
-    double r[kNb];
+  for (int kb = 0; kb < kNsb; ++kb) {
+    const int o = kb * kSb;
+    if (wave == 0 && lane < kSb) {
+      double r[kSb];  // row `lane` of the diagonal sub-block
 #pragma unroll
-    for (int j = 0; j < kNb; ++j) r[j] = a[lane][j];
+      for (int j = 0; j < kSb; ++j) r[j] = a[o + lane][o + j];
 #pragma unroll
-    for (int k = 0; k < kNb; ++k) {
-      if (k < bs) {  // uniform
-        if (lane == k) colk[kNb] = r[k];
-        __syncthreads();
-        const double d = colk[kNb];
-        if (lane == 0 && blockIdx.x == 0 && !(d > 0.0) && *info < 0) *info = j0 + k;
+      for (int k = 0; k < kSb; ++k) {
+        if (lane == k) colk[0] = r[k];
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const double d = colk[0];
+        if (lane == 0 && !(d > 0.0) && o + k < bs && *info < 0) *info = j0 + o + k;
         const double piv = sqrt(d), pinv = 1.0 / piv;
         r[k] = (lane == k) ? piv : (lane > k ? r[k] * pinv : r[k]);
+        __builtin_amdgcn_wave_barrier();
         colk[lane] = r[k];
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         const double lik = (lane > k) ? r[k] : 0.0;
 #pragma unroll
-        for (int t = k + 1; t < kNb; ++t) r[t] -= lik * colk[t];
-        __syncthreads();
+        for (int t = k + 1; t < kSb; ++t) r[t] -= lik * colk[t];
+        __builtin_amdgcn_wave_barrier();
+      }
+#pragma unroll
+      for (int j = 0; j < kSb; ++j) a[o + lane][o + j] = (j <= lane) ? r[j] : 0.0;
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      double x[kSb];  // column `lane` of the sub-block's inverse
+#pragma unroll
+      for (int i = 0; i < kSb; ++i) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < i; ++k) acc += a[o + i][o + k] * x[k];
+        const double d = a[o + i][o + i];
+        x[i] = (i < lane) ? 0.0 : (i == lane ? 1.0 / d : -acc / d);
+      }
+#pragma unroll
+      for (int i = 0; i < kSb; ++i) w[o + i][o + lane] = x[i];
+    }
+    __syncthreads();
+    const int rows = kNb - o - kSb;  // rows below the diagonal sub-block
+    if (rows > 0) {
+      // L_ik = A_ik W_kk^T: entry (rho, c) = sum_{m <= c} A[rho][o + m] W[o + c][o + m]
+      double v[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int idx = tid + 256 * q;
+        v[q] = 0.0;
+        if (idx < rows * kSb) {
+          const int rho = o + kSb + idx / kSb, c = idx % kSb;
+          double acc = 0.0;
+          for (int m = 0; m <= c; ++m) acc += a[rho][o + m] * w[o + c][o + m];
+          v[q] = acc;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int idx = tid + 256 * q;
+        if (idx < rows * kSb) a[o + kSb + idx / kSb][o + idx % kSb] = v[q];
+      }
+      __syncthreads();
+      // trailing lower triangle: A[rho][sig] -= sum_m L[rho][o + m] L[sig][o + m]
+      const int base = o + kSb;
+      for (int idx = tid; idx < rows * rows; idx += 256) {
+        const int rho = base + idx / rows, sig = base + idx % rows;
+        if (sig > rho) continue;
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < kSb; ++m) acc += a[rho][o + m] * a[sig][o + m];
+        a[rho][sig] -= acc;
+      }
+      __syncthreads();
+    }
+  }
+  // off-diagonal sub-blocks of the inverse, block row by block row
+  for (int i = 1; i < kNsb; ++i) {
+    double v[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {  // T_ij = sum_{j <= k < i} L_ik W_kj, j < i
+      const int idx = tid + 256 * q;
+      v[q] = 0.0;
+      if (idx < i * kSb * kSb) {
+        const int j = idx / (kSb * kSb), r = (idx / kSb) % kSb, c = idx % kSb;
+        double acc = 0.0;
+        for (int k = j; k < i; ++k)
+          for (int m = 0; m < kSb; ++m) acc += a[i * kSb + r][k * kSb + m] * w[k * kSb + m][j * kSb + c];
+        v[q] = acc;
       }
     }
 #pragma unroll
-    for (int j = 0; j < kNb; ++j) a[lane][j] = (j <= lane) ? r[j] : 0.0;
-    colk[lane] = 1.0 / ((lane < bs) ? a[lane][lane] : 1.0);  // diagonal reciprocals
-  }
-  __syncthreads();
-  if (blockIdx.x == 0) {
-#pragma unroll 16
-    for (int u = 0; u < kNb; ++u)
-      if (u < bs && lane <= u) K[(j0 + u) * n + j0 + lane] = a[u][lane];
-  }
-  if (rows == 0) return;
-  {  // lane's row in registers (static indices: the loops are unrolled);
-     // columns at or past bs and rows at or past `rows` carry junk and are
-     // never stored
-    double xr[kNb];
-#pragma unroll
-    for (int j = 0; j < kNb; ++j) xr[j] = x[lane][j];
-#pragma unroll
-    for (int c = 0; c < kNb; ++c) {
-      if (c < bs) {  // uniform
-        xr[c] = xr[c] * rinv[c];
-#pragma unroll
-        for (int t = c + 1; t < kNb; ++t) xr[t] -= xr[c] * a[t][c];
+    for (int q = 0; q < 3; ++q) {  // T parked where W_ij goes
+      const int idx = tid + 256 * q;
+      if (idx < i * kSb * kSb) {
+        const int j = idx / (kSb * kSb), r = (idx / kSb) % kSb, c = idx % kSb;
+        w[i * kSb + r][j * kSb + c] = v[q];
       }
     }
+    __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kNb; ++j) x[lane][j] = xr[j];
+    for (int q = 0; q < 3; ++q) {  // W_ij = -W_ii T_ij
+      const int idx = tid + 256 * q;
+      v[q] = 0.0;
+      if (idx < i * kSb * kSb) {
+        const int j = idx / (kSb * kSb), r = (idx / kSb) % kSb, c = idx % kSb;
+        double acc = 0.0;
+        for (int m = 0; m <= r; ++m) acc += w[i * kSb + r][i * kSb + m] * w[i * kSb + m][j * kSb + c];
+        v[q] = -acc;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int idx = tid + 256 * q;
+      if (idx < i * kSb * kSb) {
+        const int j = idx / (kSb * kSb), r = (idx / kSb) % kSb, c = idx % kSb;
+        w[i * kSb + r][j * kSb + c] = v[q];
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
-#pragma unroll 16
-  for (int u = 0; u < kNb; ++u)
-    if (u < rows && lane < bs) K[(r0 + u) * n + j0 + lane] = x[u][lane];
+  for (int idx = tid; idx < kNb * kNb; idx += 256) {
+    const int u = idx / kNb, v = idx % kNb;
+    if (u < bs && v <= u) K[(j0 + u) * n + j0 + v] = a[u][v];
+    W[idx] = (u < bs && v < bs) ? w[u][v] : 0.0;
+  }
+}
+
+// Dst[i][c] = Src[i][c] for i < m, c < bs (Src with leading dimension 64,
+// Dst with leading dimension n).
+__global__ void copy_panel(const double* __restrict__ src, double* __restrict__ dst, int64_t n,
+                           int64_t m, int bs) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * kNb) return;
+  const int64_t i = idx / kNb;
+  const int c = (int)(idx % kNb);
+  if (c < bs) dst[i * n + c] = src[idx];
 }
 
 // ------------------------------------------------------ triangular solves
@@ -558,29 +642,41 @@ hipError_t launch_mirror_lower(double* K, int64_t n, hipStream_t s) {
 }
 
 // Blocked right-looking Cholesky of the lower triangle, two levels: panels
-// of kPanel columns, each factored as kNb-wide blocks (diagonal block,
-// triangular solve of the column below it, update of the panel's remaining
-// columns), then one rank-kPanel update of the trailing lower triangle on
-// the float64 matrix cores.  The wide trailing update reads and writes the
-// trailing matrix kPanel / kNb times less often than block-by-block updates.
-constexpr int64_t kPanel = 256;
-hipError_t launch_cholesky(double* K, int64_t n, int64_t* info_dev, hipStream_t s) {
+// of kPanel columns, each factored as kNb-wide blocks: the diagonal block
+// factored and inverted (potrf_diag_inv), the column below it formed as the
+// product A21 L11^{-T} on the float64 matrix cores (into the scratch
+// panel, then copied back), and the panel's remaining columns updated by a
+// masked product; after the panel one rank-kPanel update of the trailing
+// lower triangle on the matrix cores.  The wide trailing update reads and
+// writes the trailing matrix kPanel / kNb times less often than
+// block-by-block updates.  scratch: cholesky_scratch_bytes(n).
+constexpr int64_t kPanel = 512;
+size_t cholesky_scratch_bytes(int64_t n) { return (size_t)(kNb * kNb + n * kNb) * sizeof(double); }
+
+hipError_t launch_cholesky(double* K, int64_t n, int64_t* info_dev, double* scratch,
+                           hipStream_t s) {
+  double* W = scratch;            // [64][64] inverse of the diagonal block
+  double* T = scratch + kNb * kNb;  // [n][64] the column panel below it
   for (int64_t p0 = 0; p0 < n; p0 += kPanel) {
     const int64_t p1 = std::min(n, p0 + kPanel);
     for (int64_t j0 = p0; j0 < p1; j0 += kNb) {
       const int bs = (int)std::min<int64_t>(kNb, p1 - j0);
       const int64_t j1 = j0 + bs, m = n - j1;
-      hipLaunchKernelGGL(potrf_trsm, dim3(m > 0 ? grid1(m, kNb) : 1), dim3(64), 0, s, K, n, j0,
-                         bs, info_dev);
+      hipLaunchKernelGGL(potrf_diag_inv, dim3(1), dim3(256), 0, s, K, n, j0, bs, W, info_dev);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
       if (m > 0) {
+        // L21 = A21 W^T (rows j1 .. n-1 of the block's columns), then back into K
+        e = launch_dgemm_nt_set(false, m, bs, bs, 1.0, K + j1 * n + j0, n, W, kNb, T, kNb, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(copy_panel, dim3(grid1(m * kNb)), dim3(256), 0, s, T, K + j1 * n + j0,
+                           n, m, bs);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
         // the panel's columns j1 .. p1 - 1, rows j1 .. n - 1 (lower part only)
-        const hipError_t e =
-            launch_dgemm_nt_lower_mask(m, p1 - j1, bs, -1.0, K + j1 * n + j0, n,
+        e = launch_dgemm_nt_lower_mask(m, p1 - j1, bs, -1.0, K + j1 * n + j0, n,
                                        K + j1 * n + j0, n, K + j1 * n + j1, n, s);
         if (e != hipSuccess) return e;
       }
-      const hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
     }
     const int64_t mt = n - p1;
     if (mt > 0) {  // trailing lower triangle -= panel panel^T

@@ -189,7 +189,11 @@ hipError_t launch_unit_spectra(const double* A, int64_t Nd, int64_t Nm, int64_t 
 hipError_t launch_add_diagonal(double* K, const double* v, int64_t n, hipStream_t s);
 hipError_t launch_symmetrize(double* K, int64_t n, hipStream_t s);    // (K + K^T) / 2
 hipError_t launch_mirror_lower(double* K, int64_t n, hipStream_t s);  // upper <- lower
-hipError_t launch_cholesky(double* K, int64_t n, int64_t* info_dev, hipStream_t s);
+// Cholesky factor of K's lower triangle in place; scratch of
+// cholesky_scratch_bytes(n) device bytes.
+hipError_t launch_cholesky(double* K, int64_t n, int64_t* info_dev, double* scratch,
+                           hipStream_t s);
+size_t cholesky_scratch_bytes(int64_t n);
 // Y[nrhs][n] <- K^{-1} Y with K's Cholesky factor in the lower triangle of K;
 // scratch: cholesky_solve_scratch(n, nrhs) bytes of device memory (the
 // forward solution and the inverted 64 x 64 diagonal blocks, two layouts).
