@@ -93,9 +93,19 @@ struct WsLayout {
 
 int64_t round8(int64_t n) { return (n + 7) / 8 * 8; }
 
+// bfloat16 operand planes: F's are stored per 32-column chunk in the
+// matrix-core slot order, F*'s in sensor order; both pitches are multiples
+// of 32 (zero-padded), so every 32-entry chunk lies inside its plane row.
+int64_t plane_pitch(const p2o_plan_s* h, p2o_op op) {
+  return ((op == P2O_F ? h->Nm : h->Nd) + 31) / 32 * 32;
+}
+int plane_slot_order(const p2o_plan_s* h, p2o_op op) {
+  return op == P2O_F ? (uses_lo(h->prec) ? 1 : 2) : 0;
+}
+
 // F : a = transformed x [nrhs][nf][Nm], b = partial spectra [nrhs][n_pc][nf][Nd]
 // F*: a = transformed x [nrhs][nf][Nd], b = product      [nrhs][nf][Nm]
-// mixed plans: c = a split into bfloat16 planes [nrhs][nf][4][round8(n_in)]
+// mixed plans: c = a split into bfloat16 planes [nrhs][nf][4][plane_pitch]
 // for the matrix-core product.
 bool use_mfma(const p2o_plan_s* h, p2o_op op, int64_t nrhs) {
   if (h->mfma_min_rhs[op] <= 0 || nrhs < h->mfma_min_rhs[op]) return false;
@@ -115,7 +125,7 @@ WsLayout ws_layout(const p2o_plan_s* h, p2o_op op, int64_t nrhs) {
   const size_t a_bytes = planes ? 0 : (size_t)nrhs * h->nf * nin * vb;
   const size_t b_bytes = (op == P2O_F) ? (size_t)nrhs * h->n_pc * h->nf * h->Nd * 16
                                        : (size_t)nrhs * h->nf * h->Nm * vb;
-  const size_t c_bytes = planes ? (size_t)nrhs * h->nf * 4 * round8(nin) * 2 : 0;
+  const size_t c_bytes = planes ? (size_t)nrhs * h->nf * 4 * plane_pitch(h, op) * 2 : 0;
   WsLayout w{};
   w.a_off = 0;
   w.b_off = align_up(a_bytes);
@@ -333,13 +343,12 @@ hipError_t launch_product(const p2o_plan_s* h, p2o_op op, void* a, void* b, void
   const Fmt16 fmt = fmt_of(h->prec);
   const bool lo = uses_lo(h->prec);
   if (mfma) {  // operand planes written by the forward transform
-    const int64_t nin = (op == P2O_F) ? h->Nm : h->Nd;
     auto* planes = static_cast<uint16_t*>(c);
     if (op == P2O_F)
       return launch_gemm_rows_bf16(h->fhat, h->scales, planes, static_cast<cpx<double>*>(b),
-                                   g, round8(nin), lo, s);
+                                   g, plane_pitch(h, op), lo, s);
     return launch_gemm_cols_bf16(h->fhat, h->scales, planes, static_cast<cpx<float>*>(b), g,
-                                 round8(nin), lo, s);
+                                 plane_pitch(h, op), lo, s);
   }
   if (op == P2O_F)
     return launch_gemv_rows_mixed(h->fhat, h->scales, static_cast<const cpx<float>*>(a),
@@ -435,7 +444,8 @@ hipError_t enqueue_forward(const p2o_plan_s* h, p2o_op op, const double* x, int6
   if (planes_path(h, op, nrhs)) {
     f.out = nullptr;
     f.planes = reinterpret_cast<uint16_t*>(ws + w.c_off);
-    f.n8 = round8(nin);
+    f.n8 = plane_pitch(h, op);
+    f.slot_order = plane_slot_order(h, op);
     f.nbins = h->nf;
     f.col_scales = (op == P2O_F) ? h->scales : nullptr;  // F's operand carries the scales
   }
@@ -1271,7 +1281,7 @@ p2o_status batch_prepare(p2o_batch b, p2o_op op, const double* const* x, double*
     I.in = ws + ((matrix && is_mixed(h->prec)) ? w.c_off : w.a_off);
     I.out = ws + w.b_off;
     I.g = GemvShape{h->nf, h->Nd, h->Nm, nrhs[i], (int)h->n_pc, h->pc_len};
-    I.n8 = round8(op == P2O_F ? h->Nm : h->Nd);
+    I.n8 = plane_pitch(h, op);
     I.path = matrix ? kPathMatrix : kPathVector;
     I.unit_begin = units;
     units += batch_units(b->cls, op, I.path, I.g, cfg);

@@ -238,7 +238,14 @@ __device__ __forceinline__ cpx<T> split_bin(const cpx<T>* buf, const cpx<T>* __r
 // Bins written as four bfloat16 planes per (batch, bin): re hi, re lo,
 // im hi, im lo (x = hi + lo, each rounded to nearest even), after the
 // optional power-of-two column scale (exact).  The block holding the last
-// columns also zeroes the padding columns ncols..n8-1.
+// columns also zeroes the padding columns ncols..n8-1.  In slot order
+// (io.slot_order), column c of each 32-column chunk goes to position
+// row_slot_position(c % 32) of that chunk.
+__device__ __forceinline__ int64_t plane_pos(int slot_order, int64_t c) {
+  if (slot_order == 0) return c;
+  return (c & ~(int64_t)31) + row_slot_position(slot_order == 1, (int)(c & 31));
+}
+
 __device__ __forceinline__ void write_planes(const cpx<float>* buf, const cpx<float>* __restrict__ tw,
                                              const int* __restrict__ perm, const FftIo& io,
                                              int logC, int N, int ncol, int64_t c0, int64_t b,
@@ -258,7 +265,7 @@ __device__ __forceinline__ void write_planes(const cpx<float>* buf, const cpx<fl
     const uint16_t rh = bf16_rne(v.x), ih = bf16_rne(v.y);
     const uint16_t rl = bf16_rne(v.x - __uint_as_float((uint32_t)rh << 16));
     const uint16_t il = bf16_rne(v.y - __uint_as_float((uint32_t)ih << 16));
-    uint16_t* o = pl + (int64_t)k * 4 * io.n8 + c0 + c;
+    uint16_t* o = pl + (int64_t)k * 4 * io.n8 + plane_pos(io.slot_order, c0 + c);
     o[0] = rh;
     o[io.n8] = rl;
     o[2 * io.n8] = ih;
@@ -268,7 +275,7 @@ __device__ __forceinline__ void write_planes(const cpx<float>* buf, const cpx<fl
     const int pad = (int)(io.n8 - io.ncols);
     for (int idx = tid; idx < (N + 1) * 4 * pad; idx += nthr) {
       const int row = idx / pad;  // k * 4 + plane
-      pl[(int64_t)row * io.n8 + io.ncols + idx % pad] = 0;
+      pl[(int64_t)row * io.n8 + plane_pos(io.slot_order, io.ncols + idx % pad)] = 0;
     }
   }
 }

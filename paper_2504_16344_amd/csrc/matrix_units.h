@@ -78,7 +78,11 @@ __device__ __forceinline__ void stage_f64_store(const cpx<double> (&v)[2 * NT], 
 template <int NT, int TH>
 constexpr int parts_per_thread() { return (256 * NT + TH - 1) / TH; }
 
-template <int NT, int TH>
+// SLOTS: F's planes, stored per 32-entry chunk in slot order (part kg of a
+// chunk holds slots 0..7 of lane group kg, and the planes are zero past the
+// contraction up to a multiple of 32), so a chunk is valid as a whole; F*'s
+// planes are in sensor order and a part is valid if it starts before `end`.
+template <int NT, int TH, bool SLOTS>
 __device__ __forceinline__ void stage_planes_load(const uint16_t* __restrict__ planes,
                                                   int64_t nf, int64_t k, int64_t n8, int64_t b0,
                                                   int nb, int64_t base, int64_t end,
@@ -88,61 +92,30 @@ __device__ __forceinline__ void stage_planes_load(const uint16_t* __restrict__ p
     const int e = threadIdx.x + TH * i;
     const int part = e & 3, plane = (e >> 2) & 3, b = e >> 4;
     const int64_t q = base + 8 * part;
-    const bool ok = e < 256 * NT && b < nb && q < end;
+    const bool ok = e < 256 * NT && b < nb && (SLOTS ? base : q) < end;
     v[i] = ld16(planes + (ok ? (((b0 + b) * nf + k) * 4 + plane) * n8 + q : 0));
   }
 }
 
+template <bool SLOTS>
 __device__ __forceinline__ u4v stage_part(const u4v& v, int e, int nb, int64_t base,
                                           int64_t end) {
-  const bool ok = (e >> 4) < nb && base + 8 * (e & 3) < end;
+  const bool ok = (e >> 4) < nb && (SLOTS ? base : base + 8 * (e & 3)) < end;
   return ok ? v : (u4v){0, 0, 0, 0};
 }
 
-// F*'s layout: s[(plane * 4 + part) * (16 NT + 1) + b] holds sensors
-// base + 8 part .. + 7 of one plane.
-template <int NT, int TH>
-__device__ __forceinline__ void stage_planes_store_cols(const u4v (&v)[parts_per_thread<NT, TH>()],
-                                                        int nb, int64_t base, int64_t end,
-                                                        u4v* s) {
+// Stage layout: s[(plane * 4 + part) * (16 NT + 1) + b] holds part `part`
+// of one plane (F*: sensors base + 8 part .. + 7; F: slots 0..7 of lane
+// group `part`).
+template <int NT, int TH, bool SLOTS>
+__device__ __forceinline__ void stage_planes_store(const u4v (&v)[parts_per_thread<NT, TH>()],
+                                                   int nb, int64_t base, int64_t end, u4v* s) {
   constexpr int PP = NT * 16 + 1;
 #pragma unroll
   for (int i = 0; i < parts_per_thread<NT, TH>(); ++i) {
     const int e = threadIdx.x + TH * i;
     if (256 * NT % TH == 0 || e < 256 * NT)
-      s[(((e >> 2) & 3) * 4 + (e & 3)) * PP + (e >> 4)] = stage_part(v[i], e, nb, base, end);
-  }
-}
-
-// Entry of matrix-core slot j (0..7) of lane group kg within a 32-entry
-// chunk, for F's bfloat16 products: the 4 lane groups of a row read one
-// contiguous 64-byte span per load (hi+lo entries are 8 bytes, hi-only 4).
-template <bool LO>
-__device__ __forceinline__ int row_slot_entry(int kg, int j) {
-  return LO ? 8 * (j >> 1) + 2 * kg + (j & 1) : 16 * (j >> 2) + 4 * kg + (j & 3);
-}
-
-// F's layout, slot order: s[(plane * 4 + kg) * (16 NT + 1) + b] holds the 8
-// values of slots 0..7 of lane group kg; each loaded part (8 consecutive
-// entries) is scattered as 4 pairs.
-template <int NT, bool LO, int TH>
-__device__ __forceinline__ void stage_planes_store_rows(const u4v (&v)[parts_per_thread<NT, TH>()],
-                                                        int nb, int64_t base, int64_t end,
-                                                        u4v* s) {
-  constexpr int PP = NT * 16 + 1;
-#pragma unroll
-  for (int i = 0; i < parts_per_thread<NT, TH>(); ++i) {
-    const int e = threadIdx.x + TH * i;
-    if (!(256 * NT % TH == 0 || e < 256 * NT)) continue;
-    const int part = e & 3, plane = (e >> 2) & 3, b = e >> 4;
-    const u4v x = stage_part(v[i], e, nb, base, end);
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {  // pair of chunk entries o, o + 1
-      const int o = 8 * part + 2 * u;
-      const int kgd = LO ? u : (o & 15) >> 2;
-      const int w = LO ? part : 2 * (o >> 4) + ((o & 3) >> 1);
-      reinterpret_cast<uint32_t*>(s + (plane * 4 + kgd) * PP + b)[w] = x[u];
-    }
+      s[(((e >> 2) & 3) * 4 + (e & 3)) * PP + (e >> 4)] = stage_part<SLOTS>(v[i], e, nb, base, end);
   }
 }
 
@@ -205,7 +178,7 @@ __device__ __forceinline__ void load_row_slots(const uint32_t* __restrict__ Arow
   } else {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int64_t e = base + row_slot_entry<LO>(kg, j);
+      const int64_t e = base + row_slot_entry(LO, kg, j);
       const uint32_t* at = Arow + (e < end ? e : 0) * WPE;
       w0[j] = __builtin_nontemporal_load(at);
       w1[j] = LO ? __builtin_nontemporal_load(at + 1) : 0u;
@@ -397,16 +370,16 @@ __device__ __forceinline__ BlockOps unpack_block(const uint32_t (&w0)[8], const 
 // 2^8 and more times larger, the matrix cores lose their low bits with a
 // bias toward minus infinity (measured on gfx950), which over thousands of
 // steps adds up coherently; summed among themselves they do not.
-template <int NT, bool LO>
-__device__ __forceinline__ void rows_bf16_products(const BlockOps& a, const u4v* xs, int kg,
-                                                   int col, f4v (&tr)[NT], f4v (&ti)[NT],
-                                                   f4v (&sr)[NT], f4v (&si)[NT]) {
-  constexpr int PP = NT * 16 + 1;
+// xop(plane, t) returns this lane's operand of vector plane `plane` (re hi,
+// re lo, im hi, im lo) for right-hand-side tile t.
+template <int NT, bool LO, typename XOp>
+__device__ __forceinline__ void rows_bf16_products(const BlockOps& a, XOp xop, f4v (&tr)[NT],
+                                                   f4v (&ti)[NT], f4v (&sr)[NT],
+                                                   f4v (&si)[NT]) {
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    const int b = t * 16 + col;
-    const u4v xrh = xs[(0 * 4 + kg) * PP + b], xrl = xs[(1 * 4 + kg) * PP + b];
-    const u4v xih = xs[(2 * 4 + kg) * PP + b], xil = xs[(3 * 4 + kg) * PP + b];
+    const u4v xrh = xop(0, t), xrl = xop(1, t);
+    const u4v xih = xop(2, t), xil = xop(3, t);
     tr[t] = mma(a.hr, xrh, tr[t]);
     ti[t] = mma(a.hr, xih, ti[t]);
     sr[t] = mma(a.hr, xrl, sr[t]);
@@ -424,21 +397,43 @@ __device__ __forceinline__ void rows_bf16_products(const BlockOps& a, const u4v*
   }
 }
 
+// The F chunk for U row sub-tiles that share the vector operands: the
+// operands of tile t are read once, and each sub-tile's accumulators get
+// exactly the sequence of rows_bf16_products.
+template <int NT, bool LO, int U, typename XOp>
+__device__ __forceinline__ void rows_bf16_products_sub(const BlockOps (&a)[U], XOp xop,
+                                                       f4v (&tr)[U][NT], f4v (&ti)[U][NT],
+                                                       f4v (&sr)[U][NT], f4v (&si)[U][NT]) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const u4v x0 = xop(0, t), x1 = xop(1, t), x2 = xop(2, t), x3 = xop(3, t);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      f4v r1[1] = {tr[u][t]}, i1[1] = {ti[u][t]}, s1[1] = {sr[u][t]}, j1[1] = {si[u][t]};
+      rows_bf16_products<1, LO>(
+          a[u], [&](int pl, int) { return pl == 0 ? x0 : pl == 1 ? x1 : pl == 2 ? x2 : x3; },
+          r1, i1, s1, j1);
+      tr[u][t] = r1[0];
+      ti[u][t] = i1[0];
+      sr[u][t] = s1[0];
+      si[u][t] = j1[0];
+    }
+  }
+}
+
 // F* chunk: x[b] += conj(f) d[b]: re = dr fr + di fi, im = di fr - dr fi.
 // As in the F chunk, the hi x hi products go to xr / xi and the hi x lo and
 // lo x hi products to their own accumulators sr / si (the matrix cores'
 // biased rounding of small addends would otherwise add up over the sensor
 // contraction; F* contractions are as long as N_d).
-template <int MT, bool LO>
-__device__ __forceinline__ void cols_bf16_products(const BlockOps& f, const u4v* ds, int kg,
-                                                   int col, f4v (&xr)[MT], f4v (&xi)[MT],
-                                                   f4v (&sr)[MT], f4v (&si)[MT]) {
-  constexpr int PP = MT * 16 + 1;
+template <int MT, bool LO, typename DOp>
+__device__ __forceinline__ void cols_bf16_products(const BlockOps& f, DOp dop, f4v (&xr)[MT],
+                                                   f4v (&xi)[MT], f4v (&sr)[MT],
+                                                   f4v (&si)[MT]) {
 #pragma unroll
   for (int t = 0; t < MT; ++t) {
-    const int b = t * 16 + col;
-    const u4v drh = ds[(0 * 4 + kg) * PP + b], drl = ds[(1 * 4 + kg) * PP + b];
-    const u4v dih = ds[(2 * 4 + kg) * PP + b], dil = ds[(3 * 4 + kg) * PP + b];
+    const u4v drh = dop(0, t), drl = dop(1, t);
+    const u4v dih = dop(2, t), dil = dop(3, t);
     xr[t] = mma(drh, f.hr, xr[t]);
     xi[t] = mma(dih, f.hr, xi[t]);
     sr[t] = mma(drl, f.hr, sr[t]);
@@ -452,6 +447,79 @@ __device__ __forceinline__ void cols_bf16_products(const BlockOps& f, const u4v*
       si[t] = mma(dih, f.lr, si[t]);
       sr[t] = mma(dih, f.li, sr[t]);
       si[t] = mma(drh, f.nli, si[t]);
+    }
+  }
+}
+
+// Output of F's bfloat16 unit: rows row0 + 4 kg + i of right-hand sides
+// b0 + 16 t + col, the two accumulator parts added in float64.
+template <int NT>
+__device__ __forceinline__ void rows_bf16_store(cpx<double>* __restrict__ P, const GemvShape& g,
+                                                int64_t b0, int nb, int64_t k, int64_t pc,
+                                                int64_t row0, int kg, int col,
+                                                const f4v (&tr)[NT], const f4v (&ti)[NT],
+                                                const f4v (&sr)[NT], const f4v (&si)[NT]) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int b = t * 16 + col;
+    if (b >= nb) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t s = row0 + 4 * kg + i;
+      if (s < g.Nd)
+        P[(((b0 + b) * g.n_pc + pc) * g.nf + k) * g.Nd + s] = {
+            (double)tr[t][i] + (double)sr[t][i], (double)ti[t][i] + (double)si[t][i]};
+    }
+  }
+}
+
+// Output of F*'s bfloat16 unit: column p for right-hand sides b0 + 16 t +
+// 4 kg + i; the two parts added in float64, scaled by the column's
+// sub-block scale sc (a power of two), rounded once.
+__device__ __forceinline__ float col_scale(const float* __restrict__ scales, const GemvShape& g,
+                                           int64_t k, int64_t p) {
+  const int64_t ntiles = (g.Nm + kScaleTile - 1) / kScaleTile;
+  return p < g.Nm ? scales[k * ntiles + p / kScaleTile] : 0.0f;
+}
+
+template <int MT>
+__device__ __forceinline__ void cols_bf16_store(float sc, cpx<float>* __restrict__ Y,
+                                                const GemvShape& g, int64_t b0, int nb, int64_t k,
+                                                int64_t p, int kg, const f4v (&xr)[MT],
+                                                const f4v (&xi)[MT], const f4v (&sr)[MT],
+                                                const f4v (&si)[MT]) {
+  if (p >= g.Nm) return;
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int b = t * 16 + 4 * kg + i;
+      if (b < nb)
+        Y[((b0 + b) * g.nf + k) * g.Nm + p] = {
+            (float)(((double)xr[t][i] + (double)sr[t][i]) * sc),
+            (float)(((double)xi[t][i] + (double)si[t][i]) * sc)};
+    }
+}
+
+// The F* chunk for U column sub-tiles sharing the data operands (see
+// rows_bf16_products_sub).
+template <int MT, bool LO, int U, typename DOp>
+__device__ __forceinline__ void cols_bf16_products_sub(const BlockOps (&f)[U], DOp dop,
+                                                       f4v (&xr)[U][MT], f4v (&xi)[U][MT],
+                                                       f4v (&sr)[U][MT], f4v (&si)[U][MT]) {
+#pragma unroll
+  for (int t = 0; t < MT; ++t) {
+    const u4v d0 = dop(0, t), d1 = dop(1, t), d2 = dop(2, t), d3 = dop(3, t);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      f4v r1[1] = {xr[u][t]}, i1[1] = {xi[u][t]}, s1[1] = {sr[u][t]}, j1[1] = {si[u][t]};
+      cols_bf16_products<1, LO>(
+          f[u], [&](int pl, int) { return pl == 0 ? d0 : pl == 1 ? d1 : pl == 2 ? d2 : d3; },
+          r1, i1, s1, j1);
+      xr[u][t] = r1[0];
+      xi[u][t] = i1[0];
+      sr[u][t] = s1[0];
+      si[u][t] = j1[0];
     }
   }
 }
@@ -489,11 +557,11 @@ __device__ __forceinline__ void mfma_rows_bf16_wg(const uint32_t* __restrict__ A
   u4v xv[RING][PER];
 #pragma unroll
   for (int d = 0; d < RING; ++d)
-    stage_planes_load<NT, kBf16Threads>(Xs, g.nf, k, n8, b0, nb, p0 + 32 * d, d < nch ? p1 : 0, xv[d]);
+    stage_planes_load<NT, kBf16Threads, true>(Xs, g.nf, k, n8, b0, nb, p0 + 32 * d, d < nch ? p1 : 0, xv[d]);
 #pragma unroll
   for (int d = 0; d < RING; ++d)
     load_row_slots<LO, VEC>(Arow, p0 + 32 * d, kg, d < nch ? p1 : 0, r0[d], r1[d]);
-  stage_planes_store_rows<NT, LO, kBf16Threads>(xv[0], nb, p0, p1, sx);
+  stage_planes_store<NT, kBf16Threads, true>(xv[0], nb, p0, p1, sx);
   __syncthreads();
   // the main loop runs whole ring turns (straight-line, so the compiler's
   // waits track each slot exactly), the tail the remaining chunks
@@ -501,13 +569,15 @@ __device__ __forceinline__ void mfma_rows_bf16_wg(const uint32_t* __restrict__ A
     const int64_t base = p0 + 32 * c;
     const BlockOps a = unpack_block<LO>(r0[d], r1[d]);
     const int64_t ahead = base + 32 * RING, aend = c + RING < nch ? p1 : 0;
-    stage_planes_load<NT, kBf16Threads>(Xs, g.nf, k, n8, b0, nb, ahead, aend, xv[d]);
+    stage_planes_load<NT, kBf16Threads, true>(Xs, g.nf, k, n8, b0, nb, ahead, aend, xv[d]);
     load_row_slots<LO, VEC>(Arow, ahead, kg, aend, r0[d], r1[d]);
     __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
-    rows_bf16_products<NT, LO>(a, sx + (c & 1) * BUF, kg, col, tr, ti, sr, si);
+    const u4v* xs = sx + (c & 1) * BUF;
+    rows_bf16_products<NT, LO>(
+        a, [&](int pl, int t) { return xs[(pl * 4 + kg) * PP + t * 16 + col]; }, tr, ti, sr, si);
     __builtin_amdgcn_sched_barrier(0);  // the store waits for its loads: after the products
-    stage_planes_store_rows<NT, LO, kBf16Threads>(xv[(d + 1) % RING], nb, base + 32, c + 1 < nch ? p1 : 0,
-                                    sx + ((c + 1) & 1) * BUF);
+    stage_planes_store<NT, kBf16Threads, true>(xv[(d + 1) % RING], nb, base + 32,
+                                               c + 1 < nch ? p1 : 0, sx + ((c + 1) & 1) * BUF);
     __syncthreads();
   };
   const int64_t nfull = nch / RING * RING;
@@ -518,18 +588,7 @@ __device__ __forceinline__ void mfma_rows_bf16_wg(const uint32_t* __restrict__ A
 #pragma unroll
   for (int d = 0; d < RING - 1; ++d)
     if (nfull + d < nch) step(nfull + d, d);
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int b = t * 16 + col;
-    if (b >= nb) continue;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t s = row0 + 4 * kg + i;
-      if (s < g.Nd)
-        P[(((b0 + b) * g.n_pc + pc) * g.nf + k) * g.Nd + s] = {
-            (double)tr[t][i] + (double)sr[t][i], (double)ti[t][i] + (double)si[t][i]};
-    }
-  }
+  rows_bf16_store<NT>(P, g, b0, nb, k, pc, row0, kg, col, tr, ti, sr, si);
 }
 
 // F* on the bfloat16 matrix cores: X^T = Dhat^T conj(Fhat), contraction over
@@ -558,23 +617,25 @@ __device__ __forceinline__ void mfma_cols_bf16_wg(const uint32_t* __restrict__ A
   u4v dv[RING][PER];
 #pragma unroll
   for (int d = 0; d < RING; ++d)
-    stage_planes_load<MT, kBf16Threads>(Ds, g.nf, k, nd8, b0, nb, 32 * d, d < nch ? g.Nd : 0, dv[d]);
+    stage_planes_load<MT, kBf16Threads, false>(Ds, g.nf, k, nd8, b0, nb, 32 * d, d < nch ? g.Nd : 0, dv[d]);
 #pragma unroll
   for (int d = 0; d < RING; ++d)
     load_col8<LO>(Ak, 32 * d + 8 * kg, d < nch ? g.Nd : 0, g.Nm, r0[d], r1[d]);
-  stage_planes_store_cols<MT, kBf16Threads>(dv[0], nb, 0, g.Nd, sd);
+  stage_planes_store<MT, kBf16Threads, false>(dv[0], nb, 0, g.Nd, sd);
   __syncthreads();
   auto step = [&](int64_t c, int d) {
     const int64_t base = 32 * c;
     const BlockOps f = unpack_block<LO>(r0[d], r1[d]);
     const int64_t ahead = base + 32 * RING, aend = c + RING < nch ? g.Nd : 0;
-    stage_planes_load<MT, kBf16Threads>(Ds, g.nf, k, nd8, b0, nb, ahead, aend, dv[d]);
+    stage_planes_load<MT, kBf16Threads, false>(Ds, g.nf, k, nd8, b0, nb, ahead, aend, dv[d]);
     load_col8<LO>(Ak, ahead + 8 * kg, aend, g.Nm, r0[d], r1[d]);
     __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
-    cols_bf16_products<MT, LO>(f, sd + (c & 1) * BUF, kg, col, xr, xi, sr, si);
+    const u4v* ds = sd + (c & 1) * BUF;
+    cols_bf16_products<MT, LO>(
+        f, [&](int pl, int t) { return ds[(pl * 4 + kg) * PP + t * 16 + col]; }, xr, xi, sr, si);
     __builtin_amdgcn_sched_barrier(0);  // the store waits for its loads: after the products
-    stage_planes_store_cols<MT, kBf16Threads>(dv[(d + 1) % RING], nb, base + 32, c + 1 < nch ? g.Nd : 0,
-                                sd + ((c + 1) & 1) * BUF);
+    stage_planes_store<MT, kBf16Threads, false>(dv[(d + 1) % RING], nb, base + 32,
+                                                c + 1 < nch ? g.Nd : 0, sd + ((c + 1) & 1) * BUF);
     __syncthreads();
   };
   const int64_t nfull = nch / RING * RING;
@@ -585,20 +646,8 @@ __device__ __forceinline__ void mfma_cols_bf16_wg(const uint32_t* __restrict__ A
 #pragma unroll
   for (int d = 0; d < RING - 1; ++d)
     if (nfull + d < nch) step(nfull + d, d);
-  const int64_t p = col0 + col;
-  if (p >= g.Nm) return;
-  const int64_t ntiles = (g.Nm + kScaleTile - 1) / kScaleTile;
-  const float sc = scales[k * ntiles + p / kScaleTile];
-#pragma unroll
-  for (int t = 0; t < MT; ++t)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int b = t * 16 + 4 * kg + i;
-      if (b < nb)  // the two parts added in float64, scaled (a power of two), rounded once
-        Y[((b0 + b) * g.nf + k) * g.Nm + p] = {
-            (float)(((double)xr[t][i] + (double)sr[t][i]) * sc),
-            (float)(((double)xi[t][i] + (double)si[t][i]) * sc)};
-    }
+  cols_bf16_store<MT>(col_scale(scales, g, k, col0 + col), Y, g, b0, nb, k, col0 + col, kg, xr,
+                      xi, sr, si);
 }
 
 }  // namespace

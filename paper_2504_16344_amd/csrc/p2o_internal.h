@@ -60,10 +60,35 @@ struct FftIo {
   // (x = hi + lo, each rounded to nearest even), optionally multiplied by
   // the column sub-block scales first; padding columns ncols..n8-1 are zero.
   uint16_t* planes;
-  int64_t n8;            // plane pitch (ncols rounded up to 8)
+  int64_t n8;            // plane pitch (ncols rounded up to 8, or to 32 in slot order)
   int64_t nbins;         // frequency bins per batch (nf)
   const float* col_scales;  // [nbins][ceil(ncols / kScaleTile)] or nullptr
+  int slot_order;        // 0: columns in order; 1 / 2: each 32-column chunk in the
+                         // matrix-core slot order of F's hi+lo / hi-only products
 };
+
+// Matrix-core slot order of F's bfloat16 products.  A 32-entry contraction
+// chunk feeds slots j = 0..7 of lane groups kg = 0..3; slot j of group kg
+// takes chunk entry row_slot_entry(kg, j), chosen so the 4 groups of a block
+// row read one contiguous 64-byte span per 16-byte load (hi+lo entries are 8
+// bytes, hi-only 4).  The forward transform stores F's vector planes with
+// entry e of each chunk at position row_slot_position(e) = 8 kg + j, so the
+// 8 slots of a group are one 16-byte run.
+__host__ __device__ constexpr int row_slot_entry(bool lo, int kg, int j) {
+  return lo ? 8 * (j >> 1) + 2 * kg + (j & 1) : 16 * (j >> 2) + 4 * kg + (j & 3);
+}
+__host__ __device__ constexpr int row_slot_position(bool lo, int e) {
+  return lo ? 8 * ((e >> 1) & 3) + 2 * (e >> 3) + (e & 1)
+            : 8 * ((e >> 2) & 3) + 4 * (e >> 4) + (e & 3);
+}
+__host__ __device__ constexpr bool row_slots_are_inverse() {
+  for (int lo = 0; lo < 2; ++lo)
+    for (int kg = 0; kg < 4; ++kg)
+      for (int j = 0; j < 8; ++j)
+        if (row_slot_position(lo, row_slot_entry(lo, kg, j)) != 8 * kg + j) return false;
+  return true;
+}
+static_assert(row_slots_are_inverse(), "slot order and plane positions must match");
 
 int64_t smooth_length(int64_t Nt);  // L: smallest even 7-smooth >= 2*Nt
 bool make_fft_desc(int64_t Nt, FftDesc* d);
