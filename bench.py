@@ -365,7 +365,8 @@ def bench_batch(args):
         "dtype": "bf16x2/f32", "data": "synthetic (seeded counter-based normals, generated on device)",
         "config": {"workload": f"{n} independent p2o instances, Nt={Nt}, Nd U{{50..600}}, "
                                f"Nm U{{1000..20000}}, 1..256 RHS each; F and F* as captured HIP "
-                               f"graphs (one persistent product launch per op per memory wave)",
+                               f"graphs (per op and memory wave: one warp-specialised product launch "
+                               f"per matrix-core instance, one persistent launch for the others)",
                    "instances": n, "Nt": Nt, "waves": len(waves),
                    "rhs_total": int(R.sum()), "budget_gb": args.budget_gb},
         "complex_tflops": round(flops / (step_ms * 1e-3) / 1e12, 2),

@@ -1261,12 +1261,18 @@ int batch_cfg(p2o_batch b, p2o_op op, const int64_t* nrhs) {
 
 // Validate the per-instance arguments, reserve workspaces and build the
 // work table (host copy) for one batched apply in configuration `cfg`.
+// bfloat16 instances on the matrix-core path get their own product launch
+// (the warp-specialised kernels of gemm_bf16.hip, bitwise equal to the
+// persistent kernel's units and faster: their loads and products run on
+// different wavefronts); they are listed in `own` and left out of the
+// table.  All other instances share the one persistent launch.
 p2o_status batch_prepare(p2o_batch b, p2o_op op, const double* const* x, double* const* y,
                          const int64_t* nrhs, int cfg, std::vector<BatchInst>* table,
-                         int64_t* total) {
+                         int64_t* total, std::vector<int>* own) {
   if (!b || !x || !y || !nrhs || (op != P2O_F && op != P2O_FADJ)) return P2O_EINVAL;
   const size_t n = b->plans.size();
-  table->assign(n, BatchInst{});
+  table->clear();
+  own->clear();
   int64_t units = 0;
   for (size_t i = 0; i < n; ++i) {
     p2o_plan_s* h = b->plans[i];
@@ -1275,7 +1281,12 @@ p2o_status batch_prepare(p2o_batch b, p2o_op op, const double* const* x, double*
     const WsLayout w = ws_layout(h, op, nrhs[i]);
     char* ws = static_cast<char*>(h->ws);
     const bool matrix = use_mfma(h, op, nrhs[i]) && h->prec != P2O_MIXED_FP16;
-    BatchInst& I = (*table)[i];
+    if (matrix && (b->cls == kClassMixedBf16 || b->cls == kClassFastBf16)) {
+      own->push_back((int)i);
+      continue;
+    }
+    table->push_back(BatchInst{});
+    BatchInst& I = table->back();
     I.fhat = h->fhat;
     I.scales = h->scales;
     I.in = ws + ((matrix && is_mixed(h->prec)) ? w.c_off : w.a_off);
@@ -1292,15 +1303,24 @@ p2o_status batch_prepare(p2o_batch b, p2o_op op, const double* const* x, double*
 
 // Enqueue one batched apply whose work table is already on the device:
 // every instance's forward transform (writing the bfloat16 operand planes
-// for matrix-core instances), one persistent product launch, every
+// for matrix-core instances), one persistent product launch over the
+// table's instances, the product launches of the instances in `own`, every
 // instance's inverse transform.
 p2o_status batch_enqueue(p2o_batch b, p2o_op op, const double* const* x, double* const* y,
                          const int64_t* nrhs, const std::vector<BatchInst>& table,
-                         const BatchInst* dev_table, int64_t total, int cfg, hipStream_t s) {
+                         const BatchInst* dev_table, int64_t total, int cfg,
+                         const std::vector<int>& own, hipStream_t s) {
   const size_t n = b->plans.size();
   for (size_t i = 0; i < n; ++i)
     TRY_HIP(enqueue_forward(b->plans[i], op, x[i], nrhs[i], static_cast<char*>(b->plans[i]->ws), s));
-  TRY_HIP(launch_batch_product(b->cls, op, dev_table, (int)n, total, cfg, s));
+  if (total > 0) TRY_HIP(launch_batch_product(b->cls, op, dev_table, (int)table.size(), total, cfg, s));
+  for (const int i : own) {
+    p2o_plan_s* h = b->plans[i];
+    const WsLayout w = ws_layout(h, op, nrhs[i]);
+    char* ws = static_cast<char*>(h->ws);
+    TRY_HIP(launch_product(h, op, ws + w.a_off, ws + w.b_off, ws + w.c_off, nrhs[i],
+                           default_cfg(h, op), s));
+  }
   for (size_t i = 0; i < n; ++i)
     TRY_HIP(enqueue_inverse(b->plans[i], op, y[i], nrhs[i], 1.0,
                             static_cast<const char*>(b->plans[i]->ws), s));
@@ -1341,13 +1361,15 @@ p2o_status p2o_batch_apply(p2o_batch b, p2o_op op, const double* const* x, doubl
   (void)hipGetLastError();
   if (!b || !nrhs || (op != P2O_F && op != P2O_FADJ)) return P2O_EINVAL;
   std::vector<BatchInst> table;
+  std::vector<int> own;
   int64_t total = 0;
   const int cfg = batch_cfg(b, op, nrhs);
-  TRY_ST(batch_prepare(b, op, x, y, nrhs, cfg, &table, &total));
+  TRY_ST(batch_prepare(b, op, x, y, nrhs, cfg, &table, &total, &own));
   hipStream_t s = (hipStream_t)stream;
   TRY_HIP(hipStreamSynchronize(s));  // the previous apply has finished reading the table
-  TRY_HIP(hipMemcpy(b->dev, table.data(), sizeof(BatchInst) * table.size(), hipMemcpyHostToDevice));
-  return batch_enqueue(b, op, x, y, nrhs, table, b->dev, total, cfg, s);
+  if (!table.empty())
+    TRY_HIP(hipMemcpy(b->dev, table.data(), sizeof(BatchInst) * table.size(), hipMemcpyHostToDevice));
+  return batch_enqueue(b, op, x, y, nrhs, table, b->dev, total, cfg, own, s);
 }
 
 p2o_status p2o_batch_set_config(p2o_batch b, p2o_op op, int64_t cfg) {
@@ -1381,20 +1403,22 @@ p2o_status p2o_batch_autotune(p2o_batch b, p2o_op op, const double* const* x, do
   p2o_status st = P2O_OK;
   for (int c = 0; c < n && st == P2O_OK; ++c) {
     std::vector<BatchInst> table;
+    std::vector<int> own;
     int64_t total = 0;
-    st = batch_prepare(b, op, x, y, nrhs, c, &table, &total);
+    st = batch_prepare(b, op, x, y, nrhs, c, &table, &total, &own);
     if (st != P2O_OK) break;
     hipError_t e = hipStreamSynchronize(s);
-    if (e == hipSuccess)
+    if (e == hipSuccess && !table.empty())
       e = hipMemcpy(b->dev, table.data(), sizeof(BatchInst) * table.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) { st = hip_fail(e); break; }
     // one whole apply (transforms included) leaves valid inputs in the
-    // workspaces, then the product launch alone is timed
-    st = batch_enqueue(b, op, x, y, nrhs, table, b->dev, total, c, s);
+    // workspaces, then the persistent product launch alone is timed (an
+    // empty one, when every instance has its own launch, takes 0 ms)
+    st = batch_enqueue(b, op, x, y, nrhs, table, b->dev, total, c, own, s);
     if (st != P2O_OK) break;
     e = hipEventRecord(e0, s);
-    for (int r = 0; r < reps && e == hipSuccess; ++r)
-      e = launch_batch_product(b->cls, op, b->dev, (int)b->plans.size(), total, c, s);
+    for (int r = 0; r < reps && e == hipSuccess && total > 0; ++r)
+      e = launch_batch_product(b->cls, op, b->dev, (int)table.size(), total, c, s);
     if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
@@ -1427,21 +1451,22 @@ p2o_status p2o_graph_capture(p2o_batch b, p2o_op op, const double* const* x, dou
   (void)hipGetLastError();
   if (!b || !nrhs || (op != P2O_F && op != P2O_FADJ)) return P2O_EINVAL;
   std::vector<BatchInst> table;
+  std::vector<int> own;
   int64_t total = 0;
   const int cfg = batch_cfg(b, op, nrhs);
-  TRY_ST(batch_prepare(b, op, x, y, nrhs, cfg, &table, &total));
+  TRY_ST(batch_prepare(b, op, x, y, nrhs, cfg, &table, &total, &own));
   TRY_HIP(hipStreamSynchronize((hipStream_t)stream));
   auto* g = new (std::nothrow) p2o_graph_s;
   if (!g) return P2O_ENOMEM;
-  hipError_t e = hipMalloc((void**)&g->dev, sizeof(BatchInst) * table.size());
-  if (e == hipSuccess)
+  hipError_t e = hipMalloc((void**)&g->dev, sizeof(BatchInst) * std::max<size_t>(1, table.size()));
+  if (e == hipSuccess && !table.empty())
     e = hipMemcpy(g->dev, table.data(), sizeof(BatchInst) * table.size(), hipMemcpyHostToDevice);
   hipStream_t cs = nullptr;
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   p2o_status st = P2O_OK;
   if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    st = batch_enqueue(b, op, x, y, nrhs, table, g->dev, total, cfg, cs);
+    st = batch_enqueue(b, op, x, y, nrhs, table, g->dev, total, cfg, own, cs);
     const hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
     if (st == P2O_OK && e2 != hipSuccess) e = e2;
   }
