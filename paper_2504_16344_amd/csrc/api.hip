@@ -1295,7 +1295,9 @@ p2o_status batch_prepare(p2o_batch b, p2o_op op, const double* const* x, double*
     I.n8 = plane_pitch(h, op);
     I.path = matrix ? kPathMatrix : kPathVector;
     I.unit_begin = units;
-    units += batch_units(b->cls, op, I.path, I.g, cfg);
+    const int64_t nu = batch_units(b->cls, op, I.path, I.g, cfg);
+    if (nu < 0) return P2O_EINVAL;  // a path the persistent kernel does not run
+    units += nu;
   }
   *total = units;
   return P2O_OK;

@@ -6,8 +6,10 @@
 // w + W, w + 2W, ... (W = workgroups in the grid, sized to the chip's
 // resident capacity), finds the owning instance by binary search over the
 // instances' first units, and runs that instance's path — four vector-unit
-// wavefront units for few right-hand sides, one matrix-core workgroup tile
-// for many — through the same code as the single-plan kernels.
+// wavefront units for few right-hand sides, one float64 matrix-core
+// workgroup tile for many (FP64 instances) — through the same code as the
+// single-plan kernels.  bfloat16 instances on the matrix-core path are not
+// in the table: each gets its own warp-specialised launch (gemm_bf16.hip).
 // Interleaving keeps every workgroup's mix of large and small instances
 // alike, and neighbouring workgroups on neighbouring tiles of one instance,
 // which share the vector operand in L2.
@@ -17,14 +19,12 @@ namespace p2o {
 namespace {
 
 // Tunable configurations of the persistent kernel: vector-unit rows per
-// wavefront (F), vector-unit column groups per wavefront (F*), and the load
-// ring depth of the bfloat16 matrix-core units (the kernel inlines every
-// path, so the ring decides whether the largest one fits 256 registers
-// without spilling).  p2o_batch_autotune times them on the batch itself.
+// wavefront (F) and vector-unit column groups per wavefront (F*).
+// p2o_batch_autotune times them on the batch itself.
 struct BatchCfg {
-  int rows_v, cols_v, ring;
+  int rows_v, cols_v;
 };
-constexpr BatchCfg kBatchCfgs[] = {{4, 2, 1}, {4, 2, 2}, {2, 1, 1}, {8, 4, 1}};
+constexpr BatchCfg kBatchCfgs[] = {{4, 2}, {2, 1}, {8, 4}};
 constexpr int kBatchCfgCount = sizeof(kBatchCfgs) / sizeof(kBatchCfgs[0]);
 
 template <int CLS>
@@ -36,25 +36,13 @@ struct ClassTraits<kClassMixedBf16> { static constexpr Fmt16 fmt = Fmt16::BF16; 
 template <>
 struct ClassTraits<kClassFastBf16> { static constexpr Fmt16 fmt = Fmt16::BF16; static constexpr bool lo = false; };
 
+// LDS of the float64 matrix-core stage (FP64 class only).
 template <int CLS>
 constexpr int stage_bytes() {
-  return CLS == kClassF64 ? stage_bytes_f64(4) : (CLS == kClassMixedFp16 ? 16 : stage_bytes_bf16(4));
+  return CLS == kClassF64 ? stage_bytes_f64(4) : 16;
 }
 
-// Workgroup size per class: the bfloat16 matrix-core units run 8 wavefronts.
-template <int CLS>
-constexpr int class_threads() {
-  return (CLS == kClassMixedBf16 || CLS == kClassFastBf16) ? kBf16Threads : 256;
-}
-
-__host__ __device__ constexpr int class_threads_rt(int cls) {
-  return (cls == kClassMixedBf16 || cls == kClassFastBf16) ? kBf16Threads : 256;
-}
-
-// Matrix-path tile (rows for F, columns for F*) per class.
-__host__ __device__ constexpr int class_tile(int cls) {
-  return cls == kClassF64 ? kWgTile : kBf16Tile;
-}
+constexpr int kBatchThreads = 256;  // 4 wavefronts: 4 vector-unit wave units, or one 64-row tile
 
 // Vector-path wave units of one instance (a workgroup unit is
 // threads / 64 of them).
@@ -67,41 +55,24 @@ __host__ __device__ __forceinline__ int64_t vector_wave_units(p2o_op op, const G
 template <int CLS, int CFG>
 __device__ __forceinline__ void rows_unit(const BatchInst& I, int64_t u, void* lds) {
   constexpr int kRowsV = kBatchCfgs[CFG].rows_v;
-  constexpr int kBatchRing = kBatchCfgs[CFG].ring;
   const GemvShape& g = I.g;
-  if (I.path == kPathMatrix) {
-    constexpr int64_t tile = class_tile(CLS);
-    const int64_t nmt = (g.Nd + tile - 1) / tile, rest = u / nmt;
-    const int64_t mt = u % nmt, k = rest % g.nf, pc = rest / g.nf;
-    for (int64_t b0 = 0; b0 < g.nrhs; b0 += 64) {
-      const int nb = (int)min((int64_t)64, g.nrhs - b0);
-      if constexpr (CLS == kClassF64) {
-        const auto* A = static_cast<const cpx<double>*>(I.fhat);
-        const auto* X = static_cast<const cpx<double>*>(I.in);
-        auto* P = static_cast<cpx<double>*>(I.out);
+  if constexpr (CLS == kClassF64) {
+    if (I.path == kPathMatrix) {
+      const int64_t nmt = (g.Nd + kWgTile - 1) / kWgTile, rest = u / nmt;
+      const int64_t mt = u % nmt, k = rest % g.nf, pc = rest / g.nf;
+      const auto* A = static_cast<const cpx<double>*>(I.fhat);
+      const auto* X = static_cast<const cpx<double>*>(I.in);
+      auto* P = static_cast<cpx<double>*>(I.out);
+      for (int64_t b0 = 0; b0 < g.nrhs; b0 += 64) {
+        const int nb = (int)min((int64_t)64, g.nrhs - b0);
         if (nb > 32) mfma_rows_f64_wg<4>(A, X, P, g, b0, nb, k, mt, pc, lds);
         else if (nb > 16) mfma_rows_f64_wg<2>(A, X, P, g, b0, nb, k, mt, pc, lds);
         else mfma_rows_f64_wg<1>(A, X, P, g, b0, nb, k, mt, pc, lds);
-      } else if constexpr (CLS == kClassMixedBf16 || CLS == kClassFastBf16) {
-        constexpr bool LO = ClassTraits<CLS>::lo;
-        const auto* A = static_cast<const uint32_t*>(I.fhat);
-        const auto* X = static_cast<const uint16_t*>(I.in);
-        auto* P = static_cast<cpx<double>*>(I.out);
-        const bool vec = LO ? (g.Nm % 2 == 0) : (g.Nm % 4 == 0);
-        if (vec) {
-          if (nb > 32) mfma_rows_bf16_wg<4, LO, true, kBatchRing>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
-          else if (nb > 16) mfma_rows_bf16_wg<2, LO, true, kBatchRing>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
-          else mfma_rows_bf16_wg<1, LO, true, kBatchRing>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
-        } else {
-          if (nb > 32) mfma_rows_bf16_wg<4, LO, false, kBatchRing>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
-          else if (nb > 16) mfma_rows_bf16_wg<2, LO, false, kBatchRing>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
-          else mfma_rows_bf16_wg<1, LO, false, kBatchRing>(A, X, P, g, I.n8, b0, nb, k, mt, pc, lds);
-        }
       }
+      return;
     }
-    return;
   }
-  const int64_t wu = u * (class_threads<CLS>() / 64) + wave_id_in_block();
+  const int64_t wu = u * (kBatchThreads / 64) + wave_id_in_block();
   if (wu >= vector_wave_units(P2O_F, g, kRowsV, 1)) return;
   const int64_t nsg = (g.Nd + kRowsV - 1) / kRowsV, rest = wu / nsg;
   const int64_t sg = wu % nsg, k = rest % g.nf, pc = rest / g.nf;
@@ -127,34 +98,24 @@ __device__ __forceinline__ void rows_unit(const BatchInst& I, int64_t u, void* l
 template <int CLS, int CFG>
 __device__ __forceinline__ void cols_unit(const BatchInst& I, int64_t u, void* lds) {
   constexpr int kColsV = kBatchCfgs[CFG].cols_v;
-  constexpr int kBatchRing = kBatchCfgs[CFG].ring;
   const GemvShape& g = I.g;
-  if (I.path == kPathMatrix) {
-    constexpr int64_t tile = class_tile(CLS);
-    const int64_t npt = (g.Nm + tile - 1) / tile;
-    const int64_t pt = u % npt, k = u / npt;
-    for (int64_t b0 = 0; b0 < g.nrhs; b0 += 64) {
-      const int nb = (int)min((int64_t)64, g.nrhs - b0);
-      if constexpr (CLS == kClassF64) {
-        const auto* A = static_cast<const cpx<double>*>(I.fhat);
-        const auto* D = static_cast<const cpx<double>*>(I.in);
-        auto* Y = static_cast<cpx<double>*>(I.out);
+  if constexpr (CLS == kClassF64) {
+    if (I.path == kPathMatrix) {
+      const int64_t npt = (g.Nm + kWgTile - 1) / kWgTile;
+      const int64_t pt = u % npt, k = u / npt;
+      const auto* A = static_cast<const cpx<double>*>(I.fhat);
+      const auto* D = static_cast<const cpx<double>*>(I.in);
+      auto* Y = static_cast<cpx<double>*>(I.out);
+      for (int64_t b0 = 0; b0 < g.nrhs; b0 += 64) {
+        const int nb = (int)min((int64_t)64, g.nrhs - b0);
         if (nb > 32) mfma_cols_f64_wg<4>(A, D, Y, g, b0, nb, k, pt, lds);
         else if (nb > 16) mfma_cols_f64_wg<2>(A, D, Y, g, b0, nb, k, pt, lds);
         else mfma_cols_f64_wg<1>(A, D, Y, g, b0, nb, k, pt, lds);
-      } else if constexpr (CLS == kClassMixedBf16 || CLS == kClassFastBf16) {
-        constexpr bool LO = ClassTraits<CLS>::lo;
-        const auto* A = static_cast<const uint32_t*>(I.fhat);
-        const auto* D = static_cast<const uint16_t*>(I.in);
-        auto* Y = static_cast<cpx<float>*>(I.out);
-        if (nb > 32) mfma_cols_bf16_wg<4, LO, kBatchRing>(A, I.scales, D, Y, g, I.n8, b0, nb, k, pt, lds);
-        else if (nb > 16) mfma_cols_bf16_wg<2, LO, kBatchRing>(A, I.scales, D, Y, g, I.n8, b0, nb, k, pt, lds);
-        else mfma_cols_bf16_wg<1, LO, kBatchRing>(A, I.scales, D, Y, g, I.n8, b0, nb, k, pt, lds);
       }
+      return;
     }
-    return;
   }
-  const int64_t wu = u * (class_threads<CLS>() / 64) + wave_id_in_block();
+  const int64_t wu = u * (kBatchThreads / 64) + wave_id_in_block();
   if (wu >= vector_wave_units(P2O_FADJ, g, 1, kColsV)) return;
   const int64_t npg = (g.Nm + 64 * kColsV - 1) / (64 * kColsV);
   const int64_t pg = wu % npg, k = wu / npg;
@@ -180,7 +141,7 @@ __device__ __forceinline__ void cols_unit(const BatchInst& I, int64_t u, void* l
 // The grid is a multiple of 8 workgroups; each XCD takes a contiguous range
 // of units per round, so neighbouring tiles of one instance share its L2.
 template <int CLS, int OP, int CFG>
-__global__ void __launch_bounds__(class_threads<CLS>())
+__global__ void __launch_bounds__(kBatchThreads)
 batch_product_kernel(const BatchInst* __restrict__ insts, int n, int64_t total) {
   __shared__ __align__(16) char lds[stage_bytes<CLS>()];
   const int64_t grid = gridDim.x;
@@ -204,14 +165,14 @@ hipError_t launch_one(const BatchInst* insts, int n, int64_t total, hipStream_t 
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_product_kernel<CLS, OP, CFG>,
-                                                     class_threads<CLS>(), 0);
+                                                     kBatchThreads, 0);
   if (e != hipSuccess) return e;
   int64_t blocks = (int64_t)std::max(1, cus) * std::max(1, per_cu);
   blocks = std::min<int64_t>(blocks, total);
   if (blocks < 1) return hipSuccess;
   blocks = (blocks + kXcds - 1) / kXcds * kXcds;
   hipLaunchKernelGGL((batch_product_kernel<CLS, OP, CFG>), dim3((unsigned)blocks),
-                     dim3(class_threads<CLS>()), 0, s, insts, n, total);
+                     dim3(kBatchThreads), 0, s, insts, n, total);
   return hipGetLastError();
 }
 
@@ -238,25 +199,24 @@ hipError_t launch_cfg(BatchClass cls, p2o_op op, const BatchInst* insts, int n, 
 int batch_config_count() { return kBatchCfgCount; }
 
 int64_t batch_units(BatchClass cls, p2o_op op, int path, const GemvShape& g, int cfg) {
-  if (path == kPathMatrix) {
-    const int64_t tile = class_tile(cls);
-    if (op == P2O_F) return g.nf * ((g.Nd + tile - 1) / tile) * g.n_pc;
-    return g.nf * ((g.Nm + tile - 1) / tile);
+  if (path == kPathMatrix) {  // float64 tiles (bfloat16 matrix-core instances have own launches)
+    if (cls != kClassF64) return -1;
+    if (op == P2O_F) return g.nf * ((g.Nd + kWgTile - 1) / kWgTile) * g.n_pc;
+    return g.nf * ((g.Nm + kWgTile - 1) / kWgTile);
   }
   const BatchCfg& c = kBatchCfgs[cfg];
   const int64_t waves = vector_wave_units(op, g, c.rows_v, c.cols_v);
-  const int64_t per = class_threads_rt(cls) / 64;
+  const int64_t per = kBatchThreads / 64;
   return (waves + per - 1) / per;
 }
 
 hipError_t launch_batch_product(BatchClass cls, p2o_op op, const BatchInst* insts, int n,
                                 int64_t total_units, int cfg, hipStream_t s) {
-  static_assert(kBatchCfgCount == 4, "one launch_cfg case per configuration");
+  static_assert(kBatchCfgCount == 3, "one launch_cfg case per configuration");
   switch (cfg) {
     case 0: return launch_cfg<0>(cls, op, insts, n, total_units, s);
     case 1: return launch_cfg<1>(cls, op, insts, n, total_units, s);
     case 2: return launch_cfg<2>(cls, op, insts, n, total_units, s);
-    case 3: return launch_cfg<3>(cls, op, insts, n, total_units, s);
   }
   return hipErrorInvalidValue;
 }

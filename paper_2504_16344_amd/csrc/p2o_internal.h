@@ -194,8 +194,9 @@ struct BatchInst {
   int path;
 };
 
-// Configurations of the persistent kernel (batch.hip: vector-unit tiles and
-// matrix-core ring depth); the work units of an instance depend on it.
+// Configurations of the persistent kernel (batch.hip: vector-unit tiles);
+// the work units of an instance depend on it (-1: a path the persistent
+// kernel does not run, the bfloat16 matrix-core one).
 int batch_config_count();
 int64_t batch_units(BatchClass cls, p2o_op op, int path, const GemvShape& g, int cfg);
 // One persistent launch over all instances' units (instances sorted by

@@ -94,9 +94,10 @@ def test_batch_argument_errors():
 
 @pytest.mark.parametrize("prec", list(TOL))
 def test_every_batch_configuration_is_bitwise_equal(prec):
-    """Each configuration of the persistent kernel (vector-unit tiles,
-    matrix-core ring depth) gives the same bits as configuration 0 and as the
-    single-plan applies, for both ops."""
+    """Each configuration of the persistent kernel (vector-unit tiles) gives
+    the same bits as configuration 0 and as the single-plan applies, for
+    both ops (matrix-core instances of the bfloat16 tiers take their own
+    launches of the single-plan kernels)."""
     print(f"\n[batch cfg] prec={prec}", flush=True)
     cases, plans = _setup(prec, seed=70)
     batch = P.Batch(plans)
