@@ -99,6 +99,15 @@ constexpr int kWsConsumers = 4;
 constexpr int kWsSub = 2;  // 16-row (F) or 16-column (F*) sub-tiles per consumer: 128 per workgroup
 constexpr int kWsProducers = 4;
 constexpr int kWsThreads = 64 * (kWsConsumers + kWsProducers);
+constexpr int kWsTile = 16 * kWsSub * kWsConsumers;  // columns of an F* tile
+static_assert(kWsTile == kBf16Tile, "F*'s slot layout assumes 1 KB sensor rows (128 columns)");
+// F's kernel: its own role counts (its tile rows follow from them) and
+// workgroups per CU.
+constexpr int kWsRowConsumers = kWsConsumers;
+constexpr int kWsRowProducers = kWsProducers;
+constexpr int kWsRowThreads = 64 * (kWsRowConsumers + kWsRowProducers);
+constexpr int kWsRowTile = 16 * kWsSub * kWsRowConsumers;
+constexpr int kWsRowPerCu = 1;
 constexpr int kWsRegRing = 3;  // chunks in flight in each producer's registers
 
 // This wavefront's LDS writes have completed.
@@ -142,7 +151,7 @@ __device__ __forceinline__ int64_t ws_padded(int64_t n) {
 struct RowsStep {
   int64_t tile, end, stride, mt, k, pc, p0, p1, nch, c;
   __device__ void decode(const GemvShape& g) {  // 32-bit divisions: tile counts < 2^31
-    const uint32_t nmt = (uint32_t)((g.Nd + kBf16Tile - 1) / kBf16Tile);
+    const uint32_t nmt = (uint32_t)((g.Nd + kWsRowTile - 1) / kWsRowTile);
     const uint32_t t = (uint32_t)tile, rest = t / nmt;
     mt = t - rest * nmt;
     k = rest % (uint32_t)g.nf;
@@ -162,7 +171,7 @@ struct RowsStep {
 
 // Chunks of all of this workgroup's F tiles (the last column chunk is shorter).
 __device__ __forceinline__ int64_t ws_rows_steps(const WsTiles& wt, const GemvShape& g) {
-  const int64_t nmt = (g.Nd + kBf16Tile - 1) / kBf16Tile;
+  const int64_t nmt = (g.Nd + kWsRowTile - 1) / kWsRowTile;
   const int64_t full = (g.pc_len + 31) / 32;
   const int64_t last = (g.Nm - (g.n_pc - 1) * g.pc_len + 31) / 32;
   return wt.count() * full - wt.count_from((g.n_pc - 1) * nmt * g.nf) * (full - last);
@@ -170,11 +179,14 @@ __device__ __forceinline__ int64_t ws_rows_steps(const WsTiles& wt, const GemvSh
 
 template <int NT, bool LO>
 struct WsRowsLds {
-  static constexpr int kBlock = kBf16Tile * 32 * 4 * (LO ? 2 : 1);  // 32 KB | 16 KB
+  static constexpr int kBlock = kWsRowTile * 32 * 4 * (LO ? 2 : 1);  // 32 KB | 16 KB
   static constexpr int kVec = 16 * NT * 256;                        // 16 NT rhs x 16 granules
   static constexpr int kSlot = kBlock + kVec;
-  static constexpr int kBlockIns = kBlock / 1024 / kWsProducers;   // per producer and chunk
-  static constexpr int kIns = kBlockIns + NT;
+  static constexpr int kBlockIns = kBlock / 1024 / kWsRowProducers;   // per producer and chunk
+  static constexpr int kVecIns = kVec / 1024 / kWsRowProducers;
+  static constexpr int kIns = kBlockIns + kVecIns;
+  static_assert(kBlock % (1024 * kWsRowProducers) == 0 && kVec % (1024 * kWsRowProducers) == 0,
+                "whole 1 KB load instructions per producer");
 };
 
 // Slot layout (16-byte granules; each producer load instruction fills one
@@ -192,9 +204,9 @@ struct WsRowsLds {
 template <int NT, bool LO>
 struct WsRowsOff {
   uint32_t blk[WsRowsLds<NT, LO>::kBlockIns];     // lane offsets (vector registers)
-  uint32_t vec[NT];
+  uint32_t vec[WsRowsLds<NT, LO>::kVecIns];
   const char* bbase[WsRowsLds<NT, LO>::kBlockIns];  // chunk-0 bases of the tile (uniform)
-  const char* vbase[NT];
+  const char* vbase[WsRowsLds<NT, LO>::kVecIns];
 };
 
 // Block rows per load instruction and the granule of lane `lane`.
@@ -223,14 +235,14 @@ __device__ __forceinline__ void ws_rows_offsets(const uint32_t* __restrict__ A,
     const int qi = p * Lay::kBlockIns + q;
     int rl, gr;
     ws_rows_lane<LO>(qi, lane, rl, gr);
-    const int64_t r0 = min(st.mt * kBf16Tile + qi * RPI, g.Nd - 1);
-    const int64_t row = min(st.mt * kBf16Tile + rl, g.Nd - 1);  // rows past Nd: dropped
+    const int64_t r0 = min(st.mt * kWsRowTile + qi * RPI, g.Nd - 1);
+    const int64_t row = min(st.mt * kWsRowTile + rl, g.Nd - 1);  // rows past Nd: dropped
     o.blk[q] = (uint32_t)(((row - r0) * g.Nm + (LO ? 2 : 4) * gr) * WPE * 4);
     o.bbase[q] = reinterpret_cast<const char*>(A) + ((st.k * g.Nd + r0) * g.Nm + st.p0) * WPE * 4;
   }
 #pragma unroll
-  for (int q = 0; q < NT; ++q) {  // right-hand sides past nb: a copy of the last (dropped)
-    const int qx = p * NT + q;
+  for (int q = 0; q < Lay::kVecIns; ++q) {  // right-hand sides past nb: a copy of the last (dropped)
+    const int qx = p * Lay::kVecIns + q;
     const int b = qx * 4 + (lane >> 4);
     const int L = (lane & 15) ^ (b & 15);
     const int rb0 = min(qx * 4, nb - 1), rb = min(b, nb - 1) - rb0;
@@ -260,15 +272,15 @@ __device__ __forceinline__ void ws_rows_load(const uint32_t* __restrict__ A,
       const int qi = p * Lay::kBlockIns + q;
       int rl, gr;
       ws_rows_lane<LO>(qi, lane, rl, gr);
-      const int64_t r0 = min(st.mt * kBf16Tile + qi * RPI, g.Nd - 1);
-      const int64_t row = min(st.mt * kBf16Tile + rl, g.Nd - 1);
+      const int64_t r0 = min(st.mt * kWsRowTile + qi * RPI, g.Nd - 1);
+      const int64_t row = min(st.mt * kWsRowTile + rl, g.Nd - 1);
       const int64_t e = min<int64_t>(EPG * gr, st.p1 - EPG - base);
       off = (uint32_t)(((row - r0) * g.Nm + e) * WPE * 4);
     }
     v[q] = __builtin_nontemporal_load(reinterpret_cast<const u4v*>(ub + off));
   }
 #pragma unroll
-  for (int q = 0; q < NT; ++q) {
+  for (int q = 0; q < Lay::kVecIns; ++q) {
     const char* ub = (live ? o.vbase[q] : reinterpret_cast<const char*>(Xs)) + vstep;
     v[Lay::kBlockIns + q] = *reinterpret_cast<const u4v*>(ub + o.vec[q]);
   }
@@ -282,24 +294,25 @@ __device__ __forceinline__ void ws_rows_store(char* slot, int p, int lane,
   for (int q = 0; q < Lay::kBlockIns; ++q)
     reinterpret_cast<u4v*>(slot + (p * Lay::kBlockIns + q) * 1024)[lane] = v[q];
 #pragma unroll
-  for (int q = 0; q < NT; ++q)
-    reinterpret_cast<u4v*>(slot + Lay::kBlock + (p * NT + q) * 1024)[lane] = v[Lay::kBlockIns + q];
+  for (int q = 0; q < Lay::kVecIns; ++q)
+    reinterpret_cast<u4v*>(slot + Lay::kBlock + (p * Lay::kVecIns + q) * 1024)[lane] =
+        v[Lay::kBlockIns + q];
 }
 
 template <int NT, bool LO>
-__global__ void __launch_bounds__(kWsThreads)
+__global__ void __launch_bounds__(kWsRowThreads, 2)  // 2 wavefronts a SIMD: 256 registers each
 gemm_rows_bf16_ws(const uint32_t* __restrict__ A, const uint16_t* __restrict__ Xs,
                   cpx<double>* __restrict__ P, GemvShape g, int64_t n8, int64_t b0, int nb) {
   using Lay = WsRowsLds<NT, LO>;
   __shared__ __align__(16) char lds[2 * Lay::kSlot];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const WsTiles wt(((g.Nd + kBf16Tile - 1) / kBf16Tile) * g.nf * g.n_pc);
+  const WsTiles wt(((g.Nd + kWsRowTile - 1) / kWsRowTile) * g.nf * g.n_pc);
   const int64_t nsteps = ws_rows_steps(wt, g), npad = ws_padded(nsteps);
   RowsStep st{wt.tile, wt.end, wt.step};
   if (st.valid()) st.decode(g);
-  if (wave >= kWsConsumers) {  // producer
-    const int p = wave - kWsConsumers;
+  if (wave >= kWsRowConsumers) {  // producer
+    const int p = wave - kWsRowConsumers;
     u4v ring[kWsRegRing][Lay::kIns];
     WsRowsOff<NT, LO> off{};  // zeros: a workgroup without tiles loads from the bases
     if (st.valid()) ws_rows_offsets<NT, LO>(A, Xs, g, n8, b0, nb, st, p, lane, off);
@@ -345,7 +358,7 @@ gemm_rows_bf16_ws(const uint32_t* __restrict__ A, const uint16_t* __restrict__ X
     const char* slot = lds + (s & 1) * Lay::kSlot;
     const u4v* blk = reinterpret_cast<const u4v*>(slot);
     const u4v* xs = reinterpret_cast<const u4v*>(slot + Lay::kBlock);
-    const int64_t row0 = st.mt * kBf16Tile + 16 * kWsSub * wave;
+    const int64_t row0 = st.mt * kWsRowTile + 16 * kWsSub * wave;
     if (row0 < g.Nd) {  // rows past Nd in a live wavefront: computed, dropped
       BlockOps a[kWsSub];
 #pragma unroll
@@ -391,7 +404,7 @@ gemm_rows_bf16_ws(const uint32_t* __restrict__ A, const uint16_t* __restrict__ X
 struct ColsStep {
   int64_t tile, end, stride, pt, k, nch, c;
   __device__ void decode(const GemvShape& g) {  // 32-bit divisions: tile counts < 2^31
-    const uint32_t npt = (uint32_t)((g.Nm + kBf16Tile - 1) / kBf16Tile);
+    const uint32_t npt = (uint32_t)((g.Nm + kWsTile - 1) / kWsTile);
     const uint32_t t = (uint32_t)tile;
     k = t / npt;
     pt = t - (uint32_t)k * npt;
@@ -408,12 +421,13 @@ struct ColsStep {
 
 template <int MT, bool LO>
 struct WsColsLds {
-  static constexpr int kRow = kBf16Tile * 4 * (LO ? 2 : 1);  // bytes of one sensor row: 1 KB | 512
+  static constexpr int kRow = kWsTile * 4 * (LO ? 2 : 1);  // bytes of one sensor row: 1 KB | 512
   static constexpr int kBlock = 32 * kRow;
   static constexpr int kVec = 16 * MT * 256;
   static constexpr int kSlot = kBlock + kVec;
   static constexpr int kBlockIns = kBlock / 1024 / kWsProducers;
   static constexpr int kIns = kBlockIns + MT;
+  static_assert(kVec == 1024 * kWsProducers * MT, "MT vector load instructions per producer");
 };
 
 // Block slot layout: sensor row sl of the chunk, granule g (LO: columns 2g,
@@ -442,7 +456,7 @@ __device__ __forceinline__ void ws_cols_offsets(const uint32_t* __restrict__ A,
                                                 int nb, const ColsStep& st, int p, int lane,
                                                 WsColsOff<MT, LO>& o) {
   const int64_t pt = st.pt;
-  o.tbase = reinterpret_cast<const char*>(A) + (st.k * g.Nd * g.Nm + pt * kBf16Tile) * (LO ? 8 : 4);
+  o.tbase = reinterpret_cast<const char*>(A) + (st.k * g.Nd * g.Nm + pt * kWsTile) * (LO ? 8 : 4);
   using Lay = WsColsLds<MT, LO>;
   constexpr int EPG = LO ? 2 : 4;  // columns a granule
 #pragma unroll
@@ -451,7 +465,7 @@ __device__ __forceinline__ void ws_cols_offsets(const uint32_t* __restrict__ A,
     const int sl = LO ? qi : 2 * qi + (lane >> 5);
     const int gr = (LO ? lane : (lane & 31)) ^ ws_cols_swz<LO>(sl);
     // columns past Nm: the row's last granule (dropped)
-    const int64_t col = min<int64_t>(EPG * gr, g.Nm - EPG - pt * kBf16Tile);
+    const int64_t col = min<int64_t>(EPG * gr, g.Nm - EPG - pt * kWsTile);
     o.blk[q] = (uint32_t)(col * (LO ? 8 : 4));
     o.blk2[q] = o.blk[q] + (LO ? 0u : (uint32_t)((lane >> 5) * g.Nm * 4));
   }
@@ -516,7 +530,7 @@ gemm_cols_bf16_ws(const uint32_t* __restrict__ A, const float* __restrict__ scal
   __shared__ __align__(16) char lds[2 * Lay::kSlot];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const WsTiles wt(((g.Nm + kBf16Tile - 1) / kBf16Tile) * g.nf);
+  const WsTiles wt(((g.Nm + kWsTile - 1) / kWsTile) * g.nf);
   const int64_t nsteps = wt.count() * ((g.Nd + 31) / 32), npad = ws_padded(nsteps);
   ColsStep st{wt.tile, wt.end, wt.step};
   if (st.valid()) st.decode(g);
@@ -559,14 +573,14 @@ gemm_cols_bf16_ws(const uint32_t* __restrict__ A, const float* __restrict__ scal
 #pragma unroll
         for (int t = 0; t < MT; ++t) xr[u][t] = xi[u][t] = sr[u][t] = si[u][t] = (f4v){0, 0, 0, 0};
         // the output scale, fetched a tile ahead of its use
-        sc[u] = col_scale(scales, g, st.k, st.pt * kBf16Tile + 16 * (kWsSub * wave + u) + n);
+        sc[u] = col_scale(scales, g, st.k, st.pt * kWsTile + 16 * (kWsSub * wave + u) + n);
       }
     }
     ws_barrier();
     if (!live) continue;
     const char* slot = lds + (s & 1) * Lay::kSlot;
     const u4v* ds = reinterpret_cast<const u4v*>(slot + Lay::kBlock);
-    const int64_t col0 = st.pt * kBf16Tile + 16 * kWsSub * wave;
+    const int64_t col0 = st.pt * kWsTile + 16 * kWsSub * wave;
     if (col0 < g.Nm) {
       BlockOps f[kWsSub];
 #pragma unroll
@@ -612,33 +626,33 @@ bool ws_offsets_fit(const GemvShape& g, int64_t pitch) {
   return (4 * g.nf * 4 + 4) * pitch * 2 < lim && 8 * g.Nm * 8 < lim;
 }
 
-int ws_grid(int64_t tiles) {
+int ws_grid(int64_t tiles, int per_cu) {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 256;
-  const int64_t g = std::min<int64_t>(tiles, cus);
+  const int64_t g = std::min<int64_t>(tiles, (int64_t)cus * per_cu);
   return (int)std::max<int64_t>(kXcds, (g + kXcds - 1) / kXcds * kXcds);
 }
 
 template <bool LO, bool VEC>
 hipError_t rows_passes(const uint32_t* A, const uint16_t* Xs, cpx<double>* P,
                        const GemvShape& g, int64_t n8, hipStream_t s) {
-  const int64_t tiles = ((g.Nd + kBf16Tile - 1) / kBf16Tile) * g.nf * g.n_pc;
-  const unsigned grid = padded_grid(tiles);
+  const unsigned grid = padded_grid(((g.Nd + kBf16Tile - 1) / kBf16Tile) * g.nf * g.n_pc);
   // 16-byte aligned rows, 32-bit tile numbers and lane offsets: the
   // warp-specialised kernel
-  const bool ws = VEC && tiles < (int64_t{1} << 31) && ws_offsets_fit(g, n8);
-  const unsigned wgrid = ws ? (unsigned)ws_grid(tiles) : 0u;
+  const int64_t wtiles = ((g.Nd + kWsRowTile - 1) / kWsRowTile) * g.nf * g.n_pc;
+  const bool ws = VEC && wtiles < (int64_t{1} << 31) && ws_offsets_fit(g, n8);
+  const unsigned wgrid = ws ? (unsigned)ws_grid(wtiles, kWsRowPerCu) : 0u;
   for (int64_t b0 = 0; b0 < g.nrhs; b0 += 64) {
     const int nb = (int)std::min<int64_t>(64, g.nrhs - b0);
     if (ws) {
       if (nb > 32)
-        hipLaunchKernelGGL((gemm_rows_bf16_ws<4, LO>), dim3(wgrid), dim3(kWsThreads), 0, s, A, Xs, P, g, n8, b0, nb);
+        hipLaunchKernelGGL((gemm_rows_bf16_ws<4, LO>), dim3(wgrid), dim3(kWsRowThreads), 0, s, A, Xs, P, g, n8, b0, nb);
       else if (nb > 16)
-        hipLaunchKernelGGL((gemm_rows_bf16_ws<2, LO>), dim3(wgrid), dim3(kWsThreads), 0, s, A, Xs, P, g, n8, b0, nb);
+        hipLaunchKernelGGL((gemm_rows_bf16_ws<2, LO>), dim3(wgrid), dim3(kWsRowThreads), 0, s, A, Xs, P, g, n8, b0, nb);
       else
-        hipLaunchKernelGGL((gemm_rows_bf16_ws<1, LO>), dim3(wgrid), dim3(kWsThreads), 0, s, A, Xs, P, g, n8, b0, nb);
+        hipLaunchKernelGGL((gemm_rows_bf16_ws<1, LO>), dim3(wgrid), dim3(kWsRowThreads), 0, s, A, Xs, P, g, n8, b0, nb);
     } else if (nb > 32)
       hipLaunchKernelGGL((gemm_rows_bf16<4, LO, VEC>), dim3(grid), dim3(kBf16Threads), 0, s, A, Xs, P, g, n8, b0, nb);
     else if (nb > 16)
@@ -660,7 +674,7 @@ hipError_t cols_passes(const uint32_t* A, const float* sc, const uint16_t* Ds,
   // and lane offsets
   const bool ws = (LO ? (g.Nm % 2 == 0) : (g.Nm % 4 == 0)) && tiles < (int64_t{1} << 31) &&
                   ws_offsets_fit(g, nd8);
-  const unsigned wgrid = ws ? (unsigned)ws_grid(tiles) : 0u;
+  const unsigned wgrid = ws ? (unsigned)ws_grid(tiles, 1) : 0u;
   for (int64_t b0 = 0; b0 < g.nrhs; b0 += 64) {
     const int nb = (int)std::min<int64_t>(64, g.nrhs - b0);
     if (ws) {
