@@ -185,9 +185,12 @@ p2o_status p2o_set_mfma_threshold(p2o_handle h, p2o_op op, int64_t min_rhs);
  * precision, on one device, each plan at most once: instances use their
  * own workspaces) so that one call applies all of them.  Per instance the
  * block product takes the vector-unit path or the matrix-core path by its
- * right-hand-side count (p2o_set_mfma_threshold of that plan), and the
- * products of all instances run in ONE persistent kernel launch that walks
- * their work units; each instance's transforms are launched around it.
+ * right-hand-side count (p2o_set_mfma_threshold of that plan).  The
+ * products of the vector-path instances (and of FP64 instances on the
+ * float64 matrix cores) run in ONE persistent kernel launch that walks
+ * their work units; each bfloat16 instance on the matrix-core path gets
+ * its own launch of the single-plan product kernel (bitwise equal
+ * results); each instance's transforms are launched around them.
  * The plans must outlive the batch.  NULL-safe destroy. */
 typedef struct p2o_batch_s* p2o_batch;
 typedef struct p2o_graph_s* p2o_graph;
@@ -203,10 +206,11 @@ p2o_status p2o_batch_apply(p2o_batch b, p2o_op op, const double* const* x,
                            double* const* y, const int64_t* nrhs, void* stream);
 
 /* The persistent kernel has a small table of configurations (its tiles):
- * vector-unit rows per wavefront for F (4, 4, 2, 8), column groups per
- * wavefront for F* (2, 2, 1, 4), and the load ring depth of the bfloat16
- * matrix-core units (1, 2, 1, 1) for candidates 0..3.  All give the same
- * results bit for bit (each output's sums run in the same order).
+ * vector-unit rows per wavefront for F (4, 2, 8) and column groups per
+ * wavefront for F* (2, 1, 4) for candidates 0..2.  All give the same
+ * results bit for bit (each output's sums run in the same order).  A batch
+ * whose instances all have their own launches has an empty persistent
+ * launch: every candidate then times at ~0 ms.
  * p2o_batch_autotune times every candidate's product launch for `op` on
  * these inputs (one whole apply first, then `reps` timed launches), keeps
  * the fastest for this batch and, when P2O_TUNE_CACHE names a file, stores

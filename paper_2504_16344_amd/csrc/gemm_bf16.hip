@@ -91,8 +91,8 @@ unsigned padded_grid(int64_t tiles) { return (unsigned)((tiles + kXcds - 1) / kX
 // into the other slot (finished by every consumer before barrier s) and
 // issue the loads of chunk s + 1 + kWsRegRing into the registers it came
 // from.  Every wavefront runs the same number of steps (the workgroup's
-// chunk count padded to whole register-ring turns; padding steps move
-// zeros and compute nothing), so the barrier counts agree.  Consumers run
+// chunk count padded to whole register-ring turns; padding steps load
+// valid bytes and compute nothing), so the barrier counts agree.  Consumers run
 // the same per-chunk products, in the same order, as the units in
 // matrix_units.h, so results are bitwise equal to theirs.
 constexpr int kWsConsumers = 4;
