@@ -25,12 +25,15 @@ constexpr int64_t kSolvePanel = 256;  // columns per rank-k update of the solves
 // kFullCols is kFull with the grid's x index running over row tiles, so
 // that consecutive work-groups share a column tile of op(B) (for an A small
 // enough to stay in the last-level cache while B streams once).
+// A and C may be the same matrix when N <= TM (one column tile): a
+// work-group reads all of its rows of A before it writes its rows of C, and
+// no other work-group touches those rows (the Cholesky's in-place panel
+// solve L21 = A21 W^T).
 enum { kFull = 0, kTriGrid = 1, kTriMask = 2, kFullCols = 3 };
 template <bool TRANSB, int TRI, bool ACC, int TM>
 __global__ void __launch_bounds__(256)
-dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A,
-             int64_t lda, const double* __restrict__ B, int64_t ldb, double* __restrict__ C,
-             int64_t ldc) {
+dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+             const double* __restrict__ B, int64_t ldb, double* C, int64_t ldc) {
   constexpr int MT = TM / 32;  // MFMA tiles per wavefront and dimension
   __shared__ double sa[kGemmK][TM + 1];
   __shared__ double sb[kGemmK][TM + 1];

@@ -122,6 +122,49 @@ symmetrize(double* __restrict__ K, int64_t n, int64_t T, int mirror) {
 // The first non-positive (or NaN) pivot goes to *info.
 constexpr int kSb = 16;               // sub-block
 constexpr int kNsb = kNb / kSb;       // sub-blocks per side
+
+// 16 x 16 sub-block products on the float64 matrix cores
+// (v_mfma_f64_16x16x4: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] of each 4-deep step; accumulator element q of lane l is
+// C[l / 16 + 4 q][l % 16]).  Sub-blocks live in LDS arrays of row pitch
+// kNb + 1; (r0, c0) is a sub-block's first row and column.
+typedef double sub_d4 __attribute__((ext_vector_type(4)));
+typedef double (*sub_lds)[kNb + 1];
+
+__device__ __forceinline__ sub_d4 sub_load(sub_lds m, int r0, int c0, int lane) {
+  sub_d4 c;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) c[q] = m[r0 + (lane >> 4) + 4 * q][c0 + (lane & 15)];
+  return c;
+}
+
+__device__ __forceinline__ void sub_store(sub_lds m, int r0, int c0, sub_d4 c, int lane) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) m[r0 + (lane >> 4) + 4 * q][c0 + (lane & 15)] = c[q];
+}
+
+// c += sign A B^T with A, B the 16 x 16 sub-blocks at (ar, ac) and (br, bc).
+__device__ __forceinline__ void sub_mul_abt(sub_d4& c, sub_lds A, int ar, int ac, sub_lds B,
+                                            int br, int bc, double sign, int lane) {
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int k = 4 * st + (lane >> 4);
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(sign * A[ar + (lane & 15)][ac + k],
+                                             B[br + (lane & 15)][bc + k], c, 0, 0, 0);
+  }
+}
+
+// c += sign A B with A, B the 16 x 16 sub-blocks at (ar, ac) and (br, bc).
+__device__ __forceinline__ void sub_mul_ab(sub_d4& c, sub_lds A, int ar, int ac, sub_lds B,
+                                           int br, int bc, double sign, int lane) {
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int k = 4 * st + (lane >> 4);
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(sign * A[ar + (lane & 15)][ac + k],
+                                             B[br + k][bc + (lane & 15)], c, 0, 0, 0);
+  }
+}
+
 __global__ void __launch_bounds__(256)
 potrf_diag_inv(double* __restrict__ K, int64_t n, int64_t j0, int bs, double* __restrict__ W,
                int64_t* __restrict__ info) {
@@ -177,84 +220,43 @@ potrf_diag_inv(double* __restrict__ K, int64_t n, int64_t j0, int bs, double* __
       for (int i = 0; i < kSb; ++i) w[o + i][o + lane] = x[i];
     }
     __syncthreads();
-    const int rows = kNb - o - kSb;  // rows below the diagonal sub-block
-    if (rows > 0) {
-      // L_ik = A_ik W_kk^T: entry (rho, c) = sum_{m <= c} A[rho][o + m] W[o + c][o + m]
-      double v[3];
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        const int idx = tid + 256 * q;
-        v[q] = 0.0;
-        if (idx < rows * kSb) {
-          const int rho = o + kSb + idx / kSb, c = idx % kSb;
-          double acc = 0.0;
-          for (int m = 0; m <= c; ++m) acc += a[rho][o + m] * w[o + c][o + m];
-          v[q] = acc;
-        }
+    // panel: L_ik = A_ik W_kk^T for the sub-blocks i below, one a wavefront
+    {
+      const int i = kb + 1 + wave;
+      if (i < kNsb) {
+        sub_d4 acc = {0.0, 0.0, 0.0, 0.0};
+        sub_mul_abt(acc, a, i * kSb, o, w, o, o, 1.0, lane);
+        sub_store(a, i * kSb, o, acc, lane);
       }
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        const int idx = tid + 256 * q;
-        if (idx < rows * kSb) a[o + kSb + idx / kSb][o + idx % kSb] = v[q];
-      }
-      __syncthreads();
-      // trailing lower triangle: A[rho][sig] -= sum_m L[rho][o + m] L[sig][o + m]
-      const int base = o + kSb;
-      for (int idx = tid; idx < rows * rows; idx += 256) {
-        const int rho = base + idx / rows, sig = base + idx % rows;
-        if (sig > rho) continue;
-        double acc = 0.0;
-#pragma unroll
-        for (int m = 0; m < kSb; ++m) acc += a[rho][o + m] * a[sig][o + m];
-        a[rho][sig] -= acc;
-      }
-      __syncthreads();
     }
+    __syncthreads();
+    // trailing sub-blocks (i, j), kb < j <= i: A_ij -= L_ik L_jk^T (the upper
+    // triangle of a diagonal sub-block takes garbage that the factorisation
+    // never reads and overwrites with zeros)
+    int t = 0;  // sub-blocks dealt round-robin to the wavefronts
+    for (int i = kb + 1; i < kNsb; ++i)
+      for (int jj = kb + 1; jj <= i; ++jj, ++t) {
+        if ((t & 3) != wave) continue;
+        sub_d4 acc = sub_load(a, i * kSb, jj * kSb, lane);
+        sub_mul_abt(acc, a, i * kSb, o, a, jj * kSb, o, -1.0, lane);
+        sub_store(a, i * kSb, jj * kSb, acc, lane);
+      }
+    __syncthreads();
   }
-  // off-diagonal sub-blocks of the inverse, block row by block row
+  // off-diagonal sub-blocks of the inverse, block row by block row:
+  // T_ij = sum_{j <= k < i} L_ik W_kj, parked where W_ij goes, then
+  // W_ij = -W_ii T_ij; the j of a block row one a wavefront
   for (int i = 1; i < kNsb; ++i) {
-    double v[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {  // T_ij = sum_{j <= k < i} L_ik W_kj, j < i
-      const int idx = tid + 256 * q;
-      v[q] = 0.0;
-      if (idx < i * kSb * kSb) {
-        const int j = idx / (kSb * kSb), r = (idx / kSb) % kSb, c = idx % kSb;
-        double acc = 0.0;
-        for (int k = j; k < i; ++k)
-          for (int m = 0; m < kSb; ++m) acc += a[i * kSb + r][k * kSb + m] * w[k * kSb + m][j * kSb + c];
-        v[q] = acc;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {  // T parked where W_ij goes
-      const int idx = tid + 256 * q;
-      if (idx < i * kSb * kSb) {
-        const int j = idx / (kSb * kSb), r = (idx / kSb) % kSb, c = idx % kSb;
-        w[i * kSb + r][j * kSb + c] = v[q];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {  // W_ij = -W_ii T_ij
-      const int idx = tid + 256 * q;
-      v[q] = 0.0;
-      if (idx < i * kSb * kSb) {
-        const int j = idx / (kSb * kSb), r = (idx / kSb) % kSb, c = idx % kSb;
-        double acc = 0.0;
-        for (int m = 0; m <= r; ++m) acc += w[i * kSb + r][i * kSb + m] * w[i * kSb + m][j * kSb + c];
-        v[q] = -acc;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const int idx = tid + 256 * q;
-      if (idx < i * kSb * kSb) {
-        const int j = idx / (kSb * kSb), r = (idx / kSb) % kSb, c = idx % kSb;
-        w[i * kSb + r][j * kSb + c] = v[q];
-      }
+    const int jj = wave;
+    if (jj < i) {
+      sub_d4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int k = jj; k < i; ++k) sub_mul_ab(acc, a, i * kSb, k * kSb, w, k * kSb, jj * kSb, 1.0, lane);
+      sub_store(w, i * kSb, jj * kSb, acc, lane);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // T read back by other lanes
+      __builtin_amdgcn_wave_barrier();
+      sub_d4 acc2 = {0.0, 0.0, 0.0, 0.0};
+      sub_mul_ab(acc2, w, i * kSb, i * kSb, w, i * kSb, jj * kSb, -1.0, lane);
+      sub_store(w, i * kSb, jj * kSb, acc2, lane);
     }
     __syncthreads();
   }
@@ -263,17 +265,6 @@ potrf_diag_inv(double* __restrict__ K, int64_t n, int64_t j0, int bs, double* __
     if (u < bs && v <= u) K[(j0 + u) * n + j0 + v] = a[u][v];
     W[idx] = (u < bs && v < bs) ? w[u][v] : 0.0;
   }
-}
-
-// Dst[i][c] = Src[i][c] for i < m, c < bs (Src with leading dimension 64,
-// Dst with leading dimension n).
-__global__ void copy_panel(const double* __restrict__ src, double* __restrict__ dst, int64_t n,
-                           int64_t m, int bs) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= m * kNb) return;
-  const int64_t i = idx / kNb;
-  const int c = (int)(idx % kNb);
-  if (c < bs) dst[i * n + c] = src[idx];
 }
 
 // ------------------------------------------------------ triangular solves
@@ -643,20 +634,22 @@ hipError_t launch_mirror_lower(double* K, int64_t n, hipStream_t s) {
 
 // Blocked right-looking Cholesky of the lower triangle, two levels: panels
 // of kPanel columns, each factored as kNb-wide blocks: the diagonal block
-// factored and inverted (potrf_diag_inv), the column below it formed as the
-// product A21 L11^{-T} on the float64 matrix cores (into the scratch
-// panel, then copied back), and the panel's remaining columns updated by a
-// masked product; after the panel one rank-kPanel update of the trailing
+// factored and inverted (potrf_diag_inv), the column below it formed in
+// place as the product A21 L11^{-T} on the float64 matrix cores, and the
+// panel's remaining columns updated by a masked product; after the panel
+// one rank-kPanel update of the trailing
 // lower triangle on the matrix cores.  The wide trailing update reads and
 // writes the trailing matrix kPanel / kNb times less often than
 // block-by-block updates.  scratch: cholesky_scratch_bytes(n).
 constexpr int64_t kPanel = 512;
-size_t cholesky_scratch_bytes(int64_t n) { return (size_t)(kNb * kNb + n * kNb) * sizeof(double); }
+size_t cholesky_scratch_bytes(int64_t n) {
+  (void)n;
+  return (size_t)kNb * kNb * sizeof(double);  // the inverse of the current diagonal block
+}
 
 hipError_t launch_cholesky(double* K, int64_t n, int64_t* info_dev, double* scratch,
                            hipStream_t s) {
-  double* W = scratch;            // [64][64] inverse of the diagonal block
-  double* T = scratch + kNb * kNb;  // [n][64] the column panel below it
+  double* W = scratch;  // [64][64] inverse of the diagonal block
   for (int64_t p0 = 0; p0 < n; p0 += kPanel) {
     const int64_t p1 = std::min(n, p0 + kPanel);
     for (int64_t j0 = p0; j0 < p1; j0 += kNb) {
@@ -666,12 +659,10 @@ hipError_t launch_cholesky(double* K, int64_t n, int64_t* info_dev, double* scra
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
       if (m > 0) {
-        // L21 = A21 W^T (rows j1 .. n-1 of the block's columns), then back into K
-        e = launch_dgemm_nt_set(false, m, bs, bs, 1.0, K + j1 * n + j0, n, W, kNb, T, kNb, s);
+        // L21 = A21 W^T in place (rows j1 .. n-1 of the block's columns)
+        e = launch_dgemm_nt_set(false, m, bs, bs, 1.0, K + j1 * n + j0, n, W, kNb,
+                                K + j1 * n + j0, n, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(copy_panel, dim3(grid1(m * kNb)), dim3(256), 0, s, T, K + j1 * n + j0,
-                           n, m, bs);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
         // the panel's columns j1 .. p1 - 1, rows j1 .. n - 1 (lower part only)
         e = launch_dgemm_nt_lower_mask(m, p1 - j1, bs, -1.0, K + j1 * n + j0, n,
                                        K + j1 * n + j0, n, K + j1 * n + j1, n, s);
