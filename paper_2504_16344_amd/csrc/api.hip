@@ -235,7 +235,10 @@ p2o_status begin_impl(int64_t Nd, int64_t Nm, int64_t Nt, p2o_prec prec,
   }
   p2o_status st = make_tables(h);
   if (st == P2O_OK) {
-    e = hipMalloc(&h->fhat, (size_t)bytes);
+    // 64 zero bytes past the last block: the matrix-core F* kernel's last
+    // granule of a row may run up to 12 bytes past it (into dropped columns)
+    e = hipMalloc(&h->fhat, (size_t)bytes + 64);
+    if (e == hipSuccess) e = hipMemset(static_cast<char*>(h->fhat) + bytes, 0, 64);
     if (e != hipSuccess) st = hip_fail(e);
   }
   if (st == P2O_OK && is_mixed(prec)) {

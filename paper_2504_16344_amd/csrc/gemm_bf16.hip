@@ -31,9 +31,10 @@
 // multiple of 32 entries.
 //
 // Two kernel families: the single-role kernels below (every wavefront loads
-// and multiplies; also the units of the persistent multi-instance kernel)
-// and the warp-specialised kernels further down, used for single plans
-// whenever rows are 16-byte aligned.  Both give bitwise equal results.
+// and multiplies; also the units of the persistent multi-instance kernel,
+// and the fallback when tile numbers or lane offsets exceed 32 bits) and the
+// warp-specialised kernels further down, used otherwise, at any row
+// alignment.  Both give bitwise equal results.
 #include "matrix_units.h"
 
 namespace p2o {
@@ -147,6 +148,53 @@ __device__ __forceinline__ int64_t ws_padded(int64_t n) {
   return (n + kWsRegRing - 1) / kWsRegRing * kWsRegRing;
 }
 
+// A 16-byte granule of block words at an address aligned to AL bytes: row
+// starts are 16-byte aligned only when a row's byte length is a multiple
+// of 16 (hi+lo: N_m even; hi-only: N_m a multiple of 4), else the granule
+// is loaded in 8- or 4-byte parts (same bytes, more instructions).
+template <int AL>
+__device__ __forceinline__ u4v ld_granule(const char* p) {
+  if constexpr (AL == 16) {
+    return __builtin_nontemporal_load(reinterpret_cast<const u4v*>(p));
+  } else if constexpr (AL == 8) {
+    const u2v x = __builtin_nontemporal_load(reinterpret_cast<const u2v*>(p));
+    const u2v y = __builtin_nontemporal_load(reinterpret_cast<const u2v*>(p + 8));
+    return (u4v){x[0], x[1], y[0], y[1]};
+  } else {
+    static_assert(AL == 4, "granule alignment 16, 8 or 4 bytes");
+    u4v r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      r[i] = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(p) + i);
+    return r;
+  }
+}
+
+// The granule that starts at entry e of a row (`row` points at entry 0, BPE
+// bytes an entry) when only entries below r exist: it is loaded in AL-byte
+// parts (each a whole number of entries, as r is a multiple of AL / BPE)
+// and a part past r re-reads the last part below r, so no byte beyond entry
+// r - 1 is read.
+template <int AL, int BPE>
+__device__ __forceinline__ u4v ld_granule_clamped(const char* row, int64_t e, int64_t r) {
+  constexpr int EPP = AL / BPE;  // entries a part
+  static_assert(EPP >= 1 && AL % BPE == 0, "a part holds whole entries");
+  auto at = [&](int i) { return row + min<int64_t>(e + i * EPP, r - EPP) * BPE; };
+  if constexpr (AL == 16) {
+    return __builtin_nontemporal_load(reinterpret_cast<const u4v*>(at(0)));
+  } else if constexpr (AL == 8) {
+    const u2v x = __builtin_nontemporal_load(reinterpret_cast<const u2v*>(at(0)));
+    const u2v y = __builtin_nontemporal_load(reinterpret_cast<const u2v*>(at(1)));
+    return (u4v){x[0], x[1], y[0], y[1]};
+  } else {
+    static_assert(AL == 4, "granule alignment 16, 8 or 4 bytes");
+    u4v v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(at(i)));
+    return v;
+  }
+}
+
 // F: tile = (row tile mt, frequency k, column chunk pc), mt fastest.
 struct RowsStep {
   int64_t tile, end, stride, mt, k, pc, p0, p1, nch, c;
@@ -252,8 +300,9 @@ __device__ __forceinline__ void ws_rows_offsets(const uint32_t* __restrict__ A,
   }
 }
 
-// Loads of chunk st (or, when !live, of any valid bytes: a padding step).
-template <int NT, bool LO>
+// Loads of chunk st (or, when !live, of any valid bytes: a padding step);
+// block granules aligned to AL bytes.
+template <int NT, bool LO, int AL>
 __device__ __forceinline__ void ws_rows_load(const uint32_t* __restrict__ A,
                                              const uint16_t* __restrict__ Xs, const GemvShape& g,
                                              int64_t n8, int64_t b0, int nb, const RowsStep& st,
@@ -267,17 +316,17 @@ __device__ __forceinline__ void ws_rows_load(const uint32_t* __restrict__ A,
 #pragma unroll
   for (int q = 0; q < Lay::kBlockIns; ++q) {
     const char* ub = (live ? o.bbase[q] : reinterpret_cast<const char*>(A)) + bstep;
-    uint32_t off = o.blk[q];
-    if (tail) {  // granules past the contraction re-read the row's last one (its vector is 0)
+    if (tail) {  // parts past the contraction re-read its last part (their vector entries are 0)
       const int qi = p * Lay::kBlockIns + q;
       int rl, gr;
       ws_rows_lane<LO>(qi, lane, rl, gr);
       const int64_t r0 = min(st.mt * kWsRowTile + qi * RPI, g.Nd - 1);
       const int64_t row = min(st.mt * kWsRowTile + rl, g.Nd - 1);
-      const int64_t e = min<int64_t>(EPG * gr, st.p1 - EPG - base);
-      off = (uint32_t)(((row - r0) * g.Nm + e) * WPE * 4);
+      v[q] = ld_granule_clamped<AL, WPE * 4>(ub + (uint32_t)((row - r0) * g.Nm * WPE * 4),
+                                             EPG * gr, st.p1 - base);
+    } else {
+      v[q] = ld_granule<AL>(ub + o.blk[q]);
     }
-    v[q] = __builtin_nontemporal_load(reinterpret_cast<const u4v*>(ub + off));
   }
 #pragma unroll
   for (int q = 0; q < Lay::kVecIns; ++q) {
@@ -299,7 +348,7 @@ __device__ __forceinline__ void ws_rows_store(char* slot, int p, int lane,
         v[Lay::kBlockIns + q];
 }
 
-template <int NT, bool LO>
+template <int NT, bool LO, int AL>
 __global__ void __launch_bounds__(kWsRowThreads, 2)  // 2 wavefronts a SIMD: 256 registers each
 gemm_rows_bf16_ws(const uint32_t* __restrict__ A, const uint16_t* __restrict__ Xs,
                   cpx<double>* __restrict__ P, GemvShape g, int64_t n8, int64_t b0, int nb) {
@@ -319,7 +368,7 @@ gemm_rows_bf16_ws(const uint32_t* __restrict__ A, const uint16_t* __restrict__ X
     auto load = [&](u4v(&v)[Lay::kIns]) {  // the next chunk of the sequence
       const bool live = st.valid();
       if (live && st.c == 0) ws_rows_offsets<NT, LO>(A, Xs, g, n8, b0, nb, st, p, lane, off);
-      ws_rows_load<NT, LO>(A, Xs, g, n8, b0, nb, st, live, off, p, lane, v);
+      ws_rows_load<NT, LO, AL>(A, Xs, g, n8, b0, nb, st, live, off, p, lane, v);
       if (live) st.next(g);
     };
 #pragma unroll
@@ -464,8 +513,11 @@ __device__ __forceinline__ void ws_cols_offsets(const uint32_t* __restrict__ A,
     const int qi = p * Lay::kBlockIns + q;
     const int sl = LO ? qi : 2 * qi + (lane >> 5);
     const int gr = (LO ? lane : (lane & 31)) ^ ws_cols_swz<LO>(sl);
-    // columns past Nm: the row's last granule (dropped)
-    const int64_t col = min<int64_t>(EPG * gr, g.Nm - EPG - pt * kWsTile);
+    // granules wholly past Nm: the row's last granule (dropped).  When Nm is
+    // not a multiple of EPG the last granule runs up to EPG - 1 entries past
+    // the row (into the next row, or the block array's tail padding): those
+    // columns are dropped too.
+    const int64_t col = min<int64_t>(EPG * gr, (g.Nm - 1 - pt * kWsTile) / EPG * EPG);
     o.blk[q] = (uint32_t)(col * (LO ? 8 : 4));
     o.blk2[q] = o.blk[q] + (LO ? 0u : (uint32_t)((lane >> 5) * g.Nm * 4));
   }
@@ -483,7 +535,7 @@ __device__ __forceinline__ void ws_cols_offsets(const uint32_t* __restrict__ A,
 // Loads of chunk st (or, when !live, of any valid bytes).  Sensors past Nd
 // re-read row Nd - 1; their data planes are zero there (pitch a multiple
 // of 32, zero-padded).
-template <int MT, bool LO>
+template <int MT, bool LO, int AL>
 __device__ __forceinline__ void ws_cols_load(const uint32_t* __restrict__ A,
                                              const uint16_t* __restrict__ Ds, const GemvShape& g,
                                              int64_t nd32, int64_t b0, int nb, const ColsStep& st,
@@ -500,7 +552,7 @@ __device__ __forceinline__ void ws_cols_load(const uint32_t* __restrict__ A,
     const char* ub = live ? o.tbase + min(s0, g.Nd - 1) * row_bytes
                           : reinterpret_cast<const char*>(A);
     const uint32_t off = (LO || s0 + 1 >= g.Nd) ? o.blk[q] : o.blk2[q];
-    v[q] = __builtin_nontemporal_load(reinterpret_cast<const u4v*>(ub + off));
+    v[q] = ld_granule<AL>(ub + off);
   }
 #pragma unroll
   for (int q = 0; q < MT; ++q) {
@@ -521,7 +573,7 @@ __device__ __forceinline__ void ws_cols_store(char* slot, int p, int lane,
     reinterpret_cast<u4v*>(slot + Lay::kBlock + (p * MT + q) * 1024)[lane] = v[Lay::kBlockIns + q];
 }
 
-template <int MT, bool LO>
+template <int MT, bool LO, int AL>
 __global__ void __launch_bounds__(kWsThreads)
 gemm_cols_bf16_ws(const uint32_t* __restrict__ A, const float* __restrict__ scales,
                   const uint16_t* __restrict__ Ds, cpx<float>* __restrict__ Y, GemvShape g,
@@ -542,7 +594,7 @@ gemm_cols_bf16_ws(const uint32_t* __restrict__ A, const float* __restrict__ scal
     auto load = [&](u4v(&v)[Lay::kIns]) {  // as for F
       const bool live = st.valid();
       if (live && st.c == 0) ws_cols_offsets<MT, LO>(A, Ds, g, nd8, b0, nb, st, p, lane, off);
-      ws_cols_load<MT, LO>(A, Ds, g, nd8, b0, nb, st, live, off, p, v);
+      ws_cols_load<MT, LO, AL>(A, Ds, g, nd8, b0, nb, st, live, off, p, v);
       if (live) st.next(g);
     };
 #pragma unroll
@@ -635,24 +687,53 @@ int ws_grid(int64_t tiles, int per_cu) {
   return (int)std::max<int64_t>(kXcds, (g + kXcds - 1) / kXcds * kXcds);
 }
 
+// Alignment of the block rows' granules: 16 bytes when a row's byte length
+// is a multiple of 16, else 8 or (hi only, 4-byte entries) 4.
+template <bool LO>
+int ws_align(int64_t Nm) {
+  const int64_t row_bytes = Nm * (LO ? 8 : 4);
+  return row_bytes % 16 == 0 ? 16 : (row_bytes % 8 == 0 ? 8 : 4);
+}
+
+template <bool LO, int AL>
+void rows_ws_launch(unsigned grid, int nb, const uint32_t* A, const uint16_t* Xs,
+                    cpx<double>* P, const GemvShape& g, int64_t n8, int64_t b0, hipStream_t s) {
+  if (nb > 32)
+    hipLaunchKernelGGL((gemm_rows_bf16_ws<4, LO, AL>), dim3(grid), dim3(kWsRowThreads), 0, s, A, Xs, P, g, n8, b0, nb);
+  else if (nb > 16)
+    hipLaunchKernelGGL((gemm_rows_bf16_ws<2, LO, AL>), dim3(grid), dim3(kWsRowThreads), 0, s, A, Xs, P, g, n8, b0, nb);
+  else
+    hipLaunchKernelGGL((gemm_rows_bf16_ws<1, LO, AL>), dim3(grid), dim3(kWsRowThreads), 0, s, A, Xs, P, g, n8, b0, nb);
+}
+
+template <bool LO, int AL>
+void cols_ws_launch(unsigned grid, int nb, const uint32_t* A, const float* sc,
+                    const uint16_t* Ds, cpx<float>* Y, const GemvShape& g, int64_t nd8,
+                    int64_t b0, hipStream_t s) {
+  if (nb > 32)
+    hipLaunchKernelGGL((gemm_cols_bf16_ws<4, LO, AL>), dim3(grid), dim3(kWsThreads), 0, s, A, sc, Ds, Y, g, nd8, b0, nb);
+  else if (nb > 16)
+    hipLaunchKernelGGL((gemm_cols_bf16_ws<2, LO, AL>), dim3(grid), dim3(kWsThreads), 0, s, A, sc, Ds, Y, g, nd8, b0, nb);
+  else
+    hipLaunchKernelGGL((gemm_cols_bf16_ws<1, LO, AL>), dim3(grid), dim3(kWsThreads), 0, s, A, sc, Ds, Y, g, nd8, b0, nb);
+}
+
 template <bool LO, bool VEC>
 hipError_t rows_passes(const uint32_t* A, const uint16_t* Xs, cpx<double>* P,
                        const GemvShape& g, int64_t n8, hipStream_t s) {
   const unsigned grid = padded_grid(((g.Nd + kBf16Tile - 1) / kBf16Tile) * g.nf * g.n_pc);
-  // 16-byte aligned rows, 32-bit tile numbers and lane offsets: the
-  // warp-specialised kernel
+  // 32-bit tile numbers and lane offsets: the warp-specialised kernel, its
+  // block loads at the rows' alignment
   const int64_t wtiles = ((g.Nd + kWsRowTile - 1) / kWsRowTile) * g.nf * g.n_pc;
-  const bool ws = VEC && wtiles < (int64_t{1} << 31) && ws_offsets_fit(g, n8);
+  const bool ws = wtiles < (int64_t{1} << 31) && ws_offsets_fit(g, n8);
   const unsigned wgrid = ws ? (unsigned)ws_grid(wtiles, kWsRowPerCu) : 0u;
+  const int al = ws_align<LO>(g.Nm);
   for (int64_t b0 = 0; b0 < g.nrhs; b0 += 64) {
     const int nb = (int)std::min<int64_t>(64, g.nrhs - b0);
     if (ws) {
-      if (nb > 32)
-        hipLaunchKernelGGL((gemm_rows_bf16_ws<4, LO>), dim3(wgrid), dim3(kWsRowThreads), 0, s, A, Xs, P, g, n8, b0, nb);
-      else if (nb > 16)
-        hipLaunchKernelGGL((gemm_rows_bf16_ws<2, LO>), dim3(wgrid), dim3(kWsRowThreads), 0, s, A, Xs, P, g, n8, b0, nb);
-      else
-        hipLaunchKernelGGL((gemm_rows_bf16_ws<1, LO>), dim3(wgrid), dim3(kWsRowThreads), 0, s, A, Xs, P, g, n8, b0, nb);
+      if (al == 16) rows_ws_launch<LO, 16>(wgrid, nb, A, Xs, P, g, n8, b0, s);
+      else if (LO || al == 8) rows_ws_launch<LO, 8>(wgrid, nb, A, Xs, P, g, n8, b0, s);
+      else rows_ws_launch<LO, LO ? 8 : 4>(wgrid, nb, A, Xs, P, g, n8, b0, s);  // hi only
     } else if (nb > 32)
       hipLaunchKernelGGL((gemm_rows_bf16<4, LO, VEC>), dim3(grid), dim3(kBf16Threads), 0, s, A, Xs, P, g, n8, b0, nb);
     else if (nb > 16)
@@ -670,20 +751,17 @@ hipError_t cols_passes(const uint32_t* A, const float* sc, const uint16_t* Ds,
                        cpx<float>* Y, const GemvShape& g, int64_t nd8, hipStream_t s) {
   const int64_t tiles = ((g.Nm + kBf16Tile - 1) / kBf16Tile) * g.nf;
   const unsigned grid = padded_grid(tiles);
-  // 16-byte loads of block granules need aligned rows; 32-bit tile numbers
-  // and lane offsets
-  const bool ws = (LO ? (g.Nm % 2 == 0) : (g.Nm % 4 == 0)) && tiles < (int64_t{1} << 31) &&
-                  ws_offsets_fit(g, nd8);
+  // 32-bit tile numbers and lane offsets: the warp-specialised kernel, its
+  // block loads at the rows' alignment
+  const bool ws = tiles < (int64_t{1} << 31) && ws_offsets_fit(g, nd8);
   const unsigned wgrid = ws ? (unsigned)ws_grid(tiles, 1) : 0u;
+  const int al = ws_align<LO>(g.Nm);
   for (int64_t b0 = 0; b0 < g.nrhs; b0 += 64) {
     const int nb = (int)std::min<int64_t>(64, g.nrhs - b0);
     if (ws) {
-      if (nb > 32)
-        hipLaunchKernelGGL((gemm_cols_bf16_ws<4, LO>), dim3(wgrid), dim3(kWsThreads), 0, s, A, sc, Ds, Y, g, nd8, b0, nb);
-      else if (nb > 16)
-        hipLaunchKernelGGL((gemm_cols_bf16_ws<2, LO>), dim3(wgrid), dim3(kWsThreads), 0, s, A, sc, Ds, Y, g, nd8, b0, nb);
-      else
-        hipLaunchKernelGGL((gemm_cols_bf16_ws<1, LO>), dim3(wgrid), dim3(kWsThreads), 0, s, A, sc, Ds, Y, g, nd8, b0, nb);
+      if (al == 16) cols_ws_launch<LO, 16>(wgrid, nb, A, sc, Ds, Y, g, nd8, b0, s);
+      else if (LO || al == 8) cols_ws_launch<LO, 8>(wgrid, nb, A, sc, Ds, Y, g, nd8, b0, s);
+      else cols_ws_launch<LO, LO ? 8 : 4>(wgrid, nb, A, sc, Ds, Y, g, nd8, b0, s);  // hi only
     } else if (nb > 32)
       hipLaunchKernelGGL((gemm_cols_bf16<4, LO>), dim3(grid), dim3(kBf16Threads), 0, s, A, sc, Ds, Y, g, nd8, b0, nb);
     else if (nb > 16)

@@ -38,23 +38,32 @@ def test_mfma_and_vector_paths_match_oracle(shape):
 
 @pytest.mark.parametrize("prec,tol", [("mixed_bf16", 1e-5), ("fast_bf16", 2e-2)])
 @pytest.mark.parametrize("shape", [(37, 300, 13, 5), (17, 1001, 97, 20), (130, 1028, 33, 70),
-                                   (100, 777, 40, 33), (5, 4100, 8, 17)],
+                                   (100, 777, 40, 33), (5, 4100, 8, 17), (20, 33, 9, 40),
+                                   (12, 34, 7, 18), (140, 1030, 21, 36)],
                          ids=lambda s: "x".join(map(str, s)))
 def test_bf16_matrix_core_path_matches_oracle(shape, prec, tol):
     """bfloat16 matrix-core products (hi+lo vector split, float32 accumulation)
-    against the oracle; odd Nm exercises the unaligned block loads and
-    Nm > 4096 several scale tiles per column chunk."""
+    against the oracle and against the vector-unit products of the same tier
+    (same operand precision: they differ by float32 rounding only, so a
+    misplaced block entry shows far above it); Nm of every residue modulo 4
+    exercises block rows at 16-, 8- and 4-byte alignment and every length of
+    the last 32-entry chunk's ragged tail, Nm > 4096 several scale tiles per
+    column chunk."""
     Nd, Nm, Nt, nrhs = shape
     print(f"\n[multi-rhs {prec}] shape={shape}", flush=True)
     blocks, m, d = workload(12, Nd, Nm, Nt, tau=Nt / 3, nrhs=nrhs)
     ref_F = oracle.apply_F(blocks, m)
     ref_A = oracle.apply_Fadj(blocks, d)
+    out = {}
     with P.Plan(dev(blocks), prec) as plan:
         for name, thr in (("mfma", 1), ("vector", 0)):
             plan.set_mfma_threshold(P.OP_F, thr)
             plan.set_mfma_threshold(P.OP_FADJ, thr)
-            check_close(host(plan.F(dev(m))), ref_F, tol, f"{name} F")
-            check_close(host(plan.FT(dev(d))), ref_A, tol, f"{name} F*")
+            out[name] = (host(plan.F(dev(m))), host(plan.FT(dev(d))))
+            check_close(out[name][0], ref_F, tol, f"{name} F")
+            check_close(out[name][1], ref_A, tol, f"{name} F*")
+    for i, op in enumerate(("F", "F*")):
+        assert rel_err(out["mfma"][i], out["vector"][i]) <= 1e-3, op
 
 
 @pytest.mark.parametrize("op", ["F", "FADJ"])
