@@ -131,6 +131,162 @@ dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int
       }
 }
 
+// ------------------------------------------ C (+)= alpha A B^T, large shapes
+// For the big contractions with both operands row-major along the
+// contraction (the Cholesky's trailing rank-512 updates, the Gram matrix,
+// the solves' rank-256 updates): a 128 x 128 tile of C a work-group, each
+// of its 4 wavefronts a 64 x 64 quarter (4 x 4 v_mfma_f64_16x16x4 tiles,
+// 128 accumulator registers), so every operand value read from LDS feeds 4
+// products and every byte staged feeds twice as many flops as on 64 x 64
+// tiles.  The contraction is cut into 16-entry chunks: one 128-byte line of
+// each operand row, loaded as 16-byte vectors and stored unchanged into
+// LDS (granule G = entries 2G, 2G + 1 of row r at granule G ^ ((r / 2) mod
+// 8), so the 16 rows a lane group reads at one granule fall on 16
+// different bank groups).  Lane group q takes contraction entries 4q .. 4q
+// + 3 of a chunk (one ds_read_b128 for two products), in the same order for
+// both operands, so the chunk's sum is complete.  Two LDS stages and one
+// barrier (without memory fences) per chunk: while the products of chunk c
+// run, chunk c + 1 is already in the other stage and chunk c + 2 is in
+// flight into registers.  Rows past M (N) re-read row M - 1 (N - 1) and are
+// dropped; entries past K are zero in both operands.
+constexpr int kNtTile = 128;
+constexpr int kNtK = 16;
+constexpr int kNtStage = kNtTile * kNtK;  // doubles of one operand in one stage
+
+__device__ __forceinline__ int nt_lds_pos(int r, int g) { return r * kNtK + 2 * (g ^ ((r >> 1) & 7)); }
+
+// This wavefront's LDS accesses have completed.
+__device__ __forceinline__ void nt_wait_lds() {
+  __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8) | (3 << 14));
+}
+
+// Work-group barrier without the memory fences of __syncthreads (which
+// would also wait for the next chunk's global loads); the compiler moves no
+// memory access across it.
+__device__ __forceinline__ void nt_barrier() {
+  __asm__ volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  __asm__ volatile("" ::: "memory");
+}
+
+// TRI: kFull (tile t = I tc + J) or kTriGrid (tiles I >= J, entries above
+// the diagonal untouched).  Both operands 16-byte aligned with even leading
+// dimensions (the launcher checks).
+template <int TRI, bool ACC>
+__global__ void __launch_bounds__(256, 2)
+dgemm_nt128_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A,
+                   int64_t lda, const double* __restrict__ B, int64_t ldb, double* __restrict__ C,
+                   int64_t ldc, int64_t tiles) {
+  __shared__ __align__(16) double lds[2][2][kNtStage];  // [stage][A | B]
+  const int64_t t = xcd_local_tile(blockIdx.x, gridDim.x);
+  if (t >= tiles) return;  // grid padding
+  int64_t ti_, tj_;
+  if constexpr (TRI == kTriGrid) {
+    int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) / 2.0);
+    while (I * (I + 1) / 2 > t) --I;
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    ti_ = I;
+    tj_ = t - I * (I + 1) / 2;
+  } else {
+    const int64_t tc = (N + kNtTile - 1) / kNtTile;
+    ti_ = t / tc;
+    tj_ = t - ti_ * tc;
+  }
+  const int64_t i0 = ti_ * kNtTile, j0 = tj_ * kNtTile;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+  // loader: granule lg of rows lr + 32 u (u < 4) of both operands
+  const int lg = tid & 7, lr = tid >> 3;
+  const double* pa[4];
+  const double* pb[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    pa[u] = A + min(i0 + lr + 32 * u, M - 1) * lda + 2 * lg;
+    pb[u] = B + min(j0 + lr + 32 * u, N - 1) * ldb + 2 * lg;
+  }
+  d2v ra[4], rb[4];
+  auto load = [&](int64_t k0) {
+    if (k0 + kNtK <= K) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        ra[u] = *reinterpret_cast<const d2v*>(pa[u] + k0);
+        rb[u] = *reinterpret_cast<const d2v*>(pb[u] + k0);
+      }
+    } else {  // the contraction's ragged end
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int64_t e = k0 + 2 * lg + h;  // contraction index of this entry
+          const int64_t ec = min(e, K - 1) - 2 * lg;
+          const double x = pa[u][ec], y = pb[u][ec];
+          ra[u][h] = e < K ? x : 0.0;
+          rb[u][h] = e < K ? y : 0.0;
+        }
+    }
+  };
+  auto store = [&](int st) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      *reinterpret_cast<d2v*>(&lds[st][0][nt_lds_pos(lr + 32 * u, lg)]) = ra[u];
+      *reinterpret_cast<d2v*>(&lds[st][1][nt_lds_pos(lr + 32 * u, lg)]) = rb[u];
+    }
+  };
+  d4v acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = (d4v){0, 0, 0, 0};
+  const int64_t nc = (K + kNtK - 1) / kNtK;
+  load(0);
+  store(0);
+  if (nc > 1) load(kNtK);
+  nt_wait_lds();
+  nt_barrier();
+  for (int64_t c = 0; c < nc; ++c) {
+    const int cur = (int)(c & 1);
+    if (c + 1 < nc) {  // chunk c + 1 into the other stage (read by chunk c - 1's products, done)
+      store(cur ^ 1);
+      if (c + 2 < nc) load((c + 2) * kNtK);
+    }
+    const double* sa = lds[cur][0];
+    const double* sb = lds[cur][1];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {  // contraction entries 4 kq + 2 h + {0, 1}
+      d2v a[4], b[4];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        a[f] = *reinterpret_cast<const d2v*>(&sa[nt_lds_pos(wr + 16 * f + col, 2 * kq + h)]);
+        b[f] = *reinterpret_cast<const d2v*>(&sb[nt_lds_pos(wc + 16 * f + col, 2 * kq + h)]);
+      }
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int fi = 0; fi < 4; ++fi)
+#pragma unroll
+          for (int fj = 0; fj < 4; ++fj) acc[fi][fj] = mfma64(a[fi][e], b[fj][e], acc[fi][fj]);
+    }
+    nt_wait_lds();
+    nt_barrier();
+  }
+#pragma unroll
+  for (int fi = 0; fi < 4; ++fi)
+#pragma unroll
+    for (int fj = 0; fj < 4; ++fj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gi = i0 + wr + 16 * fi + kq + 4 * r;  // accumulator rows interleave
+        const int64_t gj = j0 + wc + 16 * fj + col;
+        if (gi < M && gj < N && (TRI == kFull || gj <= gi)) {
+          if constexpr (ACC)
+            C[gi * ldc + gj] += alpha * acc[fi][fj][r];
+          else
+            C[gi * ldc + gj] = alpha * acc[fi][fj][r];
+        }
+      }
+}
+
 // Prefix sums along the block diagonals of X (rows (a, i) = a P + i, columns
 // (b, j) = b Q + j, a, b < T):
 //   X[(a, i)][(b, j)] <- sum_{l = 0 .. min(a, b)} X[(a - l, i)][(b - l, j)].
@@ -340,9 +496,33 @@ hipError_t launch_gemm(int64_t M, int64_t N, int64_t K, double alpha, const doub
   return hipGetLastError();
 }
 
+// The 128 x 128 kernel: both operands 16-byte aligned with even leading
+// dimensions, and C large enough that its fewer, larger tiles still fill
+// the chip.
+bool nt128_fits(int64_t M, int64_t N, const double* A, int64_t lda, const double* B,
+                int64_t ldb) {
+  const uintptr_t al = reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B);
+  return al % 16 == 0 && lda % 2 == 0 && ldb % 2 == 0 && std::min(M, N) >= 512;
+}
+
+template <int TRI, bool ACC>
+hipError_t launch_gemm_nt128(int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                             int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
+                             hipStream_t s) {
+  const int64_t tr = (M + kNtTile - 1) / kNtTile, tc = (N + kNtTile - 1) / kNtTile;
+  const int64_t tiles = TRI == kTriGrid ? tr * (tr + 1) / 2 : tr * tc;
+  const int64_t grid = (tiles + kXcds - 1) / kXcds * kXcds;
+  if (grid > 0x7fffffff) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((dgemm_nt128_kernel<TRI, ACC>), dim3((unsigned)grid), dim3(256), 0, s, M, N,
+                     K, alpha, A, lda, B, ldb, C, ldc, tiles);
+  return hipGetLastError();
+}
+
 hipError_t launch_dgemm(bool transb, int64_t M, int64_t N, int64_t K, double alpha,
                         const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
                         int64_t ldc, hipStream_t s) {
+  if (transb && M > 0 && N > 0 && K > 0 && nt128_fits(M, N, A, lda, B, ldb))
+    return launch_gemm_nt128<kFull, true>(M, N, K, alpha, A, lda, B, ldb, C, ldc, s);
   if (transb) return launch_gemm<true, kFull, true>(M, N, K, alpha, A, lda, B, ldb, C, ldc, s);
   return launch_gemm<false, kFull, true>(M, N, K, alpha, A, lda, B, ldb, C, ldc, s);
 }
@@ -351,6 +531,8 @@ hipError_t launch_dgemm_nt_set(bool lower, int64_t M, int64_t N, int64_t K, doub
                                const double* A, int64_t lda, const double* B, int64_t ldb,
                                double* C, int64_t ldc, hipStream_t s) {
   if (M <= 0 || N <= 0 || K <= 0 || (lower && M != N)) return hipErrorInvalidValue;
+  if (lower && nt128_fits(M, N, A, lda, B, ldb))
+    return launch_gemm_nt128<kTriGrid, false>(M, N, K, alpha, A, lda, B, ldb, C, ldc, s);
   if (lower)
     return launch_gemm<true, kTriGrid, false>(M, N, K, alpha, A, lda, B, ldb, C, ldc, s);
   // row tiles along x: A stays cached while B streams once
@@ -360,6 +542,8 @@ hipError_t launch_dgemm_nt_set(bool lower, int64_t M, int64_t N, int64_t K, doub
 hipError_t launch_dgemm_nt_lower(int64_t n, int64_t K, double alpha, const double* A,
                                  int64_t lda, const double* B, int64_t ldb, double* C,
                                  int64_t ldc, hipStream_t s) {
+  if (n > 0 && K > 0 && nt128_fits(n, n, A, lda, B, ldb))
+    return launch_gemm_nt128<kTriGrid, true>(n, n, K, alpha, A, lda, B, ldb, C, ldc, s);
   return launch_gemm<true, kTriGrid, true>(n, n, K, alpha, A, lda, B, ldb, C, ldc, s);
 }
 
@@ -380,6 +564,8 @@ hipError_t launch_block_diag_scan(double* X, int64_t ld, int64_t T, int64_t P, i
 
 hipError_t launch_dsyrk_lower(int64_t n, int64_t K, double alpha, const double* A, int64_t lda,
                               double* C, int64_t ldc, hipStream_t s) {
+  if (n > 0 && K > 0 && nt128_fits(n, n, A, lda, A, lda))
+    return launch_gemm_nt128<kTriGrid, true>(n, n, K, alpha, A, lda, A, lda, C, ldc, s);
   return launch_gemm<true, kTriGrid, true>(n, n, K, alpha, A, lda, A, lda, C, ldc, s);
 }
 

@@ -27,6 +27,7 @@ def _noise(seed, n, lo=0.05, hi=0.5):
     ((5, 300, 29), 2, 2),
     ((10, 500, 60), 1, 1),
     ((20, 300, 55), 2, 1),
+    ((12, 200, 110), 2, 1),  # n = 1320: trailing updates on 128 x 128 tiles, ragged edges
 ])
 def test_hessian_and_posterior_match_oracle(shape, nrhs, refine):
     Nd, Nm, Nt = shape
