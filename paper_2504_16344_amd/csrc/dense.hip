@@ -114,6 +114,22 @@ dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int
       }
     }
   }
+  // C: all reads (clamped addresses) before the masked writes, so a lane
+  // waits for one round trip, not one per entry.  (C is read only when
+  // accumulating; the in-place use, A aliasing C, overwrites.)
+  double cv[MT][MT][4];
+  if constexpr (ACC) {
+#pragma unroll
+    for (int ti = 0; ti < MT; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < MT; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gi = min(i0 + wr + 16 * ti + kq + 4 * r, M - 1);
+          const int64_t gj = min(j0 + wc + 16 * tj + col, N - 1);
+          cv[ti][tj][r] = C[gi * ldc + gj];
+        }
+  }
 #pragma unroll
   for (int ti = 0; ti < MT; ++ti)
 #pragma unroll
@@ -122,12 +138,8 @@ dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int
       for (int r = 0; r < 4; ++r) {
         const int64_t gi = i0 + wr + 16 * ti + kq + 4 * r;  // accumulator rows interleave
         const int64_t gj = j0 + wc + 16 * tj + col;
-        if (gi < M && gj < N && (TRI == kFull || TRI == kFullCols || gj <= gi)) {
-          if constexpr (ACC)
-            C[gi * ldc + gj] += alpha * acc[ti][tj][r];
-          else
-            C[gi * ldc + gj] = alpha * acc[ti][tj][r];
-        }
+        if (gi < M && gj < N && (TRI == kFull || TRI == kFullCols || gj <= gi))
+          C[gi * ldc + gj] = ACC ? cv[ti][tj][r] + alpha * acc[ti][tj][r] : alpha * acc[ti][tj][r];
       }
 }
 
@@ -270,21 +282,31 @@ dgemm_nt128_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* 
     nt_wait_lds();
     nt_barrier();
   }
+  // C: per 16-row group, all reads (clamped addresses) before the masked
+  // writes, so a lane waits for one round trip per group, not per entry
 #pragma unroll
-  for (int fi = 0; fi < 4; ++fi)
+  for (int fi = 0; fi < 4; ++fi) {
+    double cv[4][4];
+    if constexpr (ACC) {
+#pragma unroll
+      for (int fj = 0; fj < 4; ++fj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gi = min(i0 + wr + 16 * fi + kq + 4 * r, M - 1);
+          const int64_t gj = min(j0 + wc + 16 * fj + col, N - 1);
+          cv[fj][r] = C[gi * ldc + gj];
+        }
+    }
 #pragma unroll
     for (int fj = 0; fj < 4; ++fj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t gi = i0 + wr + 16 * fi + kq + 4 * r;  // accumulator rows interleave
         const int64_t gj = j0 + wc + 16 * fj + col;
-        if (gi < M && gj < N && (TRI == kFull || gj <= gi)) {
-          if constexpr (ACC)
-            C[gi * ldc + gj] += alpha * acc[fi][fj][r];
-          else
-            C[gi * ldc + gj] = alpha * acc[fi][fj][r];
-        }
+        if (gi < M && gj < N && (TRI == kFull || gj <= gi))
+          C[gi * ldc + gj] = ACC ? cv[fj][r] + alpha * acc[fi][fj][r] : alpha * acc[fi][fj][r];
       }
+  }
 }
 
 // Prefix sums along the block diagonals of X (rows (a, i) = a P + i, columns
