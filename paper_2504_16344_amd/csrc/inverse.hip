@@ -120,6 +120,22 @@ symmetrize(double* __restrict__ K, int64_t n, int64_t T, int mirror) {
 //   then the off-diagonal sub-blocks of the inverse, block row by block row:
 //   W_ij = -W_ii (sum_{j <= k < i} L_ik W_kj).
 // The first non-positive (or NaN) pivot goes to *info.
+// sqrt(d) and 1 / sqrt(d) for d > 0, for the factorisation's serial chain:
+// the hardware reciprocal square root refined by three Newton steps on
+// y = 1 / sqrt(d) (y <- y + y (1/2 - d y^2 / 2); each doubles the correct
+// bits, enough from any start better than 2^-8), then g = d y corrected
+// once by the residual d - g^2 (exact in a fused multiply-add): both within
+// a unit or two in the last place, at the cost of a few multiply-adds
+// instead of a rounded square root and a division.  NaN for d <= 0 (the
+// caller reports the pivot).
+__device__ __forceinline__ void sqrt_and_rsqrt(double d, double& g, double& y) {
+  y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int it = 0; it < 3; ++it) y = __builtin_fma(y, __builtin_fma(-0.5 * d * y, y, 0.5), y);
+  g = d * y;
+  g = __builtin_fma(0.5 * y, __builtin_fma(-g, g, d), g);
+}
+
 constexpr int kSb = 16;               // sub-block
 constexpr int kNsb = kNb / kSb;       // sub-blocks per side
 
@@ -182,7 +198,8 @@ potrf_diag_inv(double* __restrict__ K, int64_t n, int64_t j0, int bs, double* __
   for (int kb = 0; kb < kNsb; ++kb) {
     const int o = kb * kSb;
     if (wave == 0 && lane < kSb) {
-      double r[kSb];  // row `lane` of the diagonal sub-block
+      double r[kSb];     // row `lane` of the diagonal sub-block
+      double dinv[kSb];  // 1 / L_kk, the same in every lane
 #pragma unroll
       for (int j = 0; j < kSb; ++j) r[j] = a[o + lane][o + j];
 #pragma unroll
@@ -192,7 +209,9 @@ potrf_diag_inv(double* __restrict__ K, int64_t n, int64_t j0, int bs, double* __
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         const double d = colk[0];
         if (lane == 0 && !(d > 0.0) && o + k < bs && *info < 0) *info = j0 + o + k;
-        const double piv = sqrt(d), pinv = 1.0 / piv;
+        double piv, pinv;
+        sqrt_and_rsqrt(d, piv, pinv);
+        dinv[k] = pinv;
         r[k] = (lane == k) ? piv : (lane > k ? r[k] * pinv : r[k]);
         __builtin_amdgcn_wave_barrier();
         colk[lane] = r[k];
@@ -207,14 +226,18 @@ potrf_diag_inv(double* __restrict__ K, int64_t n, int64_t j0, int bs, double* __
       for (int j = 0; j < kSb; ++j) a[o + lane][o + j] = (j <= lane) ? r[j] : 0.0;
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      double x[kSb];  // column `lane` of the sub-block's inverse
+      // column `lane` of the sub-block's inverse, by a column sweep: x_k is
+      // final once scaled by 1 / L_kk, then removed from the rows below
+      // (independent updates, so the serial chain is one multiply and one
+      // fused multiply-add a step)
+      double x[kSb];
 #pragma unroll
-      for (int i = 0; i < kSb; ++i) {
-        double acc = 0.0;
+      for (int i = 0; i < kSb; ++i) x[i] = (i == lane) ? 1.0 : 0.0;
 #pragma unroll
-        for (int k = 0; k < i; ++k) acc += a[o + i][o + k] * x[k];
-        const double d = a[o + i][o + i];
-        x[i] = (i < lane) ? 0.0 : (i == lane ? 1.0 / d : -acc / d);
+      for (int k = 0; k < kSb; ++k) {
+        x[k] *= dinv[k];
+#pragma unroll
+        for (int i = k + 1; i < kSb; ++i) x[i] -= a[o + i][o + k] * x[k];
       }
 #pragma unroll
       for (int i = 0; i < kSb; ++i) w[o + i][o + lane] = x[i];
