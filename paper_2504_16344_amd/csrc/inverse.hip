@@ -204,23 +204,28 @@ potrf_diag_inv(double* __restrict__ K, int64_t n, int64_t j0, int bs, double* __
       for (int j = 0; j < kSb; ++j) r[j] = a[o + lane][o + j];
 #pragma unroll
       for (int k = 0; k < kSb; ++k) {
-        if (lane == k) colk[0] = r[k];
+        // column k as updated so far, the pivot included, goes through LDS
+        // once; every lane scales the entries it needs itself (the same
+        // product the owning lane forms), so a step waits for one round trip
+        colk[lane] = r[k];
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        const double d = colk[0];
+        const double d = colk[k];
+        double col[kSb];
+#pragma unroll
+        for (int t = k + 1; t < kSb; ++t) col[t] = colk[t];
         if (lane == 0 && !(d > 0.0) && o + k < bs && *info < 0) *info = j0 + o + k;
         double piv, pinv;
         sqrt_and_rsqrt(d, piv, pinv);
         dinv[k] = pinv;
         r[k] = (lane == k) ? piv : (lane > k ? r[k] * pinv : r[k]);
-        __builtin_amdgcn_wave_barrier();
-        colk[lane] = r[k];
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         const double lik = (lane > k) ? r[k] : 0.0;
 #pragma unroll
-        for (int t = k + 1; t < kSb; ++t) r[t] -= lik * colk[t];
+        for (int t = k + 1; t < kSb; ++t) r[t] -= lik * (col[t] * pinv);
+        // this step's reads of colk precede the next step's write (one
+        // wavefront: LDS accesses complete in issue order)
         __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       }
 #pragma unroll
       for (int j = 0; j < kSb; ++j) a[o + lane][o + j] = (j <= lane) ? r[j] : 0.0;
