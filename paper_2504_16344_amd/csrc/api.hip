@@ -1074,10 +1074,12 @@ p2o_status p2o_posterior_invert(p2o_handle h, const double* Kfac, double* Kinv, 
   (void)hipGetLastError();
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = h->Nt * h->Nd;
-  // row j of Kinv = K^{-1} e_j: the solves of K X = I, all n at once
+  // row j of Kinv = K^{-1} e_j: the solves of K X = I, all n at once,
+  // restricted to the upper triangle, which is then mirrored (exactly
+  // symmetric)
   TRY_HIP(launch_identity(Kinv, n, s));
-  TRY_HIP(launch_cholesky_solve_many(Kfac, Kinv, n, n, s));
-  TRY_HIP(launch_mirror_lower(Kinv, n, s));  // exactly symmetric
+  TRY_HIP(launch_cholesky_inverse_upper(Kfac, Kinv, n, s));
+  TRY_HIP(launch_mirror_upper(Kinv, n, s));
   TRY_HIP(hipStreamSynchronize(s));
   return P2O_OK;
 }

@@ -597,10 +597,17 @@ hipError_t launch_dsyrk_lower(int64_t n, int64_t K, double alpha, const double* 
 // matrix-core GEMMs (forward: Y[:, rest] -= Y[:, blk] L[rest, blk]^T;
 // backward: Y[:, 0 : j0] -= Y[:, blk] L[blk, 0 : j0]), the updates beyond
 // the current panel of kSolvePanel columns deferred and done as one.
-hipError_t launch_cholesky_solve_many(const double* K, double* Y, int64_t n, int64_t nrhs,
-                                      hipStream_t s) {
-  const unsigned g = grid_rhs(nrhs);
+namespace {
+// The sweeps below for all nrhs right-hand sides, or (INV, Y = I, nrhs = n)
+// only for the rows whose result is needed: row r of L^{-1} I is zero before
+// column r, so a forward step on columns below c1 touches rows r < c1 only;
+// of X = K^{-1} (symmetric) only the entries c >= r are kept, so a backward
+// step that updates columns below c0 needs rows r < c0 only.  About half the
+// work of the full solve.
+hipError_t solve_many_sweeps(const double* K, double* Y, int64_t n, int64_t nrhs, bool inv,
+                             hipStream_t s) {
   hipError_t e = hipSuccess;
+  auto rows = [&](int64_t c) { return inv ? std::min(nrhs, c) : nrhs; };
   // forward, L Z = Y: panels of kSolvePanel columns; inside a panel block by
   // block (diagonal solve, update of the panel's later columns), then one
   // rank-kSolvePanel update of all later columns
@@ -608,13 +615,14 @@ hipError_t launch_cholesky_solve_many(const double* K, double* Y, int64_t n, int
     const int64_t p1 = std::min(n, p0 + kSolvePanel);
     for (int64_t j0 = p0; j0 < p1; j0 += kTriNb) {
       const int bs = (int)std::min<int64_t>(kTriNb, p1 - j0);
-      hipLaunchKernelGGL(trsm_lower_diag_many, dim3(g), dim3(256), 0, s, K, Y, n, nrhs, j0, bs);
       const int64_t j1 = j0 + bs;
-      if (j1 < p1 && (e = launch_dgemm(true, nrhs, p1 - j1, bs, -1.0, Y + j0, n,
+      hipLaunchKernelGGL(trsm_lower_diag_many, dim3(grid_rhs(rows(j1))), dim3(256), 0, s, K, Y, n,
+                         rows(j1), j0, bs);
+      if (j1 < p1 && (e = launch_dgemm(true, rows(j1), p1 - j1, bs, -1.0, Y + j0, n,
                                        K + j1 * n + j0, n, Y + j1, n, s)) != hipSuccess)
         return e;
     }
-    if (p1 < n && (e = launch_dgemm(true, nrhs, n - p1, p1 - p0, -1.0, Y + p0, n,
+    if (p1 < n && (e = launch_dgemm(true, rows(p1), n - p1, p1 - p0, -1.0, Y + p0, n,
                                     K + p1 * n + p0, n, Y + p1, n, s)) != hipSuccess)
       return e;
   }
@@ -623,16 +631,27 @@ hipError_t launch_cholesky_solve_many(const double* K, double* Y, int64_t n, int
     const int64_t p1 = std::min(n, p0 + kSolvePanel);
     for (int64_t j0 = p0 + ((p1 - 1 - p0) / kTriNb) * kTriNb; j0 >= p0; j0 -= kTriNb) {
       const int bs = (int)std::min<int64_t>(kTriNb, p1 - j0);
-      hipLaunchKernelGGL(trsm_upper_diag_many, dim3(g), dim3(256), 0, s, K, Y, n, nrhs, j0, bs);
-      if (j0 > p0 && (e = launch_dgemm(false, nrhs, j0 - p0, bs, -1.0, Y + j0, n,
+      hipLaunchKernelGGL(trsm_upper_diag_many, dim3(grid_rhs(rows(j0 + bs))), dim3(256), 0, s, K,
+                         Y, n, rows(j0 + bs), j0, bs);
+      if (j0 > p0 && (e = launch_dgemm(false, rows(j0), j0 - p0, bs, -1.0, Y + j0, n,
                                        K + j0 * n + p0, n, Y + p0, n, s)) != hipSuccess)
         return e;
     }
-    if (p0 > 0 && (e = launch_dgemm(false, nrhs, p0, p1 - p0, -1.0, Y + p0, n, K + p0 * n, n, Y,
-                                    n, s)) != hipSuccess)
+    if (p0 > 0 && (e = launch_dgemm(false, rows(p0), p0, p1 - p0, -1.0, Y + p0, n, K + p0 * n, n,
+                                    Y, n, s)) != hipSuccess)
       return e;
   }
   return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_cholesky_solve_many(const double* K, double* Y, int64_t n, int64_t nrhs,
+                                      hipStream_t s) {
+  return solve_many_sweeps(K, Y, n, nrhs, false, s);
+}
+
+hipError_t launch_cholesky_inverse_upper(const double* K, double* Y, int64_t n, hipStream_t s) {
+  return solve_many_sweeps(K, Y, n, n, true, s);
 }
 
 hipError_t launch_qoi_gemv(const double* Q, const double* D, double* q, int64_t rows,

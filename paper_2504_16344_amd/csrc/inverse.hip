@@ -73,8 +73,9 @@ __global__ void add_diagonal(double* __restrict__ K, const double* __restrict__ 
   if (i < n) K[i * n + i] += v[i];
 }
 
-// K <- (K + K^T) / 2, or with `mirror` the lower triangle copied onto the
-// upper one, on 32 x 32 tile pairs (I, J), I <= J.
+// K <- (K + K^T) / 2 (mirror 0), the lower triangle copied onto the upper
+// one (mirror 1) or the upper onto the lower (mirror 2), on 32 x 32 tile
+// pairs (I, J), I <= J.
 __global__ void __launch_bounds__(256)
 symmetrize(double* __restrict__ K, int64_t n, int64_t T, int mirror) {
   __shared__ double a[32][33], b[32][33];
@@ -96,7 +97,9 @@ symmetrize(double* __restrict__ K, int64_t n, int64_t T, int mirror) {
   for (int r = ty; r < 32; r += 8) {
     // element (I*32+r, J*32+tx) pairs with (J*32+tx, I*32+r) = b[tx][r]
     const int64_t gi = I * 32 + r, gj = J * 32 + tx;
-    const double v = !mirror ? 0.5 * (a[r][tx] + b[tx][r]) : (gj > gi ? b[tx][r] : a[r][tx]);
+    const double v = mirror == 0   ? 0.5 * (a[r][tx] + b[tx][r])
+                     : mirror == 1 ? (gj > gi ? b[tx][r] : a[r][tx])
+                                   : (gj >= gi ? a[r][tx] : b[tx][r]);
     if (gi < n && gj < n) K[gi * n + gj] = v;
     const int64_t hi = J * 32 + tx, hj = I * 32 + r;
     if (hi < n && hj < n) K[hi * n + hj] = v;
@@ -657,6 +660,14 @@ hipError_t launch_mirror_lower(double* K, int64_t n, hipStream_t s) {
   const int64_t pairs = T * (T + 1) / 2;
   if (pairs > 0x7fffffff) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL(symmetrize, dim3((unsigned)pairs), dim3(256), 0, s, K, n, T, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_mirror_upper(double* K, int64_t n, hipStream_t s) {
+  const int64_t T = (n + 31) / 32;
+  const int64_t pairs = T * (T + 1) / 2;
+  if (pairs > 0x7fffffff) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL(symmetrize, dim3((unsigned)pairs), dim3(256), 0, s, K, n, T, 2);
   return hipGetLastError();
 }
 

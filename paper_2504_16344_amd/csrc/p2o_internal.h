@@ -215,6 +215,7 @@ hipError_t launch_unit_spectra(const double* A, int64_t Nd, int64_t Nm, int64_t 
 hipError_t launch_add_diagonal(double* K, const double* v, int64_t n, hipStream_t s);
 hipError_t launch_symmetrize(double* K, int64_t n, hipStream_t s);    // (K + K^T) / 2
 hipError_t launch_mirror_lower(double* K, int64_t n, hipStream_t s);  // upper <- lower
+hipError_t launch_mirror_upper(double* K, int64_t n, hipStream_t s);  // lower <- upper
 // Cholesky factor of K's lower triangle in place; scratch of
 // cholesky_scratch_bytes(n) device bytes.
 hipError_t launch_cholesky(double* K, int64_t n, int64_t* info_dev, double* scratch,
@@ -270,6 +271,11 @@ hipError_t launch_dgemm_nt_lower_mask(int64_t M, int64_t N, int64_t K, double al
 // (no scratch; any nrhs, efficient from a few tens of right-hand sides on).
 hipError_t launch_cholesky_solve_many(const double* K, double* Y, int64_t n, int64_t nrhs,
                                       hipStream_t s);
+// Y = I (n x n) on entry; on return row r holds K^{-1} e_r in its entries
+// c >= r (the upper triangle); the entries below the diagonal are not
+// meaningful.  The many-right-hand-side sweeps restricted to the rows whose
+// result is needed.
+hipError_t launch_cholesky_inverse_upper(const double* K, double* Y, int64_t n, hipStream_t s);
 // Spatial prior covariance C on an nx x ny parameter grid (prior.hip):
 // x[count][nx ny] <- C x in place; t1, t2 scratch of the same size; w the
 // r + 1 window weights (device).
