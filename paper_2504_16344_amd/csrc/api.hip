@@ -1074,10 +1074,22 @@ p2o_status p2o_posterior_invert(p2o_handle h, const double* Kfac, double* Kinv, 
   (void)hipGetLastError();
   hipStream_t s = (hipStream_t)stream;
   const int64_t n = h->Nt * h->Nd;
+  TRY_HIP(launch_identity(Kinv, n, s));
+  if (cholesky_inverse_by_square_fits(Kinv, n)) {
+    // L^{-T} by the forward sweep, then K^{-1} = L^{-T} L^{-1} in place
+    // (lower triangle and diagonal), mirrored: exactly symmetric
+    DevBufs bufs;
+    void* diag;
+    TRY_HIP(bufs.alloc(&diag, (size_t)n * 8));
+    TRY_HIP(launch_cholesky_inverse_by_square(Kfac, Kinv, static_cast<double*>(diag), n, s));
+    TRY_HIP(launch_set_diagonal(Kinv, static_cast<const double*>(diag), n, s));
+    TRY_HIP(launch_mirror_lower(Kinv, n, s));
+    TRY_HIP(hipStreamSynchronize(s));  // before diag is freed
+    return P2O_OK;
+  }
   // row j of Kinv = K^{-1} e_j: the solves of K X = I, all n at once,
   // restricted to the upper triangle, which is then mirrored (exactly
   // symmetric)
-  TRY_HIP(launch_identity(Kinv, n, s));
   TRY_HIP(launch_cholesky_inverse_upper(Kfac, Kinv, n, s));
   TRY_HIP(launch_mirror_upper(Kinv, n, s));
   TRY_HIP(hipStreamSynchronize(s));

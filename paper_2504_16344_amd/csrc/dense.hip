@@ -29,7 +29,7 @@ constexpr int64_t kSolvePanel = 256;  // columns per rank-k update of the solves
 // work-group reads all of its rows of A before it writes its rows of C, and
 // no other work-group touches those rows (the Cholesky's in-place panel
 // solve L21 = A21 W^T).
-enum { kFull = 0, kTriGrid = 1, kTriMask = 2, kFullCols = 3 };
+enum { kFull = 0, kTriGrid = 1, kTriMask = 2, kFullCols = 3, kTriUpperSq = 4 };
 template <bool TRANSB, int TRI, bool ACC, int TM>
 __global__ void __launch_bounds__(256)
 dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
@@ -181,19 +181,26 @@ __device__ __forceinline__ void nt_barrier() {
   __asm__ volatile("" ::: "memory");
 }
 
-// TRI: kFull (tile t = I tc + J) or kTriGrid (tiles I >= J, entries above
-// the diagonal untouched).  Both operands 16-byte aligned with even leading
-// dimensions (the launcher checks).
+// TRI: kFull (tile t = I tc + J), kTriGrid (tiles I >= J, entries above
+// the diagonal untouched) or kTriUpperSq: C = alpha Y Y^T in place for an
+// upper-triangular Y (A = B = C = Y, n x n, entries below the diagonal
+// zero): tiles I >= J, contraction from column i0 on (row i of Y is zero
+// before column i); every operand entry below the diagonal is taken as
+// zero (this launch may already have overwritten it), only the strict
+// lower triangle of C is written and the diagonal goes to diag[], so no
+// entry that any work-group reads as non-zero is ever written.  Both
+// operands 16-byte aligned with even leading dimensions (the launcher
+// checks).  No __restrict__: the in-place form aliases A, B and C.
 template <int TRI, bool ACC>
 __global__ void __launch_bounds__(256, 2)
-dgemm_nt128_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* __restrict__ A,
-                   int64_t lda, const double* __restrict__ B, int64_t ldb, double* __restrict__ C,
-                   int64_t ldc, int64_t tiles) {
+dgemm_nt128_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
+                   const double* B, int64_t ldb, double* C, int64_t ldc, int64_t tiles,
+                   double* diag) {
   __shared__ __align__(16) double lds[2][2][kNtStage];  // [stage][A | B]
   const int64_t t = xcd_local_tile(blockIdx.x, gridDim.x);
   if (t >= tiles) return;  // grid padding
   int64_t ti_, tj_;
-  if constexpr (TRI == kTriGrid) {
+  if constexpr (TRI == kTriGrid || TRI == kTriUpperSq) {
     int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) / 2.0);
     while (I * (I + 1) / 2 > t) --I;
     while ((I + 1) * (I + 2) / 2 <= t) ++I;
@@ -218,12 +225,25 @@ dgemm_nt128_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* 
     pb[u] = B + min(j0 + lr + 32 * u, N - 1) * ldb + 2 * lg;
   }
   d2v ra[4], rb[4];
+  // kTriUpperSq: the contraction starts at i0 (>= j0)
+  const int64_t kbeg = TRI == kTriUpperSq ? i0 : 0;
   auto load = [&](int64_t k0) {
     if (k0 + kNtK <= K) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         ra[u] = *reinterpret_cast<const d2v*>(pa[u] + k0);
         rb[u] = *reinterpret_cast<const d2v*>(pb[u] + k0);
+      }
+      if constexpr (TRI == kTriUpperSq) {  // entries below the diagonal are zero
+        // entry k0 + 2 lg + h of row i0 + lr + 32 u: k - row = (k0 - i0) + h - thr
+        const int da = (int)(k0 - i0), db = (int)(k0 - j0), thr = lr - 2 * lg;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            ra[u][h] = da + h >= thr + 32 * u ? ra[u][h] : 0.0;
+            rb[u][h] = db + h >= thr + 32 * u ? rb[u][h] : 0.0;
+          }
       }
     } else {  // the contraction's ragged end
 #pragma unroll
@@ -233,8 +253,10 @@ dgemm_nt128_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* 
           const int64_t e = k0 + 2 * lg + h;  // contraction index of this entry
           const int64_t ec = min(e, K - 1) - 2 * lg;
           const double x = pa[u][ec], y = pb[u][ec];
-          ra[u][h] = e < K ? x : 0.0;
-          rb[u][h] = e < K ? y : 0.0;
+          const bool la = TRI != kTriUpperSq || (int)(e - i0) >= lr + 32 * u;
+          const bool lb = TRI != kTriUpperSq || (int)(e - j0) >= lr + 32 * u;
+          ra[u][h] = e < K && la ? x : 0.0;
+          rb[u][h] = e < K && lb ? y : 0.0;
         }
     }
   };
@@ -250,17 +272,17 @@ dgemm_nt128_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* 
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = (d4v){0, 0, 0, 0};
-  const int64_t nc = (K + kNtK - 1) / kNtK;
-  load(0);
+  const int64_t nc = (K - kbeg + kNtK - 1) / kNtK;
+  load(kbeg);
   store(0);
-  if (nc > 1) load(kNtK);
+  if (nc > 1) load(kbeg + kNtK);
   nt_wait_lds();
   nt_barrier();
   for (int64_t c = 0; c < nc; ++c) {
     const int cur = (int)(c & 1);
     if (c + 1 < nc) {  // chunk c + 1 into the other stage (read by chunk c - 1's products, done)
       store(cur ^ 1);
-      if (c + 2 < nc) load((c + 2) * kNtK);
+      if (c + 2 < nc) load(kbeg + (c + 2) * kNtK);
     }
     const double* sa = lds[cur][0];
     const double* sb = lds[cur][1];
@@ -303,8 +325,12 @@ dgemm_nt128_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* 
       for (int r = 0; r < 4; ++r) {
         const int64_t gi = i0 + wr + 16 * fi + kq + 4 * r;  // accumulator rows interleave
         const int64_t gj = j0 + wc + 16 * fj + col;
-        if (gi < M && gj < N && (TRI == kFull || gj <= gi))
+        if constexpr (TRI == kTriUpperSq) {
+          if (gi < M && gj < N && gj < gi) C[gi * ldc + gj] = alpha * acc[fi][fj][r];
+          if (gi < M && gj == gi) diag[gi] = alpha * acc[fi][fj][r];
+        } else if (gi < M && gj < N && (TRI == kFull || gj <= gi)) {
           C[gi * ldc + gj] = ACC ? cv[fj][r] + alpha * acc[fi][fj][r] : alpha * acc[fi][fj][r];
+        }
       }
   }
 }
@@ -530,13 +556,13 @@ bool nt128_fits(int64_t M, int64_t N, const double* A, int64_t lda, const double
 template <int TRI, bool ACC>
 hipError_t launch_gemm_nt128(int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                              int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
-                             hipStream_t s) {
+                             hipStream_t s, double* diag = nullptr) {
   const int64_t tr = (M + kNtTile - 1) / kNtTile, tc = (N + kNtTile - 1) / kNtTile;
-  const int64_t tiles = TRI == kTriGrid ? tr * (tr + 1) / 2 : tr * tc;
+  const int64_t tiles = TRI == kFull ? tr * tc : tr * (tr + 1) / 2;
   const int64_t grid = (tiles + kXcds - 1) / kXcds * kXcds;
   if (grid > 0x7fffffff) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((dgemm_nt128_kernel<TRI, ACC>), dim3((unsigned)grid), dim3(256), 0, s, M, N,
-                     K, alpha, A, lda, B, ldb, C, ldc, tiles);
+                     K, alpha, A, lda, B, ldb, C, ldc, tiles, diag);
   return hipGetLastError();
 }
 
@@ -605,7 +631,7 @@ namespace {
 // step that updates columns below c0 needs rows r < c0 only.  About half the
 // work of the full solve.
 hipError_t solve_many_sweeps(const double* K, double* Y, int64_t n, int64_t nrhs, bool inv,
-                             hipStream_t s) {
+                             bool backward, hipStream_t s) {
   hipError_t e = hipSuccess;
   auto rows = [&](int64_t c) { return inv ? std::min(nrhs, c) : nrhs; };
   // forward, L Z = Y: panels of kSolvePanel columns; inside a panel block by
@@ -626,6 +652,7 @@ hipError_t solve_many_sweeps(const double* K, double* Y, int64_t n, int64_t nrhs
                                     K + p1 * n + p0, n, Y + p1, n, s)) != hipSuccess)
       return e;
   }
+  if (!backward) return hipGetLastError();
   // backward, L^T X = Z: the same from the last panel down
   for (int64_t p0 = ((n - 1) / kSolvePanel) * kSolvePanel; p0 >= 0; p0 -= kSolvePanel) {
     const int64_t p1 = std::min(n, p0 + kSolvePanel);
@@ -647,11 +674,27 @@ hipError_t solve_many_sweeps(const double* K, double* Y, int64_t n, int64_t nrhs
 
 hipError_t launch_cholesky_solve_many(const double* K, double* Y, int64_t n, int64_t nrhs,
                                       hipStream_t s) {
-  return solve_many_sweeps(K, Y, n, nrhs, false, s);
+  return solve_many_sweeps(K, Y, n, nrhs, false, true, s);
 }
 
 hipError_t launch_cholesky_inverse_upper(const double* K, double* Y, int64_t n, hipStream_t s) {
-  return solve_many_sweeps(K, Y, n, n, true, s);
+  return solve_many_sweeps(K, Y, n, n, true, true, s);
+}
+
+bool cholesky_inverse_by_square_fits(const double* Y, int64_t n) {
+  return nt128_fits(n, n, Y, n, Y, n);
+}
+
+hipError_t launch_cholesky_inverse_by_square(const double* K, double* Y, double* diag, int64_t n,
+                                             hipStream_t s) {
+  if (!cholesky_inverse_by_square_fits(Y, n)) return hipErrorInvalidValue;
+  // forward sweep only: row r of Y becomes L^{-1} e_r, so Y = L^{-T}
+  // (upper triangular)
+  hipError_t e = solve_many_sweeps(K, Y, n, n, true, false, s);
+  if (e != hipSuccess) return e;
+  // K^{-1} = L^{-T} L^{-1} = Y Y^T: strict lower triangle in place, the
+  // diagonal into diag
+  return launch_gemm_nt128<kTriUpperSq, false>(n, n, n, 1.0, Y, n, Y, n, Y, n, s, diag);
 }
 
 hipError_t launch_qoi_gemv(const double* Q, const double* D, double* q, int64_t rows,

@@ -611,6 +611,11 @@ __global__ void copy_diagonal(const double* __restrict__ K, double* __restrict__
   if (i < n) d[i] = K[i * n + i];
 }
 
+__global__ void set_diagonal(double* __restrict__ K, const double* __restrict__ d, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) K[i * n + i] = d[i];
+}
+
 // X = I (n x n, row-major): one thread per entry, grid-stride.
 __global__ void identity(double* __restrict__ X, int64_t n) {
   const int64_t total = n * n;
@@ -760,6 +765,11 @@ hipError_t launch_cholesky_solve(const double* K, double* Y, double* scratch, in
 size_t cholesky_solve_scratch(int64_t n, int64_t nrhs) {
   const int64_t nb = (n + kNb - 1) / kNb;
   return (size_t)(solve_inverse_offset(n, nrhs) + 2 * nb * kNb * kNb) * sizeof(double);
+}
+
+hipError_t launch_set_diagonal(double* K, const double* d, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(set_diagonal, dim3(grid1(n)), dim3(256), 0, s, K, d, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_copy_diagonal(const double* K, double* d, int64_t n, hipStream_t s) {

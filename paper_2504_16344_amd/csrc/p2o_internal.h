@@ -216,6 +216,7 @@ hipError_t launch_add_diagonal(double* K, const double* v, int64_t n, hipStream_
 hipError_t launch_symmetrize(double* K, int64_t n, hipStream_t s);    // (K + K^T) / 2
 hipError_t launch_mirror_lower(double* K, int64_t n, hipStream_t s);  // upper <- lower
 hipError_t launch_mirror_upper(double* K, int64_t n, hipStream_t s);  // lower <- upper
+hipError_t launch_set_diagonal(double* K, const double* d, int64_t n, hipStream_t s);
 // Cholesky factor of K's lower triangle in place; scratch of
 // cholesky_scratch_bytes(n) device bytes.
 hipError_t launch_cholesky(double* K, int64_t n, int64_t* info_dev, double* scratch,
@@ -276,6 +277,14 @@ hipError_t launch_cholesky_solve_many(const double* K, double* Y, int64_t n, int
 // meaningful.  The many-right-hand-side sweeps restricted to the rows whose
 // result is needed.
 hipError_t launch_cholesky_inverse_upper(const double* K, double* Y, int64_t n, hipStream_t s);
+// Y = I (n x n) on entry; on return the strict lower triangle of Y holds
+// that of K^{-1} and diag[0 .. n) its diagonal (the upper triangle holds
+// L^{-T}): the forward sweep only, then K^{-1} = L^{-T} L^{-1} as one
+// symmetric product on the matrix cores.  Needs Y 16-byte aligned and
+// n even, n >= 512 (cholesky_inverse_by_square_fits).
+bool cholesky_inverse_by_square_fits(const double* Y, int64_t n);
+hipError_t launch_cholesky_inverse_by_square(const double* K, double* Y, double* diag, int64_t n,
+                                             hipStream_t s);
 // Spatial prior covariance C on an nx x ny parameter grid (prior.hip):
 // x[count][nx ny] <- C x in place; t1, t2 scratch of the same size; w the
 // r + 1 window weights (device).

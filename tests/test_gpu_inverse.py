@@ -163,11 +163,13 @@ def test_posterior_mean_errors():
 
 
 @pytest.mark.parametrize("shape,nrhs", [((3, 40, 7), 1), ((5, 300, 29), 3), ((5, 300, 29), 20),
-                                        ((4, 60, 32), 2), ((20, 300, 55), 1)])
+                                        ((4, 60, 32), 2), ((20, 300, 55), 1), ((8, 100, 70), 2)])
 def test_posterior_mean_from_inverse(shape, nrhs):
     """Phase 4 online from K^{-1}: posterior_invert() forms K^{-1} from the
     factor (checked by K K^{-1} = I against the oracle's K, and exact
-    symmetry), then m = Gp F* (K^{-1} d) against the oracle's posterior mean;
+    symmetry; n = 1100 and 560 take the forward sweep and the in-place
+    product L^-T L^-1, the smaller ones both sweeps), then
+    m = Gp F* (K^{-1} d) against the oracle's posterior mean;
     a second call with one right-hand side reuses the plan's temporaries and
     gives the same first result (bit for bit when both calls take the
     vector-unit F* kernels)."""
