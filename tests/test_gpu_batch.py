@@ -16,8 +16,10 @@ pytestmark = pytest.mark.gpu
 
 TOL = TOL_VS_FP64
 # (Nd, Nm, Nt, nrhs): uneven shapes, odd and even Nm, 1..70 right-hand sides
+# (Nd = 100 with 40: two 64-sensor tiles, one of them ragged, on the FP64
+# matrix cores)
 INSTANCES = [(1, 1, 5, 1), (37, 300, 13, 5), (130, 1028, 33, 70), (17, 1001, 21, 20),
-             (64, 777, 40, 3), (5, 4100, 8, 17), (9, 512, 1, 9)]
+             (64, 777, 40, 3), (5, 4100, 8, 17), (9, 512, 1, 9), (100, 300, 11, 40)]
 
 
 def _setup(prec, seed=21):
