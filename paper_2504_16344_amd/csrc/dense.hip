@@ -201,11 +201,33 @@ dgemm_nt128_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* 
   if (t >= tiles) return;  // grid padding
   int64_t ti_, tj_;
   if constexpr (TRI == kTriGrid || TRI == kTriUpperSq) {
-    int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) / 2.0);
-    while (I * (I + 1) / 2 > t) --I;
-    while ((I + 1) * (I + 2) / 2 <= t) ++I;
-    ti_ = I;
-    tj_ = t - I * (I + 1) / 2;
+    // 8 x 8 super-blocks of tiles, in row-major order over the lower
+    // triangle of super-blocks, tiles row-major inside a super-block: the
+    // tiles an XCD runs at once share 8 row and 8 column bands of the
+    // operands in its L2 (row-major tiles share one row band and stream a
+    // new column band each)
+    constexpr int64_t S = 8;
+    const int64_t tr = (M + kNtTile - 1) / kNtTile;
+    int64_t rem = t, IB = 0, h = 0;
+    for (;; ++IB) {
+      h = min(S, tr - IB * S);
+      const int64_t cnt = IB * h * S + h * (h + 1) / 2;
+      if (rem < cnt) break;
+      rem -= cnt;
+    }
+    const int64_t JB = rem / (h * S);
+    if (JB < IB) {
+      const int64_t l = rem - JB * h * S;
+      ti_ = IB * S + l / S;
+      tj_ = JB * S + l % S;
+    } else {
+      const int64_t l = rem - IB * h * S;
+      int64_t r = (int64_t)((sqrt(8.0 * (double)l + 1.0) - 1.0) / 2.0);
+      while (r * (r + 1) / 2 > l) --r;
+      while ((r + 1) * (r + 2) / 2 <= l) ++r;
+      ti_ = IB * S + r;
+      tj_ = IB * S + (l - r * (r + 1) / 2);
+    }
   } else {
     const int64_t tc = (N + kNtTile - 1) / kNtTile;
     ti_ = t / tc;
