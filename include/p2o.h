@@ -335,9 +335,13 @@ p2o_status p2o_posterior_mean(p2o_handle h, const double* Kfac, const double* d,
  *   Kfac  device [(Nt*Nd)^2]: K after p2o_posterior_solve (the factor in its
  *         lower triangle; the upper triangle is not read).
  *   Kinv  device [(Nt*Nd)^2] float64 row-major, caller-allocated, must not
- *         overlap Kfac; receives K^{-1}, exactly symmetric (the solutions
- *         of K X = I for all n = Nt*Nd unit vectors at once with the blocked
- *         matrix-core solve, about 2 n^3 flops, lower triangle mirrored).
+ *         overlap Kfac; receives K^{-1}, exactly symmetric.  Where Kinv is
+ *         16-byte aligned, n = Nt*Nd even and n >= 512: L^{-T} by a forward
+ *         sweep over the identity, then K^{-1} = L^{-T} L^{-1} as one
+ *         symmetric matrix-core product in place (about 2 n^3 / 3 flops;
+ *         n doubles of temporary device memory).  Otherwise the solves of
+ *         K X = I restricted to the upper triangle (about n^3 flops).  The
+ *         triangle computed is mirrored onto the other.
  * An explicit inverse applied to d has an error of the order of
  * cond(K) u ||K^{-1}|| ||d||, against cond(K) u ||K^{-1} d|| for the
  * triangular sweeps: the same for a well-conditioned K, possibly larger
