@@ -197,7 +197,10 @@ dgemm_nt128_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* 
                    const double* B, int64_t ldb, double* C, int64_t ldc, int64_t tiles,
                    double* diag) {
   __shared__ __align__(16) double lds[2][2][kNtStage];  // [stage][A | B]
-  const int64_t t = xcd_local_tile(blockIdx.x, gridDim.x);
+  // kTriUpperSq: a tile's contraction shrinks with its row band, so the
+  // tiles are dealt to the XCDs round-robin in grid order (long ones first)
+  // rather than in contiguous ranges, which would leave one XCD the bulk
+  const int64_t t = TRI == kTriUpperSq ? (int64_t)blockIdx.x : xcd_local_tile(blockIdx.x, gridDim.x);
   if (t >= tiles) return;  // grid padding
   int64_t ti_, tj_;
   if constexpr (TRI == kTriGrid || TRI == kTriUpperSq) {
