@@ -164,6 +164,7 @@ dgemm_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int
 constexpr int kNtTile = 128;
 constexpr int kNtK = 16;
 constexpr int kNtStage = kNtTile * kNtK;  // doubles of one operand in one stage
+constexpr int kNtBRow = 130;              // row pitch (doubles) of a row-major B chunk
 
 __device__ __forceinline__ int nt_lds_pos(int r, int g) { return r * kNtK + 2 * (g ^ ((r >> 1) & 7)); }
 
@@ -191,12 +192,17 @@ __device__ __forceinline__ void nt_barrier() {
 // entry that any work-group reads as non-zero is ever written.  Both
 // operands 16-byte aligned with even leading dimensions (the launcher
 // checks).  No __restrict__: the in-place form aliases A, B and C.
-template <int TRI, bool ACC>
+// BROW: C (+)= alpha A B with B row-major along the contraction ([K][N],
+// kFull only): its chunk is kept in LDS as 16 rows of kNtBRow doubles (the
+// 130-double pitch puts the 4 lane groups of a read on distinct banks) and
+// each product takes its two contraction entries from two 8-byte reads.
+template <int TRI, bool ACC, bool BROW = false>
 __global__ void __launch_bounds__(256, 2)
 dgemm_nt128_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
                    const double* B, int64_t ldb, double* C, int64_t ldc, int64_t tiles,
                    double* diag) {
-  __shared__ __align__(16) double lds[2][2][kNtStage];  // [stage][A | B]
+  static_assert(!BROW || TRI == kFull, "row-major B on the full grid only");
+  __shared__ __align__(16) double lds[2][2][kNtStage + (BROW ? kNtK * (kNtBRow - kNtTile) : 0)];
   // kTriUpperSq: a tile's contraction shrinks with its row band, so the
   // tiles are dealt to the XCDs round-robin in grid order (long ones first)
   // rather than in contiguous ranges, which would leave one XCD the bulk
@@ -247,7 +253,9 @@ dgemm_nt128_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* 
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     pa[u] = A + min(i0 + lr + 32 * u, M - 1) * lda + 2 * lg;
-    pb[u] = B + min(j0 + lr + 32 * u, N - 1) * ldb + 2 * lg;
+    // BROW: row wave + 4 u of the chunk, columns j0 + 2 lane, + 1 (N even;
+    // columns past N re-read the last pair and are dropped)
+    pb[u] = BROW ? B + min(j0 + 2 * lane, N - 2) : B + min(j0 + lr + 32 * u, N - 1) * ldb + 2 * lg;
   }
   d2v ra[4], rb[4];
   // kTriUpperSq: the contraction starts at i0 (>= j0)
@@ -257,7 +265,8 @@ dgemm_nt128_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* 
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         ra[u] = *reinterpret_cast<const d2v*>(pa[u] + k0);
-        rb[u] = *reinterpret_cast<const d2v*>(pb[u] + k0);
+        rb[u] = BROW ? *reinterpret_cast<const d2v*>(pb[u] + (k0 + wave + 4 * u) * ldb)
+                     : *reinterpret_cast<const d2v*>(pb[u] + k0);
       }
       if constexpr (TRI == kTriUpperSq) {  // entries below the diagonal are zero
         // entry k0 + 2 lg + h of row i0 + lr + 32 u: k - row = (k0 - i0) + h - thr
@@ -277,19 +286,36 @@ dgemm_nt128_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* 
         for (int h = 0; h < 2; ++h) {
           const int64_t e = k0 + 2 * lg + h;  // contraction index of this entry
           const int64_t ec = min(e, K - 1) - 2 * lg;
-          const double x = pa[u][ec], y = pb[u][ec];
+          const double x = pa[u][ec];
           const bool la = TRI != kTriUpperSq || (int)(e - i0) >= lr + 32 * u;
-          const bool lb = TRI != kTriUpperSq || (int)(e - j0) >= lr + 32 * u;
           ra[u][h] = e < K && la ? x : 0.0;
-          rb[u][h] = e < K && lb ? y : 0.0;
+          if constexpr (!BROW) {
+            const double y = pb[u][ec];
+            const bool lb = TRI != kTriUpperSq || (int)(e - j0) >= lr + 32 * u;
+            rb[u][h] = e < K && lb ? y : 0.0;
+          }
         }
+      if constexpr (BROW) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t r = k0 + wave + 4 * u;  // contraction row of B
+          const d2v y = *reinterpret_cast<const d2v*>(pb[u] + min(r, K - 1) * ldb);
+          rb[u] = r < K ? y : (d2v){0.0, 0.0};
+        }
+      }
     }
   };
   auto store = [&](int st) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       *reinterpret_cast<d2v*>(&lds[st][0][nt_lds_pos(lr + 32 * u, lg)]) = ra[u];
-      *reinterpret_cast<d2v*>(&lds[st][1][nt_lds_pos(lr + 32 * u, lg)]) = rb[u];
+      if constexpr (BROW) {  // row wave + 4 u, two 8-byte stores (the pitch is not 16-aligned)
+        double* q = &lds[st][1][(wave + 4 * u) * kNtBRow + 2 * lane];
+        q[0] = rb[u][0];
+        q[1] = rb[u][1];
+      } else {
+        *reinterpret_cast<d2v*>(&lds[st][1][nt_lds_pos(lr + 32 * u, lg)]) = rb[u];
+      }
     }
   };
   d4v acc[4][4];
@@ -317,7 +343,12 @@ dgemm_nt128_kernel(int64_t M, int64_t N, int64_t K, double alpha, const double* 
 #pragma unroll
       for (int f = 0; f < 4; ++f) {
         a[f] = *reinterpret_cast<const d2v*>(&sa[nt_lds_pos(wr + 16 * f + col, 2 * kq + h)]);
-        b[f] = *reinterpret_cast<const d2v*>(&sb[nt_lds_pos(wc + 16 * f + col, 2 * kq + h)]);
+        if constexpr (BROW) {
+          const double* q = &sb[(4 * kq + 2 * h) * kNtBRow + wc + 16 * f + col];
+          b[f] = (d2v){q[0], q[kNtBRow]};
+        } else {
+          b[f] = *reinterpret_cast<const d2v*>(&sb[nt_lds_pos(wc + 16 * f + col, 2 * kq + h)]);
+        }
       }
 #pragma unroll
       for (int e = 0; e < 2; ++e)
@@ -578,7 +609,7 @@ bool nt128_fits(int64_t M, int64_t N, const double* A, int64_t lda, const double
   return al % 16 == 0 && lda % 2 == 0 && ldb % 2 == 0 && std::min(M, N) >= 512;
 }
 
-template <int TRI, bool ACC>
+template <int TRI, bool ACC, bool BROW = false>
 hipError_t launch_gemm_nt128(int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                              int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
                              hipStream_t s, double* diag = nullptr) {
@@ -586,7 +617,7 @@ hipError_t launch_gemm_nt128(int64_t M, int64_t N, int64_t K, double alpha, cons
   const int64_t tiles = TRI == kFull ? tr * tc : tr * (tr + 1) / 2;
   const int64_t grid = (tiles + kXcds - 1) / kXcds * kXcds;
   if (grid > 0x7fffffff) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((dgemm_nt128_kernel<TRI, ACC>), dim3((unsigned)grid), dim3(256), 0, s, M, N,
+  hipLaunchKernelGGL((dgemm_nt128_kernel<TRI, ACC, BROW>), dim3((unsigned)grid), dim3(256), 0, s, M, N,
                      K, alpha, A, lda, B, ldb, C, ldc, tiles, diag);
   return hipGetLastError();
 }
@@ -597,6 +628,8 @@ hipError_t launch_dgemm(bool transb, int64_t M, int64_t N, int64_t K, double alp
   if (transb && M > 0 && N > 0 && K > 0 && nt128_fits(M, N, A, lda, B, ldb))
     return launch_gemm_nt128<kFull, true>(M, N, K, alpha, A, lda, B, ldb, C, ldc, s);
   if (transb) return launch_gemm<true, kFull, true>(M, N, K, alpha, A, lda, B, ldb, C, ldc, s);
+  if (M > 0 && N > 0 && K > 0 && N % 2 == 0 && nt128_fits(M, N, A, lda, B, ldb))
+    return launch_gemm_nt128<kFull, true, true>(M, N, K, alpha, A, lda, B, ldb, C, ldc, s);
   return launch_gemm<false, kFull, true>(M, N, K, alpha, A, lda, B, ldb, C, ldc, s);
 }
 

@@ -53,6 +53,32 @@ def test_hessian_and_posterior_match_oracle(shape, nrhs, refine):
     assert np.abs(L @ L.T - K_ref).max() / np.abs(K_ref).max() <= 1e-12
 
 
+def test_posterior_many_right_hand_sides():
+    """520 right-hand sides at n = 1100: the blocked many-right-hand-side
+    solve, whose backward rank-256 updates (C += A B with B the row-major
+    factor) run on the 128 x 128 matrix-core tiles, against the oracle's
+    posterior mean for a sample of right-hand sides and against the same
+    solve one right-hand side at a time (the substitution kernels)."""
+    Nd, Nm, Nt, nrhs = 20, 300, 55, 520
+    print(f"\n[inverse] many right-hand sides nrhs={nrhs}", flush=True)
+    blocks, _, _ = workload(12, Nd, Nm, Nt, tau=Nt / 3)
+    n = Nt * Nd
+    nv = _noise(12, n)
+    d = S.vector(12, S.ARRAY_D, nrhs * n).reshape(nrhs, Nt, Nd)
+    K_ref = oracle.hessian_gram(blocks, 0.25, nv)
+    with P.Plan(dev(blocks), "fp64") as plan:
+        K = plan.hessian(0.25, dev(nv))
+        m_all = host(plan.posterior(K, dev(d), 0.25, refine_steps=0))  # factors K
+        sample = [0, 1, 255, 256, 511, 519]
+        m_one = np.stack([host(plan.posterior_mean(K, dev(d[r:r + 1]), 0.25))[0] for r in sample])
+    m_ref = np.stack([oracle.posterior_mean(blocks, 0.25, nv, d[r], K=K_ref) for r in sample])
+    e_ref = rel_err(m_all[sample], m_ref)
+    e_one = rel_err(m_all[sample], m_one)
+    print(f"  m err vs oracle {e_ref:.2e}, vs one at a time {e_one:.2e}", flush=True)
+    assert e_ref <= 1e-10
+    assert e_one <= 1e-12
+
+
 def test_inversion_workload_100x5000x200():
     """Full-size K (20000 x 20000): sampled columns against the paper's
     unit-vector definition in the oracle, then the posterior mean checked by
