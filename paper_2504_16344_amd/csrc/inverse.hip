@@ -263,16 +263,23 @@ potrf_diag_inv(double* __restrict__ K, int64_t n, int64_t j0, int bs, double* __
     __syncthreads();
     // trailing sub-blocks (i, j), kb < j <= i: A_ij -= L_ik L_jk^T (the upper
     // triangle of a diagonal sub-block takes garbage that the factorisation
-    // never reads and overwrites with zeros)
-    int t = 0;  // sub-blocks dealt round-robin to the wavefronts
+    // never reads and overwrites with zeros).  The next diagonal sub-block
+    // goes to wavefront 0, which factors it straight after, with no
+    // work-group barrier in between: the others, dealt round-robin to
+    // wavefronts 1..3, touch neither it nor its inverse, and the barrier
+    // after that factorisation orders them before the next panel products.
+    int t = 0;
     for (int i = kb + 1; i < kNsb; ++i)
-      for (int jj = kb + 1; jj <= i; ++jj, ++t) {
-        if ((t & 3) != wave) continue;
+      for (int jj = kb + 1; jj <= i; ++jj) {
+        const int owner = (i == kb + 1 && jj == kb + 1) ? 0 : 1 + (t++ % 3);
+        if (owner != wave) continue;
         sub_d4 acc = sub_load(a, i * kSb, jj * kSb, lane);
         sub_mul_abt(acc, a, i * kSb, o, a, jj * kSb, o, -1.0, lane);
         sub_store(a, i * kSb, jj * kSb, acc, lane);
       }
-    __syncthreads();
+    // wavefront 0's lanes 0..15 read the sub-block its 64 lanes just stored
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
   // off-diagonal sub-blocks of the inverse, block row by block row:
   // T_ij = sum_{j <= k < i} L_ik W_kj, parked where W_ij goes, then
