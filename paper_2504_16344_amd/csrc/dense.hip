@@ -511,8 +511,12 @@ trsm_upper_diag_many(const double* __restrict__ K, double* __restrict__ Y, int64
 // and U steps per loop turn, all loads issued before any product
 // (unconditional, clamped addresses; entries past the range are zeroed at
 // the consumer).  The W partial sums are added in LDS in a fixed order.  Q
-// is streamed once per pass with non-temporal loads.
-template <int RB, int U, int W, int RQ>
+// is streamed once per pass with non-temporal loads.  V16 (cols even, Q and
+// D 16-byte aligned): a lane's 2 entries are one 16-byte load (measured
+// 152 -> 110 us for a 4200 x 20000 Q; the 8-byte pairs left it at 0.55 of
+// the HBM peak); the per-lane order of the additions is the same either
+// way, so the results are identical.
+template <int RB, int U, int W, int RQ, bool V16>
 __global__ void __launch_bounds__(64 * W)
 qoi_gemv(const double* __restrict__ Q, const double* __restrict__ D, double* __restrict__ q,
          int64_t rows, int64_t cols, int64_t r0, int nb) {
@@ -531,13 +535,32 @@ qoi_gemv(const double* __restrict__ Q, const double* __restrict__ D, double* __r
     for (int b = 0; b < RB; ++b) acc[w][b] = 0.0;
   for (int64_t j0 = c0 + 2 * lane; j0 < c1; j0 += 128 * U) {
     double qv[RQ][2 * U], dv[RB][2 * U];
+    if constexpr (V16) {  // j0 is even, so the pair is 16-byte aligned
 #pragma unroll
-    for (int u = 0; u < 2 * U; ++u) {
-      const int64_t j = min(j0 + 128 * (u >> 1) + (u & 1), cols - 1);
+      for (int u = 0; u < 2 * U; u += 2) {
+        const int64_t j = min(j0 + 128 * (u >> 1), cols - 2);
 #pragma unroll
-      for (int w = 0; w < RQ; ++w) qv[w][u] = __builtin_nontemporal_load(Qr[w] + j);
+        for (int w = 0; w < RQ; ++w) {
+          const d2v x = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(Qr[w] + j));
+          qv[w][u] = x.x;
+          qv[w][u + 1] = x.y;
+        }
 #pragma unroll
-      for (int b = 0; b < RB; ++b) dv[b][u] = D[(r0 + min(b, nb - 1)) * cols + j];
+        for (int b = 0; b < RB; ++b) {
+          const d2v y = *reinterpret_cast<const d2v*>(D + (r0 + min(b, nb - 1)) * cols + j);
+          dv[b][u] = y.x;
+          dv[b][u + 1] = y.y;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 2 * U; ++u) {
+        const int64_t j = min(j0 + 128 * (u >> 1) + (u & 1), cols - 1);
+#pragma unroll
+        for (int w = 0; w < RQ; ++w) qv[w][u] = __builtin_nontemporal_load(Qr[w] + j);
+#pragma unroll
+        for (int b = 0; b < RB; ++b) dv[b][u] = D[(r0 + min(b, nb - 1)) * cols + j];
+      }
     }
 #pragma unroll
     for (int u = 0; u < 2 * U; ++u) {
@@ -755,27 +778,37 @@ hipError_t launch_cholesky_inverse_by_square(const double* K, double* Y, double*
   return launch_gemm_nt128<kTriUpperSq, false>(n, n, n, 1.0, Y, n, Y, n, Y, n, s, diag);
 }
 
-hipError_t launch_qoi_gemv(const double* Q, const double* D, double* q, int64_t rows,
+namespace {
+template <bool V16>
+hipError_t qoi_gemv_passes(const double* Q, const double* D, double* q, int64_t rows,
                            int64_t cols, int64_t nrhs, hipStream_t s) {
   // wavefronts per work-group, 128-entry steps per turn, rows of Q per work-group
-  constexpr int W = 8, U = 1, RQ = 4;
+  constexpr int W = 8, U = 4, RQ = 2;
   const int64_t g = (rows + RQ - 1) / RQ;
   if (g > 0x7fffffff) return hipErrorInvalidConfiguration;
   for (int64_t r0 = 0; r0 < nrhs; r0 += 4) {
     const int nb = (int)std::min<int64_t>(4, nrhs - r0);
     if (nb == 1)
-      hipLaunchKernelGGL((qoi_gemv<1, U, W, RQ>), dim3((unsigned)g), dim3(64 * W), 0, s, Q, D, q,
-                         rows, cols, r0, nb);
+      hipLaunchKernelGGL((qoi_gemv<1, U, W, RQ, V16>), dim3((unsigned)g), dim3(64 * W), 0, s, Q, D,
+                         q, rows, cols, r0, nb);
     else if (nb == 2)
-      hipLaunchKernelGGL((qoi_gemv<2, U, W, RQ>), dim3((unsigned)g), dim3(64 * W), 0, s, Q, D, q,
-                         rows, cols, r0, nb);
+      hipLaunchKernelGGL((qoi_gemv<2, U, W, RQ, V16>), dim3((unsigned)g), dim3(64 * W), 0, s, Q, D,
+                         q, rows, cols, r0, nb);
     else
-      hipLaunchKernelGGL((qoi_gemv<4, U, W, RQ>), dim3((unsigned)g), dim3(64 * W), 0, s, Q, D, q,
-                         rows, cols, r0, nb);
+      hipLaunchKernelGGL((qoi_gemv<4, U, W, RQ, V16>), dim3((unsigned)g), dim3(64 * W), 0, s, Q, D,
+                         q, rows, cols, r0, nb);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+}  // namespace
+
+hipError_t launch_qoi_gemv(const double* Q, const double* D, double* q, int64_t rows,
+                           int64_t cols, int64_t nrhs, hipStream_t s) {
+  const uintptr_t al = reinterpret_cast<uintptr_t>(Q) | reinterpret_cast<uintptr_t>(D);
+  if (cols % 2 == 0 && al % 16 == 0) return qoi_gemv_passes<true>(Q, D, q, rows, cols, nrhs, s);
+  return qoi_gemv_passes<false>(Q, D, q, rows, cols, nrhs, s);
 }
 
 }  // namespace p2o
